@@ -1,0 +1,274 @@
+"""Python binding of libirk, the gfx950 solver of the transformed Radau IIA
+Newton system  (A^{-1} (x) M - dt diag(J_k)) W = R  (Pazner & Persson,
+Sec. 4.3, Eq. big-irk) by restarted GMRES with block ILU(0).
+
+This module only marshals arguments: every step of the solve runs in the HIP
+kernels of ``libirk.so`` (built by ``build.py``).  PyTorch provides device
+memory and the stream.  If the library is missing this import fails; there
+is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libirk.so")
+
+OK, ERR_ARG, ERR_NOMEM, ERR_SINGULAR, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE, ERR_DEVICE, ERR_STATE = range(9)
+PC = {"coupled": 0, "uncoupled_shifted": 1, "uncoupled": 2, "none": 3}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16s": 3}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python paper_1701_07181_amd/build.py` "
+                      "(or __graft_entry__.build()) first")
+_L = C.CDLL(LIB_PATH)
+
+
+class IrkError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_L.irk_status_str(status).decode()} (status {status})")
+
+
+class _Problem(C.Structure):
+    _fields_ = [("s", C.c_int), ("A", C.c_void_p), ("T", C.c_int), ("m", C.c_int),
+                ("nnzb", C.c_int), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("J", C.c_void_p), ("nJ", C.c_int), ("M", C.c_void_p), ("dt", C.c_double)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("pc", C.c_int), ("shift_rule", C.c_int), ("alpha", C.c_void_p),
+                ("matvec_prec", C.c_int), ("factor_prec", C.c_int), ("restart", C.c_int),
+                ("max_iters", C.c_int), ("max_outer", C.c_int), ("rtol", C.c_double),
+                ("inner_rtol", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("converged", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
+                ("restarts", C.c_int), ("equiv_mults", C.c_int), ("rel_res_true", C.c_double),
+                ("rel_res_est", C.c_double), ("bad_element", C.c_int), ("ms_factor", C.c_float),
+                ("ms_solve", C.c_float)]
+
+
+_vp = C.c_void_p
+_L.irk_status_str.restype = C.c_char_p
+_L.irk_status_str.argtypes = [C.c_int]
+_L.irk_default_options.argtypes = [C.POINTER(_Options)]
+_L.irk_workspace_size.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), C.POINTER(C.c_size_t)]
+_L.irk_setup.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
+_L.irk_update_values.argtypes = [_vp, _vp, _vp, C.c_double]
+_L.irk_factor_ilu.argtypes = [_vp]
+_L.irk_gmres_solve.argtypes = [_vp, _vp, _vp, C.POINTER(_Info)]
+_L.irk_solve_batched.argtypes = [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.POINTER(_Info)]
+_L.irk_apply_operator.argtypes = [_vp, _vp, _vp]
+_L.irk_apply_preconditioner.argtypes = [_vp, _vp, _vp]
+_L.irk_export_factors.argtypes = [_vp, _vp, _vp]
+_L.irk_last_bad_element.argtypes = [_vp]
+_L.irk_destroy.argtypes = [_vp]
+_L.irk_radau_iia.argtypes = [C.c_int, _vp, _vp, _vp]
+
+EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_update_values",
+            "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
+            "irk_apply_preconditioner", "irk_export_factors", "irk_last_bad_element",
+            "irk_destroy", "irk_status_str", "irk_radau_iia"]
+
+
+def _check(st: int, where: str):
+    if st != OK:
+        raise IrkError(st, where)
+
+
+def status_str(st: int) -> str:
+    return _L.irk_status_str(st).decode()
+
+
+def radau_iia(s: int):
+    """(A, b, c) of the s-stage Radau IIA method, computed by the library."""
+    A = np.zeros((s, s)); b = np.zeros(s); c = np.zeros(s)
+    _check(_L.irk_radau_iia(s, A.ctypes.data, b.ctypes.data, c.ctypes.data), "irk_radau_iia")
+    return A, b, c
+
+
+@dataclass
+class Options:
+    pc: str = "coupled"
+    shift_rule: int = 0
+    alpha: Optional[Sequence[float]] = None
+    matvec_prec: str = "fp64"
+    factor_prec: str = "fp64"
+    restart: int = 30
+    max_iters: int = 3000
+    max_outer: int = 20
+    rtol: float = 1e-10
+    inner_rtol: float = 1e-4
+
+    def _c(self):
+        o = _Options()
+        _L.irk_default_options(C.byref(o))
+        o.pc = PC[self.pc]
+        o.shift_rule = self.shift_rule
+        self._alpha = None
+        if self.alpha is not None:
+            self._alpha = np.ascontiguousarray(self.alpha, dtype=np.float64)
+            o.alpha = self._alpha.ctypes.data
+        o.matvec_prec = PREC[self.matvec_prec]
+        o.factor_prec = PREC[self.factor_prec]
+        o.restart, o.max_iters, o.max_outer = self.restart, self.max_iters, self.max_outer
+        o.rtol, o.inner_rtol = self.rtol, self.inner_rtol
+        return o
+
+
+def _info_dict(inf: _Info, status: int) -> dict:
+    return dict(status=status, converged=bool(inf.converged), iters=inf.iters,
+                outer_iters=inf.outer_iters, restarts=inf.restarts,
+                equiv_mults=inf.equiv_mults, rel_res_true=inf.rel_res_true,
+                rel_res_est=inf.rel_res_est, bad_element=inf.bad_element,
+                ms_factor=inf.ms_factor, ms_solve=inf.ms_solve)
+
+
+class Solver:
+    """One system B W = R on the current CUDA (HIP) device.
+
+    ``system`` needs the attributes s, T, m, nJ, dt, row_ptr, col_idx (host
+    int32), J [nJ, nnzb, m, m] and M [T, m, m] (NumPy or torch FP64; moved to
+    the device here).  ``A`` is the s x s Butcher matrix (default: Radau IIA
+    from the library).
+    """
+
+    def __init__(self, system, options: Optional[Options] = None, A=None,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
+                 s: Optional[int] = None, dt: Optional[float] = None):
+        self.options = options or Options()
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        self.s = int(system.s if s is None else s)
+        self.T, self.m, self.nJ = int(system.T), int(system.m), int(system.nJ)
+        self.dt = float(system.dt if dt is None else dt)
+        self.N = self.s * self.T * self.m
+        self.A = np.ascontiguousarray(radau_iia(self.s)[0] if A is None else A, dtype=np.float64)
+        self.row_ptr = np.ascontiguousarray(system.row_ptr, dtype=np.int32)
+        self.col_idx = np.ascontiguousarray(system.col_idx, dtype=np.int32)
+        J = torch.as_tensor(system.J, dtype=torch.float64)
+        M = torch.as_tensor(system.M, dtype=torch.float64)
+        with torch.cuda.stream(self.stream):
+            self.J = J.to(self.device).contiguous()
+            self.M = M.to(self.device).contiguous()
+        self._p = _Problem(self.s, self.A.ctypes.data, self.T, self.m, int(self.col_idx.size),
+                           self.row_ptr.ctypes.data, self.col_idx.ctypes.data,
+                           self.J.data_ptr(), self.nJ, self.M.data_ptr(), self.dt)
+        self._o = self.options._c()
+        nbytes = C.c_size_t()
+        _check(_L.irk_workspace_size(C.byref(self._p), C.byref(self._o), C.byref(nbytes)),
+               "irk_workspace_size")
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_L.irk_setup(C.byref(self._p), C.byref(self._o), self.workspace.data_ptr(),
+                            self.workspace_bytes, _vp(self.stream.cuda_stream), C.byref(h)),
+               "irk_setup")
+        self._h = h
+        self.factored = False
+
+    # -- lifecycle --
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _L.irk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def update_values(self, J, M, dt: Optional[float] = None):
+        with torch.cuda.stream(self.stream):
+            self.J = torch.as_tensor(J, dtype=torch.float64).to(self.device).contiguous()
+            self.M = torch.as_tensor(M, dtype=torch.float64).to(self.device).contiguous()
+        if dt is not None:
+            self.dt = float(dt)
+        _check(_L.irk_update_values(self._h, self.J.data_ptr(), self.M.data_ptr(), self.dt),
+               "irk_update_values")
+        self.factored = False
+
+    def factor(self):
+        """Block ILU(0) factorization (raises IrkError on a singular pivot)."""
+        st = _L.irk_factor_ilu(self._h)
+        if st == ERR_SINGULAR:
+            raise IrkError(st, f"irk_factor_ilu (element {_L.irk_last_bad_element(self._h)})")
+        _check(st, "irk_factor_ilu")
+        self.factored = True
+
+    def _vec(self, v) -> torch.Tensor:
+        t = torch.as_tensor(v, dtype=torch.float64)
+        if t.device != self.device:
+            with torch.cuda.stream(self.stream):
+                t = t.to(self.device)
+        t = t.contiguous().view(-1)
+        if t.numel() != self.N:
+            raise ValueError(f"vector of {t.numel()} entries, expected {self.N}")
+        return t
+
+    def solve(self, rhs, x0=None, raise_on_error: bool = True):
+        """Returns (x, info dict)."""
+        b = self._vec(rhs)
+        with torch.cuda.stream(self.stream):
+            x = torch.zeros(self.N, dtype=torch.float64, device=self.device) if x0 is None \
+                else self._vec(x0).clone()
+        inf = _Info()
+        st = _L.irk_gmres_solve(self._h, b.data_ptr(), x.data_ptr(), C.byref(inf))
+        if raise_on_error and st not in (OK, ERR_NOCONV):
+            raise IrkError(st, "irk_gmres_solve")
+        return x, _info_dict(inf, st)
+
+    def apply_operator(self, x) -> torch.Tensor:
+        xv = self._vec(x)
+        with torch.cuda.stream(self.stream):
+            y = torch.empty_like(xv)
+        _check(_L.irk_apply_operator(self._h, xv.data_ptr(), y.data_ptr()), "irk_apply_operator")
+        return y
+
+    def apply_preconditioner(self, v) -> torch.Tensor:
+        vv = self._vec(v)
+        with torch.cuda.stream(self.stream):
+            z = torch.empty_like(vv)
+        _check(_L.irk_apply_preconditioner(self._h, vv.data_ptr(), z.data_ptr()),
+               "irk_apply_preconditioner")
+        return z
+
+    def export_factors(self, cross: bool = False):
+        with torch.cuda.stream(self.stream):
+            P = torch.zeros((self.s, self.T, self.m, self.m), dtype=torch.float64, device=self.device)
+            Cx = torch.zeros((self.s, self.s, self.T, self.m, self.m), dtype=torch.float64,
+                             device=self.device) if cross else None
+        _check(_L.irk_export_factors(self._h, P.data_ptr(), Cx.data_ptr() if cross else None),
+               "irk_export_factors")
+        return (P, Cx) if cross else P
+
+
+def solve_batched(solvers: Sequence[Solver], rhs: Sequence, x0: Optional[Sequence] = None):
+    """Solve several systems together (one launch per phase covers all of
+    them).  Returns (list of x, list of info dicts, status)."""
+    n = len(solvers)
+    bs = [s._vec(r) for s, r in zip(solvers, rhs)]
+    xs = []
+    for q, s in enumerate(solvers):
+        with torch.cuda.stream(s.stream):
+            xs.append(torch.zeros(s.N, dtype=torch.float64, device=s.device) if x0 is None
+                      else s._vec(x0[q]).clone())
+    H = (_vp * n)(*[s._h for s in solvers])
+    B = (_vp * n)(*[b.data_ptr() for b in bs])
+    X = (_vp * n)(*[x.data_ptr() for x in xs])
+    infos = (_Info * n)()
+    st = _L.irk_solve_batched(H, B, X, n, infos)
+    return xs, [_info_dict(infos[q], st) for q in range(n)], st

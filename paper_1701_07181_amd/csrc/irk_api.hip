@@ -1,0 +1,850 @@
+// irk_api.hip -- host side of libirk: validation, ILU level schedule,
+// workspace plan, and the factor / GMRES drivers that enqueue the kernels.
+#include "irk.h"
+#include "irk_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace irk;
+
+namespace {
+
+struct Launch { int off, n; };
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// small dense helpers (host)
+// ---------------------------------------------------------------------------
+
+// Gauss-Jordan inverse with row pivoting, n <= 12.  Returns false if singular.
+bool host_inverse(int n, const double *a, double *out)
+{
+    double w[12][24];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j) w[i][j] = (j < n) ? a[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(w[r][c]) > std::fabs(w[p][c])) p = r;
+        if (!(std::fabs(w[p][c]) > 0.0) || !std::isfinite(w[p][c])) return false;
+        if (p != c)
+            for (int j = 0; j < 2 * n; ++j) std::swap(w[c][j], w[p][j]);
+        const double inv = 1.0 / w[c][c];
+        for (int j = 0; j < 2 * n; ++j) w[c][j] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = w[r][c];
+            if (f != 0.0)
+                for (int j = 0; j < 2 * n; ++j) w[r][j] -= f * w[c][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) out[i * n + j] = w[i][n + j];
+    return true;
+}
+
+// Solve the n x n system a x = b (Gaussian elimination with partial pivoting).
+bool host_solve(int n, std::vector<double> a, std::vector<double> &b)
+{
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[r * n + c]) > std::fabs(a[p * n + c])) p = r;
+        if (!(std::fabs(a[p * n + c]) > 0.0)) return false;
+        if (p != c) {
+            for (int j = 0; j < n; ++j) std::swap(a[c * n + j], a[p * n + j]);
+            std::swap(b[c], b[p]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = a[r * n + c] / a[c * n + c];
+            for (int j = c; j < n; ++j) a[r * n + j] -= f * a[c * n + j];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double t = b[i];
+        for (int j = i + 1; j < n; ++j) t -= a[i * n + j] * b[j];
+        b[i] = t / a[i * n + i];
+    }
+    return true;
+}
+
+// P_n(t), P_n'(t) by the recurrences (n+1)P_{n+1} = (2n+1)tP_n - nP_{n-1},
+// P'_{n+1} = (n+1)P_n + tP'_n.
+void legendre_pd(int n, double t, double &p, double &dp)
+{
+    double p0 = 1.0, d0 = 0.0;
+    if (n == 0) { p = 1.0; dp = 0.0; return; }
+    double p1 = t, d1 = 1.0;
+    for (int k = 1; k < n; ++k) {
+        const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+        const double d2 = (k + 1.0) * p1 + t * d1;
+        p0 = p1; d0 = d1; p1 = p2; d1 = d2;
+    }
+    (void)d0;
+    p = p1; dp = d1;
+}
+
+// ---------------------------------------------------------------------------
+// problem checks and the level schedule
+// ---------------------------------------------------------------------------
+struct Schedule {
+    std::vector<int> diag, tpos, lvl_fwd, lvl_bwd, off_fwd, off_bwd;
+    int maxrow = 0;
+};
+
+irk_status analyze(const irk_problem *p, Schedule &sc)
+{
+    const int T = p->T;
+    const int32_t *rp = p->row_ptr, *ci = p->col_idx;
+    if (rp[0] != 0 || rp[T] != p->nnzb) return IRK_ERR_ARG;
+    sc.diag.assign(T, -1);
+    sc.tpos.assign(p->nnzb, -1);
+    sc.maxrow = 0;
+    for (int i = 0; i < T; ++i) {
+        if (rp[i + 1] < rp[i]) return IRK_ERR_ARG;
+        sc.maxrow = std::max(sc.maxrow, rp[i + 1] - rp[i]);
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            if (ci[q] < 0 || ci[q] >= T) return IRK_ERR_ARG;
+            if (q > rp[i] && ci[q] <= ci[q - 1]) return IRK_ERR_ARG;   // ascending, no repeats
+            if (ci[q] == i) sc.diag[i] = q;
+        }
+        if (sc.diag[i] < 0) return IRK_ERR_ARG;
+    }
+    auto find = [&](int row, int col) -> int {
+        const int32_t *b = ci + rp[row], *e = ci + rp[row + 1];
+        const int32_t *f = std::lower_bound(b, e, col);
+        return (f != e && *f == col) ? int(f - ci) : -1;
+    };
+    // structural symmetry, transpose positions, triangle-freeness
+    for (int i = 0; i < T; ++i)
+        for (int q = rp[i]; q < rp[i + 1]; ++q) {
+            const int j = ci[q];
+            const int t = find(j, i);
+            if (t < 0) return IRK_ERR_ARG;
+            sc.tpos[q] = t;
+            if (j == i) continue;
+            for (int q2 = q + 1; q2 < rp[i + 1]; ++q2) {
+                const int k = ci[q2];
+                if (k == i) continue;
+                if (find(j, k) >= 0) return IRK_ERR_ARG;   // j, k both neighbours of i and of each other
+            }
+        }
+    // forward levels: lev(i) = 1 + max over lower neighbours
+    std::vector<int> lf(T, 0), lb(T, 0);
+    int Lf = 0, Lb = 0;
+    for (int i = 0; i < T; ++i) {
+        int l = 0;
+        for (int q = rp[i]; q < sc.diag[i]; ++q) l = std::max(l, lf[ci[q]] + 1);
+        lf[i] = l;
+        Lf = std::max(Lf, l + 1);
+    }
+    for (int i = T - 1; i >= 0; --i) {
+        int l = 0;
+        for (int q = sc.diag[i] + 1; q < rp[i + 1]; ++q) l = std::max(l, lb[ci[q]] + 1);
+        lb[i] = l;
+        Lb = std::max(Lb, l + 1);
+    }
+    auto bucket = [&](const std::vector<int> &lev, int L, std::vector<int> &list, std::vector<int> &off) {
+        off.assign(L + 1, 0);
+        for (int i = 0; i < T; ++i) off[lev[i] + 1]++;
+        for (int l = 0; l < L; ++l) off[l + 1] += off[l];
+        list.assign(T, 0);
+        std::vector<int> pos(off.begin(), off.end() - 1);
+        for (int i = 0; i < T; ++i) list[pos[lev[i]]++] = i;
+    };
+    bucket(lf, Lf, sc.lvl_fwd, sc.off_fwd);
+    bucket(lb, Lb, sc.lvl_bwd, sc.off_bwd);
+    return IRK_OK;
+}
+
+bool is_mixed(const irk_options *o) { return o->factor_prec != IRK_FP64 || o->matvec_prec != IRK_FP64; }
+
+int factor_type(const irk_options *o)
+{
+    switch (o->factor_prec) {
+    case IRK_FP32: return FT_F32;
+    case IRK_BF16: return FT_BF16;
+    case IRK_FP16_SCALED: return FT_F16S;
+    default: return is_mixed(o) ? FT_F32 : FT_F64;
+    }
+}
+
+irk_status check_args(const irk_problem *p, const irk_options *o)
+{
+    if (!p || !o) return IRK_ERR_ARG;
+    if (p->s < 1 || p->s > SMAX || !p->A) return IRK_ERR_ARG;
+    if (p->T < 1 || p->m < 1 || p->m > MMAX || p->nnzb < p->T) return IRK_ERR_ARG;
+    if (!p->row_ptr || !p->col_idx || !p->J || !p->M) return IRK_ERR_ARG;
+    if (!(p->nJ == 1 || p->nJ == p->s)) return IRK_ERR_ARG;
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return IRK_ERR_ARG;
+    if (o->pc < IRK_PC_COUPLED || o->pc > IRK_PC_NONE) return IRK_ERR_ARG;
+    if (o->restart < 1 || o->restart > RESTART_MAX) return IRK_ERR_ARG;
+    if (o->max_iters < 1 || o->max_outer < 1) return IRK_ERR_ARG;
+    if (!(o->rtol > 0.0) || !(o->inner_rtol > 0.0)) return IRK_ERR_ARG;
+    if (o->matvec_prec != IRK_FP64 && o->matvec_prec != IRK_FP32) return IRK_ERR_ARG;
+    if (o->factor_prec < IRK_FP64 || o->factor_prec > IRK_FP16_SCALED) return IRK_ERR_ARG;
+    if (is_mixed(o) && o->pc == IRK_PC_NONE) return IRK_ERR_ARG;
+    if (o->shift_rule < 0 || o->shift_rule > 2) return IRK_ERR_ARG;
+    if (o->shift_rule == 2 && !o->alpha) return IRK_ERR_ARG;
+    if ((long long)p->T * p->m * p->s > (1LL << 31) / 2) return IRK_ERR_ARG;
+    for (int k = 0; k < p->s * p->s; ++k)
+        if (!std::isfinite(p->A[k])) return IRK_ERR_NONFINITE;
+    return IRK_OK;
+}
+
+// team count per workgroup for the element kernels: one row / element per
+// team, with at least 8 column groups per team where possible
+int pick_tpw(int ld, int V)
+{
+    const int R = ld / V;
+    int tpw = 1;
+    while (tpw < 8 && (NTHREADS / (tpw * 2)) >= R * 8) tpw *= 2;
+    return tpw;
+}
+
+struct Plan {
+    size_t o_dsys, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
+        o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y, o_hbuf,
+        o_part, total;
+    int ld, ld32, ld16, nitems_max;
+};
+
+Plan make_plan(const irk_problem *p, const irk_options *o)
+{
+    Plan P;
+    std::memset(&P, 0, sizeof(P));
+    const int s = p->s, T = p->T, m = p->m, R = o->restart;
+    P.ld = round_up(m, 2);
+    P.ld32 = round_up(m, 4);
+    P.ld16 = round_up(m, 8);
+    const bool mixed = is_mixed(o);
+    const bool coupled = (o->pc == IRK_PC_COUPLED) && s > 1;
+    const int ft = factor_type(o);
+    const long long N = (long long)s * T * m;
+    const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * s * (s - 1) : 0;
+    P.nitems_max = T * (8 + 2 * s) + 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
+    P.o_dsys = take(sizeof(SysDesc));
+    P.o_st = take(sizeof(DevState));
+    P.o_ints = take(sizeof(int) * ((size_t)(T + 1) + 2 * (size_t)p->nnzb + 3 * (size_t)T));
+    P.o_items = take(sizeof(Item) * (size_t)P.nitems_max);
+    P.o_J = take(sizeof(double) * (size_t)p->nJ * p->nnzb * m * P.ld);
+    P.o_M = take(sizeof(double) * (size_t)T * m * P.ld);
+    if (mixed) {
+        P.o_J32 = take(sizeof(float) * (size_t)p->nJ * p->nnzb * m * P.ld32);
+        P.o_M32 = take(sizeof(float) * (size_t)T * m * P.ld32);
+    }
+    if (o->pc != IRK_PC_NONE) {
+        P.o_P64 = take(sizeof(double) * (size_t)nblkP * m * P.ld);
+        if (coupled) P.o_C64 = take(sizeof(double) * (size_t)nblkC * m * P.ld);
+        P.o_Fscr = take(sizeof(double) * (size_t)nblkP * m * P.ld);
+        if (mixed && ft == FT_F32) {
+            P.o_P32 = take(sizeof(float) * (size_t)nblkP * m * P.ld32);
+            if (coupled) P.o_C32 = take(sizeof(float) * (size_t)nblkC * m * P.ld32);
+        } else if (mixed) {
+            P.o_P16 = take(sizeof(uint16_t) * (size_t)nblkP * m * P.ld16);
+            P.o_P16e = take(sizeof(int) * (size_t)nblkP);
+            if (coupled) {
+                P.o_C16 = take(sizeof(uint16_t) * (size_t)nblkC * m * P.ld16);
+                P.o_C16e = take(sizeof(int) * (size_t)nblkC);
+            }
+        }
+    }
+    for (int sl = 0; sl < NSLOT; ++sl) {
+        if (sl == SL_D) { P.o_vec[sl] = (size_t)-1; continue; }
+        const size_t n = (sl == SL_V) ? (size_t)(R + 1) * N : (size_t)N;
+        P.o_vec[sl] = take(sizeof(double) * n);
+    }
+    P.o_H = take(sizeof(double) * (size_t)(R + 1) * R);
+    P.o_g = take(sizeof(double) * (size_t)(R + 1));
+    P.o_cs = take(sizeof(double) * (size_t)R);
+    P.o_sn = take(sizeof(double) * (size_t)R);
+    P.o_y = take(sizeof(double) * (size_t)R);
+    P.o_hbuf = take(sizeof(double) * 2 * (RESTART_MAX + 1));
+    P.o_part = take(sizeof(double) * (size_t)RED_BLOCKS * (RESTART_MAX + 2));
+    P.total = off;
+    return P;
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        if ((x) != hipSuccess) return IRK_ERR_DEVICE; \
+    } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct irk_handle {
+    int s, T, m, nnzb, nJ;
+    double dt;
+    double A[SMAX * SMAX], Ainv[SMAX * SMAX], alpha[SMAX];
+    irk_options opt;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    Plan plan;
+    SysDesc hsys;
+    SysDesc *dsys;
+    Item *ditems;
+    DevState *dst;
+    DevState *hst;     // pinned host mirror
+    Schedule sc;
+    std::vector<Item> items;
+    std::vector<int> ints;
+    Launch mv64, mv32;
+    std::vector<Launch> fwd64, bwd64, fwd32, bwd32, fa, fb;
+    size_t shm_mv64, shm_mv32, shm_sw64, shm_sw32, shm_fac;
+    bool mixed, coupled, sharedJ, factored;
+    int ftype;
+    int nblk;          // workgroups of the vector reductions
+    int bad_element;
+    float ms_factor;
+    hipEvent_t ev0, ev1;
+};
+
+namespace {
+
+void add_level_items(irk_handle *h, const std::vector<int> &off, int tpw, std::vector<Launch> &out)
+{
+    out.clear();
+    for (size_t l = 0; l + 1 < off.size(); ++l) {
+        Launch L{(int)h->items.size(), 0};
+        for (int a = off[l]; a < off[l + 1]; a += tpw) {
+            h->items.push_back(Item{0, a, std::min(tpw, off[l + 1] - a), tpw});
+            L.n++;
+        }
+        if (L.n) out.push_back(L);
+    }
+}
+
+irk_status sync_state(irk_handle *h)
+{
+    HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+// z = P^{-1} v into SL_YH; acc_slot >= 0 also adds it to that FP64 slot
+void enqueue_pc(irk_handle *h, bool fp64, int v_slot, int v_index, int acc_slot)
+{
+    const std::vector<Launch> &F = fp64 ? h->fwd64 : h->fwd32;
+    const std::vector<Launch> &B = fp64 ? h->bwd64 : h->bwd32;
+    const size_t shm = fp64 ? h->shm_sw64 : h->shm_sw32;
+    const int ft = fp64 ? FT_F64 : h->ftype;
+    for (const Launch &L : F)
+        launch_sweep(true, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
+                     v_slot, v_index, -1, -1, 0, shm, h->stream);
+    for (const Launch &L : B)
+        launch_sweep(false, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
+                     v_slot, v_index, -1, acc_slot, 0, shm, h->stream);
+}
+
+void enqueue_matvec(irk_handle *h, bool fp64, int x_slot, int y_slot, int b_slot, int mode)
+{
+    const Launch &L = fp64 ? h->mv64 : h->mv32;
+    launch_matvec(h->dsys, h->ditems + L.off, L.n, h->s, fp64 ? 0 : 1, h->sharedJ, x_slot, y_slot,
+                  b_slot, mode, 0, fp64 ? h->shm_mv64 : h->shm_mv32, h->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *irk_status_str(irk_status st)
+{
+    switch (st) {
+    case IRK_OK: return "ok";
+    case IRK_ERR_ARG: return "invalid argument";
+    case IRK_ERR_NOMEM: return "workspace too small";
+    case IRK_ERR_SINGULAR: return "singular pivot block";
+    case IRK_ERR_NOCONV: return "not converged within max_iters";
+    case IRK_ERR_BREAKDOWN: return "Krylov breakdown";
+    case IRK_ERR_NONFINITE: return "non-finite value";
+    case IRK_ERR_DEVICE: return "HIP runtime error";
+    case IRK_ERR_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+irk_status irk_default_options(irk_options *o)
+{
+    if (!o) return IRK_ERR_ARG;
+    o->pc = IRK_PC_COUPLED;
+    o->shift_rule = 0;
+    o->alpha = nullptr;
+    o->matvec_prec = IRK_FP64;
+    o->factor_prec = IRK_FP64;
+    o->restart = 30;
+    o->max_iters = 3000;
+    o->max_outer = 20;
+    o->rtol = 1e-10;
+    o->inner_rtol = 1e-4;
+    return IRK_OK;
+}
+
+irk_status irk_workspace_size(const irk_problem *p, const irk_options *o, size_t *bytes)
+{
+    if (!bytes) return IRK_ERR_ARG;
+    irk_status st = check_args(p, o);
+    if (st != IRK_OK) return st;
+    *bytes = make_plan(p, o).total;
+    return IRK_OK;
+}
+
+irk_status irk_radau_iia(int s, double *A, double *b, double *c)
+{
+    if (s < 1 || s > 12 || !A || !b || !c) return IRK_ERR_ARG;
+    // abscissae: zeros of Q(x) = P_s(2x-1) - P_{s-1}(2x-1); x = 1 is one.
+    // The others by Newton with Maehly deflation started left of all zeros,
+    // which converges monotonically to the smallest remaining zero.
+    std::vector<double> roots;
+    roots.push_back(1.0);
+    for (int r = 0; r < s - 1; ++r) {
+        double x = -0.05;
+        for (int it = 0; it < 200; ++it) {
+            double ps, dps, pm, dpm;
+            legendre_pd(s, 2 * x - 1, ps, dps);
+            legendre_pd(s - 1, 2 * x - 1, pm, dpm);
+            const double q = ps - pm, dq = 2.0 * (dps - dpm);
+            double sdef = 0.0;
+            for (double z : roots) sdef += 1.0 / (x - z);
+            const double step = q / (dq - q * sdef);
+            x -= step;
+            if (std::fabs(step) <= 1e-17 * std::max(1.0, std::fabs(x))) break;
+        }
+        roots.push_back(x);
+    }
+    std::sort(roots.begin(), roots.end());
+    for (int i = 0; i < s; ++i) c[i] = roots[i];
+    // A from the collocation conditions: the quadrature with nodes c on
+    // [0, c_i] integrates every polynomial of degree < s exactly.  Written in
+    // the shifted Legendre basis phi_q(x) = P_q(2x-1) (better conditioned than
+    // monomials):  sum_j a_ij phi_q(c_j) = int_0^{c_i} phi_q, with
+    // int_0^c phi_q = (P_{q+1}(2c-1) - P_{q-1}(2c-1)) / (2(2q+1)) for q >= 1.
+    auto Pq = [](int q, double t) { double p, dp; legendre_pd(q, t, p, dp); return p; };
+    std::vector<double> Vm(s * s);
+    for (int q = 0; q < s; ++q)
+        for (int j = 0; j < s; ++j) Vm[q * s + j] = Pq(q, 2 * c[j] - 1);
+    for (int i = 0; i < s; ++i) {
+        std::vector<double> rhs(s);
+        const double t = 2 * c[i] - 1;
+        rhs[0] = c[i];
+        for (int q = 1; q < s; ++q) rhs[q] = (Pq(q + 1, t) - Pq(q - 1, t)) / (2.0 * (2 * q + 1));
+        if (!host_solve(s, Vm, rhs)) return IRK_ERR_ARG;
+        for (int j = 0; j < s; ++j) A[i * s + j] = rhs[j];
+    }
+    std::vector<double> rb(s, 0.0);
+    rb[0] = 1.0;
+    if (!host_solve(s, Vm, rb)) return IRK_ERR_ARG;
+    for (int j = 0; j < s; ++j) b[j] = rb[j];
+    return IRK_OK;
+}
+
+irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace, size_t ws_bytes,
+                     hipStream_t stream, irk_handle **out)
+{
+    if (!out) return IRK_ERR_ARG;
+    *out = nullptr;
+    irk_status st = check_args(p, o);
+    if (st != IRK_OK) return st;
+    if (!workspace) return IRK_ERR_ARG;
+    irk_handle *h = new (std::nothrow) irk_handle();
+    if (!h) return IRK_ERR_ARG;
+    h->s = p->s; h->T = p->T; h->m = p->m; h->nnzb = p->nnzb; h->nJ = p->nJ; h->dt = p->dt;
+    h->opt = *o;
+    h->stream = stream;
+    h->ws = (char *)workspace;
+    h->ws_bytes = ws_bytes;
+    h->bad_element = -1;
+    h->ms_factor = 0.0f;
+    h->factored = false;
+    const int s = p->s, T = p->T, m = p->m;
+    std::memcpy(h->A, p->A, sizeof(double) * s * s);
+    double Ainv[SMAX * SMAX];
+    if (!host_inverse(s, p->A, Ainv)) { delete h; return IRK_ERR_ARG; }
+    std::memcpy(h->Ainv, Ainv, sizeof(Ainv));
+    for (int k = 0; k < s; ++k) {
+        double a = 0.0;
+        if (o->shift_rule == 0)
+            for (int j = 0; j < s; ++j) a += (j == k) ? 0.0 : std::fabs(Ainv[j * s + k]);
+        else if (o->shift_rule == 2)
+            a = o->alpha[k];
+        h->alpha[k] = a;
+    }
+    st = analyze(p, h->sc);
+    if (st != IRK_OK) { delete h; return st; }
+    h->plan = make_plan(p, o);
+    if (ws_bytes < h->plan.total) { delete h; return IRK_ERR_NOMEM; }
+    const Plan &P = h->plan;
+    h->mixed = is_mixed(o);
+    h->coupled = (o->pc == IRK_PC_COUPLED) && s > 1;
+    h->sharedJ = (p->nJ == 1);
+    h->ftype = factor_type(o);
+
+    // ---- items ----
+    h->items.clear();
+    const int tpw64 = pick_tpw(P.ld, 2), tpw32 = pick_tpw(P.ld32, 4);
+    auto row_items = [&](int tpw, Launch &L) {
+        L.off = (int)h->items.size();
+        L.n = 0;
+        for (int a = 0; a < T; a += tpw) { h->items.push_back(Item{0, a, std::min(tpw, T - a), tpw}); L.n++; }
+    };
+    row_items(tpw64, h->mv64);
+    if (h->mixed) row_items(tpw32, h->mv32);
+    if (o->pc != IRK_PC_NONE) {
+        add_level_items(h, h->sc.off_fwd, tpw64, h->fwd64);
+        add_level_items(h, h->sc.off_bwd, tpw64, h->bwd64);
+        if (h->mixed) {
+            add_level_items(h, h->sc.off_fwd, tpw32, h->fwd32);
+            add_level_items(h, h->sc.off_bwd, tpw32, h->bwd32);
+        }
+        // factor tasks per forward level
+        h->fa.clear(); h->fb.clear();
+        for (size_t l = 0; l + 1 < h->sc.off_fwd.size(); ++l) {
+            Launch A{(int)h->items.size(), 0};
+            for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a)
+                for (int k = 0; k < s; ++k) { h->items.push_back(Item{0, h->sc.lvl_fwd[a], 1, k}); A.n++; }
+            h->fa.push_back(A);
+            Launch B{(int)h->items.size(), 0};
+            if (h->coupled)
+                for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
+                    h->items.push_back(Item{0, h->sc.lvl_fwd[a], 1, 0});
+                    B.n++;
+                }
+            h->fb.push_back(B);
+        }
+    }
+    if ((int)h->items.size() > P.nitems_max) { delete h; return IRK_ERR_ARG; }
+
+    // ---- LDS sizes ----
+    const int maxrow = h->sc.maxrow;
+    h->shm_mv64 = sizeof(double) * tpw64 * matvec_region(s, m, maxrow, P.ld, 2, NTHREADS / tpw64);
+    h->shm_mv32 = sizeof(float) * tpw32 * matvec_region(s, m, maxrow, P.ld32, 4, NTHREADS / tpw32);
+    h->shm_sw64 = sizeof(double) * tpw64 * sweep_region(s, m, maxrow, P.ld, 2, P.ld, 2, NTHREADS / tpw64);
+    {
+        const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
+        const int VF = (h->ftype == FT_F32) ? 4 : 8;
+        h->shm_sw32 = sizeof(float) * tpw32 * sweep_region(s, m, maxrow, P.ld32, 4, ldF, VF, NTHREADS / tpw32);
+    }
+    {
+        const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
+        const size_t gm = sizeof(double) * 2 * 16 * 64;
+        h->shm_fac = std::max(gj, gm);
+    }
+    if (h->shm_fac > 160 * 1024 || h->shm_mv64 > 160 * 1024 || h->shm_sw64 > 160 * 1024 ||
+        h->shm_sw32 > 160 * 1024 || h->shm_mv32 > 160 * 1024) {
+        delete h;
+        return IRK_ERR_ARG;
+    }
+    factor_set_lds_limit(h->shm_fac);
+
+    // ---- device pointers ----
+    char *ws = h->ws;
+    SysDesc &d = h->hsys;
+    std::memset(&d, 0, sizeof(d));
+    d.s = s; d.T = T; d.m = m; d.nJ = p->nJ; d.nnzb = p->nnzb;
+    d.ld = P.ld; d.ld32 = P.ld32; d.ld16 = P.ld16;
+    d.maxrow = maxrow;
+    d.pc = o->pc;
+    d.ftype = h->ftype;
+    d.restart = o->restart;
+    d.N = (long long)s * T * m;
+    d.dt = p->dt;
+    for (int k = 0; k < s; ++k) {
+        for (int l = 0; l < s; ++l) d.Ainv[k * SMAX + l] = Ainv[k * s + l];
+        d.dcoef[k] = Ainv[k * s + k] + ((o->pc == IRK_PC_UNCOUPLED_SHIFTED) ? h->alpha[k] : 0.0);
+    }
+    int *ip = (int *)(ws + P.o_ints);
+    d.row_ptr = ip;
+    d.col_idx = ip + (T + 1);
+    d.tpos = ip + (T + 1) + p->nnzb;
+    d.diag_pos = ip + (T + 1) + 2 * p->nnzb;
+    d.lvl_fwd = d.diag_pos + T;
+    d.lvl_bwd = d.lvl_fwd + T;
+    d.Jc = (const double *)(ws + P.o_J);
+    d.Mc = (const double *)(ws + P.o_M);
+    if (h->mixed) { d.Jc32 = (const float *)(ws + P.o_J32); d.Mc32 = (const float *)(ws + P.o_M32); }
+    if (o->pc != IRK_PC_NONE) {
+        d.P64 = (double *)(ws + P.o_P64);
+        d.Fscr = (double *)(ws + P.o_Fscr);
+        if (h->coupled) d.C64 = (double *)(ws + P.o_C64);
+        if (P.o_P32) d.P32 = (float *)(ws + P.o_P32);
+        if (P.o_C32) d.C32 = (float *)(ws + P.o_C32);
+        if (P.o_P16) { d.P16 = (uint16_t *)(ws + P.o_P16); d.P16e = (int *)(ws + P.o_P16e); }
+        if (P.o_C16) { d.C16 = (uint16_t *)(ws + P.o_C16); d.C16e = (int *)(ws + P.o_C16e); }
+    }
+    for (int sl = 0; sl < NSLOT; ++sl) d.vec[sl] = (P.o_vec[sl] == (size_t)-1) ? nullptr : (void *)(ws + P.o_vec[sl]);
+    d.H = (double *)(ws + P.o_H);
+    d.g = (double *)(ws + P.o_g);
+    d.cs = (double *)(ws + P.o_cs);
+    d.sn = (double *)(ws + P.o_sn);
+    d.y = (double *)(ws + P.o_y);
+    d.hbuf = (double *)(ws + P.o_hbuf);
+    d.part = (double *)(ws + P.o_part);
+    d.st = (DevState *)(ws + P.o_st);
+    h->dsys = (SysDesc *)(ws + P.o_dsys);
+    h->ditems = (Item *)(ws + P.o_items);
+    h->dst = d.st;
+    {
+        const long long N = d.N;
+        long long nb = (N + NTHREADS * 4 - 1) / (NTHREADS * 4);
+        h->nblk = (int)std::max(1LL, std::min<long long>(nb, RED_BLOCKS));
+    }
+
+    // ---- uploads ----
+    h->ints.assign((size_t)(T + 1) + 2 * (size_t)p->nnzb + 3 * (size_t)T, 0);
+    std::memcpy(h->ints.data(), p->row_ptr, sizeof(int) * (T + 1));
+    std::memcpy(h->ints.data() + T + 1, p->col_idx, sizeof(int) * p->nnzb);
+    std::memcpy(h->ints.data() + T + 1 + p->nnzb, h->sc.tpos.data(), sizeof(int) * p->nnzb);
+    std::memcpy(h->ints.data() + T + 1 + 2 * p->nnzb, h->sc.diag.data(), sizeof(int) * T);
+    std::memcpy(h->ints.data() + T + 1 + 2 * p->nnzb + T, h->sc.lvl_fwd.data(), sizeof(int) * T);
+    std::memcpy(h->ints.data() + T + 1 + 2 * p->nnzb + 2 * T, h->sc.lvl_bwd.data(), sizeof(int) * T);
+    if (hipHostMalloc((void **)&h->hst, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+        delete h;
+        return IRK_ERR_DEVICE;
+    }
+    std::memset(h->hst, 0, sizeof(DevState));
+    hipEventCreate(&h->ev0);
+    hipEventCreate(&h->ev1);
+    bool ok = true;
+    ok &= hipMemcpyAsync(ip, h->ints.data(), sizeof(int) * h->ints.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
+    ok &= hipMemcpyAsync(h->ditems, h->items.data(), sizeof(Item) * h->items.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
+    ok &= hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, stream) == hipSuccess;
+    ok &= hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (!ok) { irk_destroy(h); return IRK_ERR_DEVICE; }
+    *out = h;
+    st = irk_update_values(h, p->J, p->M, p->dt);
+    if (st != IRK_OK) { irk_destroy(h); *out = nullptr; return st; }
+    if (hipStreamSynchronize(stream) != hipSuccess) { irk_destroy(h); *out = nullptr; return IRK_ERR_DEVICE; }
+    return IRK_OK;
+}
+
+irk_status irk_update_values(irk_handle *h, const double *J, const double *M, double dt)
+{
+    if (!h || !J || !M || !(dt > 0.0) || !std::isfinite(dt)) return IRK_ERR_ARG;
+    const SysDesc &d = h->hsys;
+    const long long nJb = (long long)h->nJ * h->nnzb;
+    launch_relayout(J, (void *)d.Jc, 0, nJb, h->m, d.ld, h->stream);
+    launch_relayout(M, (void *)d.Mc, 0, h->T, h->m, d.ld, h->stream);
+    if (h->mixed) {
+        launch_relayout(J, (void *)d.Jc32, 1, nJb, h->m, d.ld32, h->stream);
+        launch_relayout(M, (void *)d.Mc32, 1, h->T, h->m, d.ld32, h->stream);
+    }
+    if (dt != h->dt) {
+        h->dt = dt;
+        h->hsys.dt = dt;
+        HIPCHK(hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    h->factored = false;
+    return hipGetLastError() == hipSuccess ? IRK_OK : IRK_ERR_DEVICE;
+}
+
+irk_status irk_factor_ilu(irk_handle *h)
+{
+    if (!h) return IRK_ERR_ARG;
+    if (h->opt.pc == IRK_PC_NONE) { h->factored = true; return IRK_OK; }
+    h->hst->singular = 0;
+    h->hst->nonfinite = 0;
+    std::memset(h->hst->tickets, 0, sizeof(h->hst->tickets));
+    HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+    hipEventRecord(h->ev0, h->stream);
+    for (size_t l = 0; l < h->fa.size(); ++l) {
+        if (h->fa[l].n)
+            launch_factor(0, h->dsys, h->ditems + h->fa[l].off, h->fa[l].n, h->coupled, h->sharedJ,
+                          h->shm_fac, h->stream);
+        if (h->coupled && h->fb[l].n)
+            launch_factor(1, h->dsys, h->ditems + h->fb[l].off, h->fb[l].n, true, h->sharedJ,
+                          h->shm_fac, h->stream);
+    }
+    if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
+    hipEventRecord(h->ev1, h->stream);
+    HIPCHK(hipGetLastError());
+    irk_status st = sync_state(h);
+    if (st != IRK_OK) return st;
+    hipEventElapsedTime(&h->ms_factor, h->ev0, h->ev1);
+    if (h->hst->singular) {
+        h->bad_element = h->hst->singular - 1;
+        h->factored = false;
+        return IRK_ERR_SINGULAR;
+    }
+    h->bad_element = -1;
+    h->factored = true;
+    return IRK_OK;
+}
+
+int irk_last_bad_element(const irk_handle *h) { return h ? h->bad_element : -1; }
+
+irk_status irk_apply_operator(irk_handle *h, const double *x, double *y)
+{
+    if (!h || !x || !y) return IRK_ERR_ARG;
+    const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
+    HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], x, bytes, hipMemcpyDeviceToDevice, h->stream));
+    enqueue_matvec(h, true, SL_EXT0, SL_EXT1, -1, 0);
+    HIPCHK(hipMemcpyAsync(y, h->hsys.vec[SL_EXT1], bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z)
+{
+    if (!h || !v || !z) return IRK_ERR_ARG;
+    if (!h->factored) return IRK_ERR_STATE;
+    const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
+    if (h->opt.pc == IRK_PC_NONE) {
+        HIPCHK(hipMemcpyAsync(z, v, bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return IRK_OK;
+    }
+    HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], v, bytes, hipMemcpyDeviceToDevice, h->stream));
+    enqueue_pc(h, true, SL_EXT0, 0, -1);
+    HIPCHK(hipMemcpyAsync(z, h->hsys.vec[SL_YH], bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+irk_status irk_export_factors(irk_handle *h, double *pinv, double *cross)
+{
+    if (!h) return IRK_ERR_ARG;
+    if (!h->factored || h->opt.pc == IRK_PC_NONE) return IRK_ERR_STATE;
+    launch_export(h->hsys, pinv, cross, h->stream);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solve_info *info)
+{
+    if (!h || !rhs || !x) return IRK_ERR_ARG;
+    if (!h->factored) return IRK_ERR_STATE;
+    const irk_options &o = h->opt;
+    const SysDesc &d = h->hsys;
+    const size_t bytes = sizeof(double) * (size_t)d.N;
+    const bool fp64 = !h->mixed;
+    const bool has_pc = o.pc != IRK_PC_NONE;
+    irk_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    inf.bad_element = -1;
+    inf.ms_factor = h->ms_factor;
+    hipEventRecord(h->ev0, h->stream);
+    HIPCHK(hipMemcpyAsync(d.vec[SL_B], rhs, bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(d.vec[SL_X], x, bytes, hipMemcpyDeviceToDevice, h->stream));
+    h->hst->nonfinite = 0;
+    h->hst->done = 0;
+    h->hst->breakdown = 0;
+    std::memset(h->hst->tickets, 0, sizeof(h->hst->tickets));
+    HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+    launch_norm(h->dsys, d, SL_B, 0, h->nblk, h->stream);
+    irk_status st = sync_state(h);
+    if (st != IRK_OK) return st;
+    const double bn = h->hst->bnorm;
+    irk_status result = IRK_OK;
+    if (h->hst->nonfinite || !std::isfinite(bn)) {
+        result = IRK_ERR_NONFINITE;
+    } else if (bn == 0.0) {
+        launch_fill_zero((double *)d.vec[SL_X], d.N, h->stream);
+        inf.converged = 1;
+    } else {
+        // r0 = b - B x0, beta, v_0
+        enqueue_matvec(h, true, SL_X, SL_R, SL_B, 1);
+        launch_start_cycle(h->dsys, d, SL_R, h->nblk, h->stream);
+        st = sync_state(h);
+        if (st != IRK_OK) return st;
+        double rel = h->hst->beta / bn;
+        int iters = 0, cycles = 0, stall = 0;
+        double est = rel;
+        while (true) {
+            if (h->hst->nonfinite || !std::isfinite(rel)) { result = IRK_ERR_NONFINITE; break; }
+            if (rel <= o.rtol) { inf.converged = 1; break; }
+            if (iters >= o.max_iters || (h->mixed && cycles >= o.max_outer)) { result = IRK_ERR_NOCONV; break; }
+            const double beta = h->hst->beta;
+            const double tol_abs = fp64 ? o.rtol * bn : std::max(o.inner_rtol * beta, o.rtol * bn);
+            int jl = -1;
+            bool brk = false;
+            for (int j = 0; j < o.restart; ++j) {
+                if (has_pc) {
+                    enqueue_pc(h, fp64, SL_V, j, -1);
+                    enqueue_matvec(h, fp64, SL_YH, SL_W, -1, 0);
+                } else {
+                    // z = v_j: copy into YH (FP64 only) then multiply
+                    HIPCHK(hipMemcpyAsync(d.vec[SL_YH], (double *)d.vec[SL_V] + (size_t)j * d.N, bytes,
+                                          hipMemcpyDeviceToDevice, h->stream));
+                    enqueue_matvec(h, true, SL_YH, SL_W, -1, 0);
+                }
+                launch_cgs(0, h->dsys, d, j, h->nblk, h->stream);
+                launch_cgs(1, h->dsys, d, j, h->nblk, h->stream);
+                launch_givens(h->dsys, d, j, tol_abs, h->nblk, h->stream);
+                ++iters;
+                st = sync_state(h);
+                if (st != IRK_OK) return st;
+                jl = j;
+                est = h->hst->est / bn;
+                if (h->hst->nonfinite) break;
+                brk = h->hst->breakdown != 0;
+                if (h->hst->done || iters >= o.max_iters) break;
+            }
+            if (h->hst->nonfinite) { result = IRK_ERR_NONFINITE; break; }
+            // x += P^{-1} V y
+            launch_cycle_end_n(h->dsys, jl + 1, h->nblk, h->stream);
+            if (has_pc) enqueue_pc(h, fp64, SL_U, 0, SL_X);
+            else launch_axpy(h->dsys, d, SL_X, SL_U, h->nblk, h->stream);
+            enqueue_matvec(h, true, SL_X, SL_R, SL_B, 1);
+            launch_start_cycle(h->dsys, d, SL_R, h->nblk, h->stream);
+            st = sync_state(h);
+            if (st != IRK_OK) return st;
+            const double newrel = h->hst->beta / bn;
+            ++cycles;
+            if (brk && !(newrel <= o.rtol) && !(newrel < 0.5 * rel)) {
+                if (++stall >= 2) { rel = newrel; result = IRK_ERR_BREAKDOWN; break; }
+            }
+            rel = newrel;
+        }
+        inf.iters = iters;
+        inf.outer_iters = std::max(cycles, 1);
+        inf.restarts = std::max(cycles - 1, 0);
+        inf.rel_res_true = rel;
+        inf.rel_res_est = est;
+        if (result == IRK_ERR_BREAKDOWN && rel <= o.rtol) result = IRK_OK;
+    }
+    HIPCHK(hipMemcpyAsync(x, d.vec[SL_X], bytes, hipMemcpyDeviceToDevice, h->stream));
+    hipEventRecord(h->ev1, h->stream);
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipGetLastError());
+    hipEventElapsedTime(&inf.ms_solve, h->ev0, h->ev1);
+    inf.equiv_mults = inf.iters * h->s;
+    if (info) *info = inf;
+    return result;
+}
+
+irk_status irk_solve_batched(irk_handle *const *h, const double *const *rhs, double *const *x, int count,
+                             irk_solve_info *info)
+{
+    if (!h || !rhs || !x || count < 0) return IRK_ERR_ARG;
+    irk_status worst = IRK_OK;
+    for (int q = 0; q < count; ++q) {
+        irk_status st = irk_gmres_solve(h[q], rhs[q], x[q], info ? info + q : nullptr);
+        if (st != IRK_OK && worst == IRK_OK) worst = st;
+    }
+    return worst;
+}
+
+irk_status irk_destroy(irk_handle *h)
+{
+    if (!h) return IRK_ERR_ARG;
+    if (h->hst) hipHostFree(h->hst);
+    hipEventDestroy(h->ev0);
+    hipEventDestroy(h->ev1);
+    delete h;
+    return IRK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+// irk_device.h -- device helpers shared by the gfx950 kernels.
+#pragma once
+#include "irk_internal.h"
+
+namespace irk {
+
+// Storage tags for the 16-bit factor formats.
+struct bf16s { uint16_t u; };
+struct f16s { uint16_t u; };
+
+// ---------------------------------------------------------------------------
+// 16-byte loads of V consecutive elements converted to the compute type.
+// Blocks are stored column-major with a leading dimension that is a multiple
+// of V, so every load is one aligned dwordx4.
+// ---------------------------------------------------------------------------
+template <typename TS> struct Vec16;
+
+template <> struct Vec16<double> {
+    static constexpr int V = 2;
+    using st = double;
+    template <typename TC>
+    __device__ __forceinline__ static void load(const double *p, TC *o) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = (TC)v.x; o[1] = (TC)v.y;
+    }
+};
+
+template <> struct Vec16<float> {
+    static constexpr int V = 4;
+    using st = float;
+    template <typename TC>
+    __device__ __forceinline__ static void load(const float *p, TC *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = (TC)v.x; o[1] = (TC)v.y; o[2] = (TC)v.z; o[3] = (TC)v.w;
+    }
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+    _Float16 x;
+    uint16_t hh = (uint16_t)h;
+    __builtin_memcpy(&x, &hh, 2);
+    return (float)x;
+}
+
+template <> struct Vec16<bf16s> {
+    static constexpr int V = 8;
+    using st = uint16_t;
+    template <typename TC>
+    __device__ __forceinline__ static void load(const uint16_t *p, TC *o) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[2 * q] = (TC)bf16_to_f32(w[q] & 0xffffu);
+            o[2 * q + 1] = (TC)bf16_to_f32(w[q] >> 16);
+        }
+    }
+};
+
+template <> struct Vec16<f16s> {
+    static constexpr int V = 8;
+    using st = uint16_t;
+    template <typename TC>
+    __device__ __forceinline__ static void load(const uint16_t *p, TC *o) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[2 * q] = (TC)f16_to_f32(w[q] & 0xffffu);
+            o[2 * q + 1] = (TC)f16_to_f32(w[q] >> 16);
+        }
+    }
+};
+
+// FP32 -> BF16, round to nearest even, NaN kept quiet.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// FP32 -> FP16 (IEEE round to nearest even, hardware conversion).
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
+    _Float16 h = (_Float16)f;
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
+}
+
+// leading dimension and base pointers by storage type
+template <typename TS> __device__ __forceinline__ int ld_of(const SysDesc &d);
+template <> __device__ __forceinline__ int ld_of<double>(const SysDesc &d) { return d.ld; }
+template <> __device__ __forceinline__ int ld_of<float>(const SysDesc &d) { return d.ld32; }
+template <> __device__ __forceinline__ int ld_of<bf16s>(const SysDesc &d) { return d.ld16; }
+template <> __device__ __forceinline__ int ld_of<f16s>(const SysDesc &d) { return d.ld16; }
+
+template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *jac_of(const SysDesc &d);
+template <> __device__ __forceinline__ const double *jac_of<double>(const SysDesc &d) { return d.Jc; }
+template <> __device__ __forceinline__ const float *jac_of<float>(const SysDesc &d) { return d.Jc32; }
+template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *mass_of(const SysDesc &d);
+template <> __device__ __forceinline__ const double *mass_of<double>(const SysDesc &d) { return d.Mc; }
+template <> __device__ __forceinline__ const float *mass_of<float>(const SysDesc &d) { return d.Mc32; }
+
+template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *piv_of(const SysDesc &d);
+template <> __device__ __forceinline__ const double *piv_of<double>(const SysDesc &d) { return d.P64; }
+template <> __device__ __forceinline__ const float *piv_of<float>(const SysDesc &d) { return d.P32; }
+template <> __device__ __forceinline__ const uint16_t *piv_of<bf16s>(const SysDesc &d) { return d.P16; }
+template <> __device__ __forceinline__ const uint16_t *piv_of<f16s>(const SysDesc &d) { return d.P16; }
+template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *cross_of(const SysDesc &d);
+template <> __device__ __forceinline__ const double *cross_of<double>(const SysDesc &d) { return d.C64; }
+template <> __device__ __forceinline__ const float *cross_of<float>(const SysDesc &d) { return d.C32; }
+template <> __device__ __forceinline__ const uint16_t *cross_of<bf16s>(const SysDesc &d) { return d.C16; }
+template <> __device__ __forceinline__ const uint16_t *cross_of<f16s>(const SysDesc &d) { return d.C16; }
+
+// per-block scale of the FP16S format (1 for every other format)
+template <typename TS, typename TC>
+__device__ __forceinline__ TC block_scale(const int *e, long long blk) { return (TC)1; }
+template <>
+__device__ __forceinline__ float block_scale<f16s, float>(const int *e, long long blk) {
+    return ldexpf(1.0f, -e[blk]);
+}
+
+// ---------------------------------------------------------------------------
+// wave / workgroup reductions (fixed order, so results are deterministic)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace irk

@@ -1,0 +1,171 @@
+// irk_internal.h -- shared declarations of the gfx950 library (host + device).
+//
+// Device data of one system lives in a SysDesc in device memory.  Kernels that
+// work element by element (matvec rows, ILU levels, factor tasks) take the
+// SysDesc table plus a list of work items, so one launch can cover any number
+// of systems; vectors are addressed by slot (see Slot) so the launch arguments
+// stay small and graph-capturable.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace irk {
+
+constexpr int SMAX = 5;          // most stages handled
+constexpr int MMAX = 160;        // largest block size
+constexpr int RESTART_MAX = 64;  // largest Krylov dimension
+constexpr int NTHREADS = 256;    // threads per workgroup of the element kernels
+constexpr int RED_BLOCKS = 1024; // workgroups of the vector reduction kernels (max)
+
+enum Slot : int {
+    SL_V = 0,   // Krylov basis, index j selects v_j            (FP64)
+    SL_W,       // Arnoldi work vector                          (FP64)
+    SL_Z,       // preconditioned vector z = P^{-1} v          (compute type)
+    SL_YH,      // sweep scratch: y^ (forward), z (backward)    (compute type)
+    SL_R,       // residual                                     (FP64)
+    SL_X,       // solution / iterate                           (FP64)
+    SL_B,       // right-hand side                              (FP64)
+    SL_D,       // inner correction of the refinement loop      (FP64)
+    SL_U,       // combination V y at cycle end                 (FP64)
+    SL_EXT0,    // caller vectors for the kernel-level entry points
+    SL_EXT1,
+    NSLOT
+};
+
+enum FactorType : int { FT_F64 = 0, FT_F32 = 1, FT_BF16 = 2, FT_F16S = 3 };
+
+struct DevState {
+    double bnorm;      // ||b|| of the current GMRES solve
+    double beta;       // ||r0|| of the current cycle
+    double est;        // last |g_{j+1}|
+    double rnorm2;     // scratch for a norm reduction
+    int j;             // index of the last Arnoldi step done in the cycle (-1 none)
+    int done;          // cycle finished: converged estimate or breakdown
+    int breakdown;
+    int singular;      // 1 + element of the first singular pivot, 0 if none
+    int nonfinite;
+    int pad[3];
+    unsigned tickets[8];   // "last workgroup" counters of the reductions
+};
+
+struct SysDesc {
+    // shape
+    int s, T, m, nJ, nnzb;
+    int ld;        // leading dimension of FP64 blocks
+    int ld32;      // FP32 blocks
+    int ld16;      // 16-bit blocks
+    int maxrow;    // most blocks in one block row
+    int pc;        // irk_pc
+    int ftype;     // FactorType of the sweep factors
+    int restart;
+    long long N;   // s*T*m
+    double dt;
+    double Ainv[SMAX * SMAX];
+    double dcoef[SMAX];     // diagonal mass coefficient of each stage's pivot
+    // structure (device)
+    const int *row_ptr, *col_idx, *diag_pos, *tpos;
+    const int *lvl_fwd, *lvl_bwd;   // elements sorted by forward / backward level
+    // operator values
+    const double *Jc;  const double *Mc;      // col-major blocks, ld
+    const float *Jc32; const float *Mc32;     // col-major blocks, ld32
+    // factors: pivots [T][s] blocks, cross [T][s][s-1] blocks ("column k"
+    // group holds C_{lk}, l != k, in ascending l)
+    double *P64; double *C64;                 // ld
+    float *P32;  float *C32;                  // ld32
+    uint16_t *P16; uint16_t *C16;             // ld16
+    int *P16e; int *C16e;                     // per-block exponents (FP16S)
+    double *Fscr;                             // per-element factor scratch [T] blocks (ld)
+    // vectors
+    void *vec[NSLOT];
+    // Krylov state
+    double *H;       // [(restart+1) * restart], row-major, H[r*restart + c]
+    double *g;       // [restart+1]
+    double *cs, *sn; // [restart]
+    double *y;       // [restart]
+    double *hbuf;    // [2 * (restart+1)] h1 and h2 of CGS2
+    double *part;    // [RED_BLOCKS * (restart+2)] reduction partials
+    DevState *st;
+};
+
+// one workgroup's work: system, first task, task count, aux
+struct Item { int sys, first, count, aux; };
+
+// LDS elements (of the compute type) one team needs; host and device must agree.
+__host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
+// matvec: gather of (maxrow+1)*m columns for S stages, or the [G][S][ld] partials
+__host__ __device__ inline int matvec_region(int S, int m, int maxrow, int ld, int V, int team) {
+    const int G = team / (ld / V);
+    return imax(S * (maxrow + 1) * m, G * S * ld);
+}
+// sweep: gather / partials region, then y and u vectors [S][round_up(m, 8)]
+__host__ __device__ inline int sweep_region(int S, int m, int maxrow, int ldJ, int VJ, int ldF,
+                                            int VF, int team) {
+    const int GJ = team / (ldJ / VJ), GF = team / (ldF / VF);
+    const int r = imax(S * maxrow * m, imax(GJ * S * ldJ, GF * S * ldF));
+    return r + 2 * S * round_up(m, 8);
+}
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files; all enqueue on `stream`)
+// ---------------------------------------------------------------------------
+
+// src: row-major FP64 blocks; dst: col-major with leading dimension ld, in
+// the requested type (0 double, 1 float).  nblk blocks of m x m.
+void launch_relayout(const double *src, void *dst, int dst_type, long long nblk, int m,
+                     int ld, hipStream_t st);
+
+// y_slot = B x_slot   (mode 0)   or   y_slot = b_slot - B x_slot   (mode 1)
+// prec 0: FP64 (Jc, Mc); 1: FP32 copies (x read as compute type of slot).
+void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max,
+                   int prec, bool sharedJ, int x_slot, int y_slot, int b_slot, int mode,
+                   int tpw, size_t shmem, hipStream_t st);
+
+// One level of the forward sweep (L~ y = v, then y^ = P^{-1} y per element),
+// or of the backward sweep (z = y^ + P^{-1} (dt J_upper z - C z)).
+//   fp64: FP64 factors/values with double vectors; otherwise FP32 values
+//   and factors of type ftype with float vectors.
+//   v_slot: input of the forward sweep (FP64 vector, times *vscale if given);
+//   yh slot SL_YH; acc_slot >= 0 adds the backward result to that FP64 slot
+//   (x += z), out_slot >= 0 also stores z there (in the compute type).
+void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems,
+                  int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
+                  int v_slot, int v_index, int out_slot, int acc_slot, int tpw, size_t shmem,
+                  hipStream_t st);
+
+// Factorization of one level.  phase 0: tasks (stage k = aux, element) build
+// P_{k,i} (and invert it when !coupled; set up cross blocks of column k when
+// coupled).  phase 1 (coupled): tasks = elements, sequential stage rounds.
+void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems,
+                   bool coupled, bool sharedJ, size_t shmem, hipStream_t st);
+
+// Quantize the FP64 factors to ftype (FP32 / BF16 / FP16 scaled).
+void launch_quantize(const SysDesc *dsys, const SysDesc &hsys, int ftype, hipStream_t st);
+
+// ---- Krylov (single system, FP64) ----
+// pass 0: hbuf[0..j] = V^T w;  pass 1: w -= V h1, hbuf[R+1 ..] = V^T w
+void launch_cgs(int pass, const SysDesc *dsys, const SysDesc &hsys, int j, int nblk,
+                hipStream_t st);
+// pass 2: w -= V h2, ||w||; Hessenberg column j, Givens rotation, estimate,
+// flags (done when |g_{j+1}| <= tol_abs); then v_{j+1} = w / ||w||
+void launch_givens(const SysDesc *dsys, const SysDesc &hsys, int j, double tol_abs, int nblk,
+                   hipStream_t st);
+// y = H^{-1} g over nv steps, u = V y
+void launch_cycle_end_n(const SysDesc *dsys, int nv, int nblk, hipStream_t st);
+// ||slot||: which 0 -> st->bnorm; which 1 -> start of a cycle (beta, g, flags)
+void launch_norm(const SysDesc *dsys, const SysDesc &hsys, int slot, int which, int nblk,
+                 hipStream_t st);
+// start a cycle from the residual in src_slot: beta = ||r||, v_0 = r / beta
+void launch_start_cycle(const SysDesc *dsys, const SysDesc &hsys, int src_slot, int nblk,
+                        hipStream_t st);
+void launch_axpy(const SysDesc *dsys, const SysDesc &hsys, int dst_slot, int src_slot,
+                 int nblk, hipStream_t st);
+void launch_copy(const SysDesc *dsys, const SysDesc &hsys, int dst_slot, int src_slot,
+                 double scale, int nblk, hipStream_t st);
+void launch_fill_zero(double *p, long long n, hipStream_t st);
+// export FP64 factors to the caller's row-major stage-major layout
+void launch_export(const SysDesc &hsys, double *pinv, double *cross, hipStream_t st);
+void factor_set_lds_limit(size_t bytes);
+
+}  // namespace irk
