@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Benchmark: transformed Radau IIA linear solves per second on one MI355X.
+
+Workload (default): s = 3 Radau IIA on a periodic 64 x 64 quad mesh with
+randomly permuted elements, 64 x 64 blocks (DG p = 3, 4 components),
+5 blocks per row, shared Jacobian, FP64, stage-coupled block ILU(0),
+GMRES(30), relative true-residual tolerance 1e-10, dt = 0.1.  Synthetic
+values of the shape and distribution of the paper's DG Jacobians.
+
+One step = one full linear solve of the hot path with the operator already
+resident in HBM: operator ingest (block relayout), block ILU(0)
+factorization, and preconditioned GMRES to tolerance.  The level schedule
+is built once per sparsity pattern (setup) and reused, as within a Newton
+loop.
+
+Prints one JSON line.  Also reports the dominant kernel (the BSR
+multi-stage matvec) against the HBM roofline, from HIP events recorded
+around every matvec launch inside the timed region, and the CPU oracle's
+time on the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+
+def matvec_bytes(s, T, m, nnzb, nJ=1, w=8):
+    """Algorithmic bytes of one multi-stage matvec: every Jacobian block and
+    mass block once, the input and output stage vectors once, the BSR
+    indices once."""
+    return (nJ * nnzb * m * m * w + T * m * m * w + 2 * s * T * m * 8
+            + 4 * (T + 1) + 4 * nnzb)
+
+
+def sweep_bytes(s, T, m, nnzb, coupled, w=8):
+    """Algorithmic bytes of one preconditioner application (both sweeps):
+    off-diagonal Jacobian blocks once, every pivot inverse twice, the
+    cross-stage blocks twice (coupled), and four stage-vector passes."""
+    r_blocks = nnzb - T
+    cross = s * (s - 1) * T * m * m * w * 2 if coupled and s > 1 else 0
+    return r_blocks * m * m * w + 2 * s * T * m * m * w + cross + 4 * s * T * m * 8
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--pc", default="coupled", choices=["coupled", "uncoupled_shifted", "uncoupled"])
+    ap.add_argument("--dt", type=float, default=0.1)
+    ap.add_argument("--N", type=int, default=64, help="mesh side (64 = the full workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="no HIP events around kernels")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "multi-GPU sharding is a design note, not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import dgsynth
+    import paper_1701_07181_amd as irk
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    sy = dgsynth.config_system("cfg1", dt=args.dt, N=args.N)
+    print(f"# generated T={sy.T} m={sy.m} s={sy.s} nnzb={sy.nnzb} in {time.time()-t0:.1f}s",
+          file=sys.stderr, flush=True)
+    opts = irk.Options(pc=args.pc, rtol=1e-10, restart=30)
+    solver = irk.Solver(sy, opts)
+    Jd, Md = solver.J, solver.M
+    rhs = torch.as_tensor(sy.rhs).cuda()
+    stream = solver.stream
+
+    def step():
+        solver.update_values(Jd, Md, args.dt)
+        solver.factor()
+        x, info = solver.solve(rhs)
+        return info
+
+    for _ in range(args.warmup):
+        info = step()
+    torch.cuda.synchronize()
+    print(f"# warmup done: iters={info['iters']} rel_res={info['rel_res_true']:.2e}",
+          file=sys.stderr, flush=True)
+    if not args.no_profile:
+        solver.profile(True)
+    lat = []
+    infos = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step())
+        lat.append((time.perf_counter() - ts) * 1e3)
+        print(f"# step {k}: {lat[-1]:.2f} ms iters={infos[-1]['iters']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = solver.profile_read() if not args.no_profile else None
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = args.steps / elapsed
+
+    assert all(i["converged"] for i in infos), "a timed solve did not converge"
+    iters = [i["iters"] for i in infos]
+    res = max(i["rel_res_true"] for i in infos)
+
+    mv_bytes = matvec_bytes(sy.s, sy.T, sy.m, sy.nnzb)
+    roof = None
+    extra = {}
+    if prof and prof["matvec_count"]:
+        mv_ms = prof["matvec_ms"] / prof["matvec_count"]
+        ach = mv_bytes / (mv_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_matvec (BSR multi-stage matvec, FP64)",
+                "avg_launch_us": round(mv_ms * 1e3, 2), "launches": prof["matvec_count"],
+                "bytes_per_launch": mv_bytes}
+        if prof["pc_count"]:
+            pc_ms = prof["pc_ms"] / prof["pc_count"]
+            sb = sweep_bytes(sy.s, sy.T, sy.m, sy.nnzb, args.pc == "coupled")
+            extra["preconditioner_apply"] = {
+                "avg_us": round(pc_ms * 1e3, 1), "bytes": sb,
+                "achieved_GBs": round(sb / (pc_ms * 1e-3) / 1e9, 1),
+                "frac": round(sb / (pc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if prof["orth_count"]:
+            extra["arnoldi_avg_us"] = round(prof["orth_ms"] / prof["orth_count"] * 1e3, 1)
+        if prof["factor_count"]:
+            extra["factor_avg_ms"] = round(prof["factor_ms"] / prof["factor_count"], 3)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        A, _, _ = oracle.radau_iia(sy.s)
+        P = oracle.Problem(sy)
+        tc = time.perf_counter()
+        xo, io = oracle.solve(P, A, sy.rhs, pc=args.pc, rtol=1e-10, orth="cgs2")
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(1.0 / tcpu, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full solve of the same workload (factor + GMRES, {io['iters']} "
+                         f"iterations), plain FP64 C loops, single thread, {tcpu:.1f} s"}
+
+    out = {
+        "metric": "IRK solves/s at 1e-8 rel residual; BSR matvec GB/s vs HBM peak; p99 latency",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cfg1: s=3 Radau IIA, periodic {args.N}x{args.N} quad mesh "
+                               f"(T={sy.T}), m={sy.m}, shared J, FP64, {args.pc} block ILU(0), "
+                               f"GMRES(30), rtol 1e-10, dt={args.dt}",
+                   "s": sy.s, "T": sy.T, "m": sy.m, "nnzb": sy.nnzb, "pc": args.pc,
+                   "dt": args.dt, "rtol": 1e-10, "restart": 30},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "iters": {"min": min(iters), "max": max(iters)},
+        "equiv_mults": iters[0] * sy.s,
+        "rel_res_true_max": res,
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,25 @@ irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z);
  * slots left untouched; may be NULL). */
 irk_status irk_export_factors(irk_handle *h, double *pinv, double *cross);
 
+/* Kernel timing for benchmarks.  While enabled, the library records HIP
+ * events on the handle's stream around every operator launch (FP64 and
+ * FP32), every preconditioner application (all sweep levels of one apply),
+ * every Arnoldi orthogonalization (CGS2 + Givens) and every factorization.
+ * irk_profile_read waits for the stream, adds up the recorded intervals and
+ * clears them.  Up to 4096 intervals are kept between reads; later ones are
+ * counted in `dropped`. */
+typedef struct {
+    int matvec_count;  double matvec_ms;   /* FP64 operator launches            */
+    int matvec32_count; double matvec32_ms;/* FP32 operator launches            */
+    int pc_count;      double pc_ms;       /* preconditioner applications       */
+    int orth_count;    double orth_ms;     /* CGS2 + Givens steps               */
+    int factor_count;  double factor_ms;   /* factorizations (incl. quantize)   */
+    int dropped;
+} irk_profile_stats;
+
+irk_status irk_profile_enable(irk_handle *h, int on);
+irk_status irk_profile_read(irk_handle *h, irk_profile_stats *out);
+
 /* Element of the last singular pivot, or -1. */
 int irk_last_bad_element(const irk_handle *h);
 

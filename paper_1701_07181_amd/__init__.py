@@ -56,6 +56,15 @@ class _Info(C.Structure):
                 ("ms_solve", C.c_float)]
 
 
+class _Prof(C.Structure):
+    _fields_ = [("matvec_count", C.c_int), ("matvec_ms", C.c_double),
+                ("matvec32_count", C.c_int), ("matvec32_ms", C.c_double),
+                ("pc_count", C.c_int), ("pc_ms", C.c_double),
+                ("orth_count", C.c_int), ("orth_ms", C.c_double),
+                ("factor_count", C.c_int), ("factor_ms", C.c_double),
+                ("dropped", C.c_int)]
+
+
 _vp = C.c_void_p
 _L.irk_status_str.restype = C.c_char_p
 _L.irk_status_str.argtypes = [C.c_int]
@@ -72,11 +81,14 @@ _L.irk_export_factors.argtypes = [_vp, _vp, _vp]
 _L.irk_last_bad_element.argtypes = [_vp]
 _L.irk_destroy.argtypes = [_vp]
 _L.irk_radau_iia.argtypes = [C.c_int, _vp, _vp, _vp]
+_L.irk_profile_enable.argtypes = [_vp, C.c_int]
+_L.irk_profile_read.argtypes = [_vp, C.POINTER(_Prof)]
 
 EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_update_values",
             "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
             "irk_apply_preconditioner", "irk_export_factors", "irk_last_bad_element",
-            "irk_destroy", "irk_status_str", "irk_radau_iia"]
+            "irk_destroy", "irk_status_str", "irk_radau_iia", "irk_profile_enable",
+            "irk_profile_read"]
 
 
 def _check(st: int, where: str):
@@ -245,6 +257,16 @@ class Solver:
         _check(_L.irk_apply_preconditioner(self._h, vv.data_ptr(), z.data_ptr()),
                "irk_apply_preconditioner")
         return z
+
+    def profile(self, on: bool = True):
+        """Turn HIP-event kernel timing on or off (clears recorded intervals)."""
+        _check(_L.irk_profile_enable(self._h, 1 if on else 0), "irk_profile_enable")
+
+    def profile_read(self) -> dict:
+        """Totals since the last read: counts and milliseconds per kernel class."""
+        p = _Prof()
+        _check(_L.irk_profile_read(self._h, C.byref(p)), "irk_profile_read")
+        return {f: getattr(p, f) for f, _ in _Prof._fields_}
 
     def export_factors(self, cross: bool = False):
         with torch.cuda.stream(self.stream):

@@ -310,7 +310,32 @@ struct irk_handle {
     int bad_element;
     float ms_factor;
     hipEvent_t ev0, ev1;
+    // profiling: event pool and recorded intervals (kind, event index)
+    bool prof;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, int>> spans;
+    int dropped;
 };
+
+namespace {
+enum ProfKind { PK_MV64 = 0, PK_MV32, PK_PC, PK_ORTH, PK_FACTOR, PK_N };
+
+// Start an interval; returns its pool index or -1.
+int prof_begin(irk_handle *h)
+{
+    if (!h->prof) return -1;
+    const int idx = 2 * (int)h->spans.size();
+    if (idx + 1 >= (int)h->pool.size()) { h->dropped++; return -1; }
+    hipEventRecord(h->pool[idx], h->stream);
+    return idx;
+}
+void prof_end(irk_handle *h, int idx, int kind)
+{
+    if (idx < 0) return;
+    hipEventRecord(h->pool[idx + 1], h->stream);
+    h->spans.push_back({kind, idx});
+}
+}  // namespace
 
 namespace {
 
@@ -337,6 +362,7 @@ irk_status sync_state(irk_handle *h)
 // z = P^{-1} v into SL_YH; acc_slot >= 0 also adds it to that FP64 slot
 void enqueue_pc(irk_handle *h, bool fp64, int v_slot, int v_index, int acc_slot)
 {
+    const int pi = prof_begin(h);
     const std::vector<Launch> &F = fp64 ? h->fwd64 : h->fwd32;
     const std::vector<Launch> &B = fp64 ? h->bwd64 : h->bwd32;
     const size_t shm = fp64 ? h->shm_sw64 : h->shm_sw32;
@@ -347,13 +373,16 @@ void enqueue_pc(irk_handle *h, bool fp64, int v_slot, int v_index, int acc_slot)
     for (const Launch &L : B)
         launch_sweep(false, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
                      v_slot, v_index, -1, acc_slot, 0, shm, h->stream);
+    prof_end(h, pi, PK_PC);
 }
 
 void enqueue_matvec(irk_handle *h, bool fp64, int x_slot, int y_slot, int b_slot, int mode)
 {
     const Launch &L = fp64 ? h->mv64 : h->mv32;
+    const int pi = prof_begin(h);
     launch_matvec(h->dsys, h->ditems + L.off, L.n, h->s, fp64 ? 0 : 1, h->sharedJ, x_slot, y_slot,
                   b_slot, mode, 0, fp64 ? h->shm_mv64 : h->shm_mv32, h->stream);
+    prof_end(h, pi, fp64 ? PK_MV64 : PK_MV32);
 }
 
 }  // namespace
@@ -659,6 +688,7 @@ irk_status irk_factor_ilu(irk_handle *h)
     std::memset(h->hst->tickets, 0, sizeof(h->hst->tickets));
     HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
     hipEventRecord(h->ev0, h->stream);
+    const int pf = prof_begin(h);
     for (size_t l = 0; l < h->fa.size(); ++l) {
         if (h->fa[l].n)
             launch_factor(0, h->dsys, h->ditems + h->fa[l].off, h->fa[l].n, h->coupled, h->sharedJ,
@@ -668,6 +698,7 @@ irk_status irk_factor_ilu(irk_handle *h)
                           h->shm_fac, h->stream);
     }
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
+    prof_end(h, pf, PK_FACTOR);
     hipEventRecord(h->ev1, h->stream);
     HIPCHK(hipGetLastError());
     irk_status st = sync_state(h);
@@ -780,9 +811,11 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
                                           hipMemcpyDeviceToDevice, h->stream));
                     enqueue_matvec(h, true, SL_YH, SL_W, -1, 0);
                 }
+                const int po = prof_begin(h);
                 launch_cgs(0, h->dsys, d, j, h->nblk, h->stream);
                 launch_cgs(1, h->dsys, d, j, h->nblk, h->stream);
                 launch_givens(h->dsys, d, j, tol_abs, h->nblk, h->stream);
+                prof_end(h, po, PK_ORTH);
                 ++iters;
                 st = sync_state(h);
                 if (st != IRK_OK) return st;
@@ -837,9 +870,46 @@ irk_status irk_solve_batched(irk_handle *const *h, const double *const *rhs, dou
     return worst;
 }
 
+irk_status irk_profile_enable(irk_handle *h, int on)
+{
+    if (!h) return IRK_ERR_ARG;
+    if (on && h->pool.empty()) {
+        h->pool.resize(8192);
+        for (auto &e : h->pool)
+            if (hipEventCreate(&e) != hipSuccess) return IRK_ERR_DEVICE;
+    }
+    h->prof = on != 0;
+    h->spans.clear();
+    h->dropped = 0;
+    return IRK_OK;
+}
+
+irk_status irk_profile_read(irk_handle *h, irk_profile_stats *out)
+{
+    if (!h || !out) return IRK_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (const auto &sp : h->spans) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->pool[sp.second], h->pool[sp.second + 1]) != hipSuccess) continue;
+        switch (sp.first) {
+        case PK_MV64: out->matvec_count++; out->matvec_ms += ms; break;
+        case PK_MV32: out->matvec32_count++; out->matvec32_ms += ms; break;
+        case PK_PC: out->pc_count++; out->pc_ms += ms; break;
+        case PK_ORTH: out->orth_count++; out->orth_ms += ms; break;
+        default: out->factor_count++; out->factor_ms += ms; break;
+        }
+    }
+    out->dropped = h->dropped;
+    h->spans.clear();
+    h->dropped = 0;
+    return IRK_OK;
+}
+
 irk_status irk_destroy(irk_handle *h)
 {
     if (!h) return IRK_ERR_ARG;
+    for (auto &e : h->pool) hipEventDestroy(e);
     if (h->hst) hipHostFree(h->hst);
     hipEventDestroy(h->ev0);
     hipEventDestroy(h->ev1);
