@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -211,8 +212,8 @@ int pick_tpw(int ld, int V)
 
 struct Plan {
     size_t o_dsys, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
-        o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y, o_hbuf,
-        o_part, total;
+        o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_flags, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
+        o_hbuf, o_part, total;
     int ld, ld32, ld16, nitems_max;
 };
 
@@ -246,6 +247,7 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
         P.o_P64 = take(sizeof(double) * (size_t)nblkP * m * P.ld);
         if (coupled) P.o_C64 = take(sizeof(double) * (size_t)nblkC * m * P.ld);
         P.o_Fscr = take(sizeof(double) * (size_t)nblkP * m * P.ld);
+        P.o_flags = take(sizeof(unsigned) * (size_t)T);
         if (mixed && ft == FT_F32) {
             P.o_P32 = take(sizeof(float) * (size_t)nblkP * m * P.ld32);
             if (coupled) P.o_C32 = take(sizeof(float) * (size_t)nblkC * m * P.ld32);
@@ -303,6 +305,9 @@ struct irk_handle {
     std::vector<int> ints;
     Launch mv64, mv32;
     std::vector<Launch> fwd64, bwd64, fwd32, bwd32, fa, fb;
+    bool persist;      // one persistent launch per sweep instead of one per level
+    int pgrid;         // workgroups of a persistent sweep
+    unsigned epoch;    // flag value of the current persistent sweep
     size_t shm_mv64, shm_mv32, shm_sw64, shm_sw32, shm_fac;
     bool mixed, coupled, sharedJ, factored;
     int ftype;
@@ -367,12 +372,24 @@ void enqueue_pc(irk_handle *h, bool fp64, int v_slot, int v_index, int acc_slot)
     const std::vector<Launch> &B = fp64 ? h->bwd64 : h->bwd32;
     const size_t shm = fp64 ? h->shm_sw64 : h->shm_sw32;
     const int ft = fp64 ? FT_F64 : h->ftype;
-    for (const Launch &L : F)
-        launch_sweep(true, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
-                     v_slot, v_index, -1, -1, 0, shm, h->stream);
-    for (const Launch &L : B)
-        launch_sweep(false, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
-                     v_slot, v_index, -1, acc_slot, 0, shm, h->stream);
+    if (h->persist) {
+        const int nf = F.back().off + F.back().n - F.front().off;
+        const int nb = B.back().off + B.back().n - B.front().off;
+        ++h->epoch;
+        launch_sweep(true, h->dsys, h->ditems + F.front().off, nf, h->s, fp64, ft, h->coupled,
+                     h->sharedJ, v_slot, v_index, -1, shm, h->stream, std::min(nf, h->pgrid), h->epoch);
+        ++h->epoch;
+        launch_sweep(false, h->dsys, h->ditems + B.front().off, nb, h->s, fp64, ft, h->coupled,
+                     h->sharedJ, v_slot, v_index, acc_slot, shm, h->stream, std::min(nb, h->pgrid),
+                     h->epoch);
+    } else {
+        for (const Launch &L : F)
+            launch_sweep(true, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
+                         v_slot, v_index, -1, shm, h->stream, 0, 0u);
+        for (const Launch &L : B)
+            launch_sweep(false, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
+                         v_slot, v_index, acc_slot, shm, h->stream, 0, 0u);
+    }
     prof_end(h, pi, PK_PC);
 }
 
@@ -567,7 +584,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     }
     {
         const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
-        const size_t gm = sizeof(double) * 2 * 16 * 64;
+        const size_t gm = sizeof(double) * 2 * 64 * 64;
         h->shm_fac = std::max(gj, gm);
     }
     if (h->shm_fac > 160 * 1024 || h->shm_mv64 > 160 * 1024 || h->shm_sw64 > 160 * 1024 ||
@@ -576,6 +593,17 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         return IRK_ERR_ARG;
     }
     factor_set_lds_limit(h->shm_fac);
+    {
+        // sweep mode: one launch per level (default) or one persistent
+        // dependency-driven launch per sweep (IRK_SWEEP_PERSIST=1)
+        const char *e = std::getenv("IRK_SWEEP_PERSIST");
+        h->persist = (e && e[0] == '1');
+        int dev = 0, ncu = 256;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        h->pgrid = std::max(1, ncu) * 4;
+        h->epoch = 0;
+    }
 
     // ---- device pointers ----
     char *ws = h->ws;
@@ -607,6 +635,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         d.P64 = (double *)(ws + P.o_P64);
         d.Fscr = (double *)(ws + P.o_Fscr);
         if (h->coupled) d.C64 = (double *)(ws + P.o_C64);
+        d.dep_flags = (unsigned *)(ws + P.o_flags);
         if (P.o_P32) d.P32 = (float *)(ws + P.o_P32);
         if (P.o_C32) d.C32 = (float *)(ws + P.o_C32);
         if (P.o_P16) { d.P16 = (uint16_t *)(ws + P.o_P16); d.P16e = (int *)(ws + P.o_P16e); }
@@ -627,7 +656,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     {
         const long long N = d.N;
         long long nb = (N + NTHREADS * 4 - 1) / (NTHREADS * 4);
-        h->nblk = (int)std::max(1LL, std::min<long long>(nb, RED_BLOCKS));
+        h->nblk = (int)std::max(1LL, std::min<long long>(nb, 512));
     }
 
     // ---- uploads ----
@@ -650,6 +679,8 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     ok &= hipMemcpyAsync(h->ditems, h->items.data(), sizeof(Item) * h->items.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (o->pc != IRK_PC_NONE)
+        ok &= hipMemsetAsync(ws + P.o_flags, 0, sizeof(unsigned) * (size_t)T, stream) == hipSuccess;
     if (!ok) { irk_destroy(h); return IRK_ERR_DEVICE; }
     *out = h;
     st = irk_update_values(h, p->J, p->M, p->dt);
@@ -826,6 +857,7 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
                 if (h->hst->done || iters >= o.max_iters) break;
             }
             if (h->hst->nonfinite) { result = IRK_ERR_NONFINITE; break; }
+            if (h->hst->spin_timeout) { result = IRK_ERR_DEVICE; break; }
             // x += P^{-1} V y
             launch_cycle_end_n(h->dsys, jl + 1, h->nblk, h->stream);
             if (has_pc) enqueue_pc(h, fp64, SL_U, 0, SL_X);

@@ -4,6 +4,17 @@
 
 namespace irk {
 
+// Global address space.  Pointers taken from the device-side descriptor are
+// generic; casting them lets the compiler emit global_* (not flat_*) memory
+// instructions, which do not share the LDS wait counter.
+#define GAS __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GAS T *gp(T *p) { return (GAS T *)(p); }
+
+// Native vector types (plain clang vectors load from any address space).
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // Storage tags for the 16-bit factor formats.
 struct bf16s { uint16_t u; };
 struct f16s { uint16_t u; };
@@ -19,8 +30,8 @@ template <> struct Vec16<double> {
     static constexpr int V = 2;
     using st = double;
     template <typename TC>
-    __device__ __forceinline__ static void load(const double *p, TC *o) {
-        const double2 v = *reinterpret_cast<const double2 *>(p);
+    __device__ __forceinline__ static void load(const GAS double *p, TC *o) {
+        const dbl2 v = *reinterpret_cast<const GAS dbl2 *>(p);
         o[0] = (TC)v.x; o[1] = (TC)v.y;
     }
 };
@@ -29,8 +40,8 @@ template <> struct Vec16<float> {
     static constexpr int V = 4;
     using st = float;
     template <typename TC>
-    __device__ __forceinline__ static void load(const float *p, TC *o) {
-        const float4 v = *reinterpret_cast<const float4 *>(p);
+    __device__ __forceinline__ static void load(const GAS float *p, TC *o) {
+        const flt4 v = *reinterpret_cast<const GAS flt4 *>(p);
         o[0] = (TC)v.x; o[1] = (TC)v.y; o[2] = (TC)v.z; o[3] = (TC)v.w;
     }
 };
@@ -47,8 +58,8 @@ template <> struct Vec16<bf16s> {
     static constexpr int V = 8;
     using st = uint16_t;
     template <typename TC>
-    __device__ __forceinline__ static void load(const uint16_t *p, TC *o) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    __device__ __forceinline__ static void load(const GAS uint16_t *p, TC *o) {
+        const u32x4 v = *reinterpret_cast<const GAS u32x4 *>(p);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -62,8 +73,8 @@ template <> struct Vec16<f16s> {
     static constexpr int V = 8;
     using st = uint16_t;
     template <typename TC>
-    __device__ __forceinline__ static void load(const uint16_t *p, TC *o) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    __device__ __forceinline__ static void load(const GAS uint16_t *p, TC *o) {
+        const u32x4 v = *reinterpret_cast<const GAS u32x4 *>(p);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -96,30 +107,30 @@ template <> __device__ __forceinline__ int ld_of<float>(const SysDesc &d) { retu
 template <> __device__ __forceinline__ int ld_of<bf16s>(const SysDesc &d) { return d.ld16; }
 template <> __device__ __forceinline__ int ld_of<f16s>(const SysDesc &d) { return d.ld16; }
 
-template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *jac_of(const SysDesc &d);
-template <> __device__ __forceinline__ const double *jac_of<double>(const SysDesc &d) { return d.Jc; }
-template <> __device__ __forceinline__ const float *jac_of<float>(const SysDesc &d) { return d.Jc32; }
-template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *mass_of(const SysDesc &d);
-template <> __device__ __forceinline__ const double *mass_of<double>(const SysDesc &d) { return d.Mc; }
-template <> __device__ __forceinline__ const float *mass_of<float>(const SysDesc &d) { return d.Mc32; }
+template <typename TS> __device__ __forceinline__ const GAS typename Vec16<TS>::st *jac_of(const SysDesc &d);
+template <> __device__ __forceinline__ const GAS double *jac_of<double>(const SysDesc &d) { return gp((const double *)d.Jc); }
+template <> __device__ __forceinline__ const GAS float *jac_of<float>(const SysDesc &d) { return gp((const float *)d.Jc32); }
+template <typename TS> __device__ __forceinline__ const GAS typename Vec16<TS>::st *mass_of(const SysDesc &d);
+template <> __device__ __forceinline__ const GAS double *mass_of<double>(const SysDesc &d) { return gp((const double *)d.Mc); }
+template <> __device__ __forceinline__ const GAS float *mass_of<float>(const SysDesc &d) { return gp((const float *)d.Mc32); }
 
-template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *piv_of(const SysDesc &d);
-template <> __device__ __forceinline__ const double *piv_of<double>(const SysDesc &d) { return d.P64; }
-template <> __device__ __forceinline__ const float *piv_of<float>(const SysDesc &d) { return d.P32; }
-template <> __device__ __forceinline__ const uint16_t *piv_of<bf16s>(const SysDesc &d) { return d.P16; }
-template <> __device__ __forceinline__ const uint16_t *piv_of<f16s>(const SysDesc &d) { return d.P16; }
-template <typename TS> __device__ __forceinline__ const typename Vec16<TS>::st *cross_of(const SysDesc &d);
-template <> __device__ __forceinline__ const double *cross_of<double>(const SysDesc &d) { return d.C64; }
-template <> __device__ __forceinline__ const float *cross_of<float>(const SysDesc &d) { return d.C32; }
-template <> __device__ __forceinline__ const uint16_t *cross_of<bf16s>(const SysDesc &d) { return d.C16; }
-template <> __device__ __forceinline__ const uint16_t *cross_of<f16s>(const SysDesc &d) { return d.C16; }
+template <typename TS> __device__ __forceinline__ const GAS typename Vec16<TS>::st *piv_of(const SysDesc &d);
+template <> __device__ __forceinline__ const GAS double *piv_of<double>(const SysDesc &d) { return gp((const double *)d.P64); }
+template <> __device__ __forceinline__ const GAS float *piv_of<float>(const SysDesc &d) { return gp((const float *)d.P32); }
+template <> __device__ __forceinline__ const GAS uint16_t *piv_of<bf16s>(const SysDesc &d) { return gp((const uint16_t *)d.P16); }
+template <> __device__ __forceinline__ const GAS uint16_t *piv_of<f16s>(const SysDesc &d) { return gp((const uint16_t *)d.P16); }
+template <typename TS> __device__ __forceinline__ const GAS typename Vec16<TS>::st *cross_of(const SysDesc &d);
+template <> __device__ __forceinline__ const GAS double *cross_of<double>(const SysDesc &d) { return gp((const double *)d.C64); }
+template <> __device__ __forceinline__ const GAS float *cross_of<float>(const SysDesc &d) { return gp((const float *)d.C32); }
+template <> __device__ __forceinline__ const GAS uint16_t *cross_of<bf16s>(const SysDesc &d) { return gp((const uint16_t *)d.C16); }
+template <> __device__ __forceinline__ const GAS uint16_t *cross_of<f16s>(const SysDesc &d) { return gp((const uint16_t *)d.C16); }
 
 // per-block scale of the FP16S format (1 for every other format)
 template <typename TS, typename TC>
 __device__ __forceinline__ TC block_scale(const int *e, long long blk) { return (TC)1; }
 template <>
 __device__ __forceinline__ float block_scale<f16s, float>(const int *e, long long blk) {
-    return ldexpf(1.0f, -e[blk]);
+    return ldexpf(1.0f, -gp(e)[blk]);
 }
 
 // ---------------------------------------------------------------------------

@@ -45,7 +45,8 @@ struct DevState {
     int breakdown;
     int singular;      // 1 + element of the first singular pivot, 0 if none
     int nonfinite;
-    int pad[3];
+    int spin_timeout;   // a persistent sweep gave up waiting on a dependency
+    int pad[2];
     unsigned tickets[8];   // "last workgroup" counters of the reductions
 };
 
@@ -75,7 +76,8 @@ struct SysDesc {
     float *P32;  float *C32;                  // ld32
     uint16_t *P16; uint16_t *C16;             // ld16
     int *P16e; int *C16e;                     // per-block exponents (FP16S)
-    double *Fscr;                             // per-element factor scratch [T] blocks (ld)
+    double *Fscr;                             // per-element factor scratch [T][s] blocks (ld)
+    unsigned *dep_flags;                      // [T] completion flags of the persistent sweeps
     // vectors
     void *vec[NSLOT];
     // Krylov state
@@ -129,10 +131,13 @@ void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max
 //   v_slot: input of the forward sweep (FP64 vector, times *vscale if given);
 //   yh slot SL_YH; acc_slot >= 0 adds the backward result to that FP64 slot
 //   (x += z), out_slot >= 0 also stores z there (in the compute type).
+//   pgrid > 0: one persistent launch of pgrid workgroups covers all levels
+//   (items of every level, in level order), synchronized by per-element
+//   flags that carry `epoch`; pgrid == 0: items of one level, one workgroup each.
 void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                   int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
-                  int v_slot, int v_index, int out_slot, int acc_slot, int tpw, size_t shmem,
-                  hipStream_t st);
+                  int v_slot, int v_index, int acc_slot, size_t shmem, hipStream_t st,
+                  int pgrid, unsigned epoch);
 
 // Factorization of one level.  phase 0: tasks (stage k = aux, element) build
 // P_{k,i} (and invert it when !coupled; set up cross blocks of column k when

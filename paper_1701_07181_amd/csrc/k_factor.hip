@@ -28,18 +28,80 @@ namespace irk {
 
 // ---------------------------------------------------------------------------
 // C = (acc ? C : 0) + alpha * A * B for m x m column-major blocks (leading
-// dimension ld), computed by the whole workgroup: 64 x 64 output tiles, K
-// panels of 16 staged in LDS, 4 x 4 register tile per thread.
+// dimension ld), computed by the whole workgroup with a 4 x 4 register tile
+// per thread (16 x 16 threads cover a 64 x 64 output tile).
+//   m <= 64: both operands are staged in LDS at once (one round of loads in
+//            flight, no panel barriers);
+//   m >  64: 64 x 64 output tiles, K panels of 16, the next panel prefetched
+//            into registers while the current one is multiplied.
+// LDS: 2 * 64 * 64 doubles.
 // ---------------------------------------------------------------------------
 constexpr int GT = 64, GK = 16;
 
-__device__ void wg_gemm(int m, int ld, double alpha, const double *__restrict__ A,
-                        const double *__restrict__ B, bool acc, double *C, double *lds)
+__device__ __forceinline__ void tile_fma(const double *As, const double *Bs, int kn, int tx, int ty,
+                                         double (&c)[4][4])
 {
-    double *As = lds;               // [GK][GT]
-    double *Bs = lds + GK * GT;     // [GK][GT]
+#pragma unroll 4
+    for (int kk = 0; kk < kn; ++kk) {
+        const double2 a01 = *reinterpret_cast<const double2 *>(&As[kk * GT + tx * 4]);
+        const double2 a23 = *reinterpret_cast<const double2 *>(&As[kk * GT + tx * 4 + 2]);
+        const double2 b01 = *reinterpret_cast<const double2 *>(&Bs[kk * GT + ty * 4]);
+        const double2 b23 = *reinterpret_cast<const double2 *>(&Bs[kk * GT + ty * 4 + 2]);
+        const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c[a][b] += av[a] * bv[b];
+    }
+}
+
+__device__ __forceinline__ void tile_store(int m, int ld, double alpha, bool acc, GAS double *C, int i0,
+                                           int j0, int tx, int ty, const double (&c)[4][4])
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int gj = j0 + ty * 4 + b;
+        if (gj >= m) continue;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int gi = i0 + tx * 4 + a;
+            if (gi >= m) continue;
+            GAS double *cp = C + (size_t)gj * ld + gi;
+            *cp = (acc ? *cp : 0.0) + alpha * c[a][b];
+        }
+    }
+}
+
+__device__ __forceinline__ void wg_gemm(int m, int ld, double alpha, const double *__restrict__ Ap,
+                        const double *__restrict__ Bp, bool acc, double *Cp, double *lds)
+{
+    const GAS double *A = gp(Ap);
+    const GAS double *B = gp(Bp);
+    GAS double *C = gp(Cp);
+    double *As = lds;               // [k][64]
+    double *Bs = lds + GT * GT;     // [k][64]
     const int t = threadIdx.x;
     const int tx = t & 15, ty = t >> 4;
+    if (m <= GT) {
+        // whole operands: As[k][i] = A(i,k), Bs[k][j] = B(k,j)
+        for (int e = t; e < GT * GT; e += NTHREADS) {
+            const int i = e & 63, k = e >> 6;
+            As[k * GT + i] = (i < m && k < m) ? A[(size_t)k * ld + i] : 0.0;
+            const int kb = e & 63, j = e >> 6;
+            Bs[kb * GT + j] = (kb < m && j < m) ? B[(size_t)j * ld + kb] : 0.0;
+        }
+        __syncthreads();
+        double c[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
+        tile_fma(As, Bs, m, tx, ty, c);
+        tile_store(m, ld, alpha, acc, C, 0, 0, tx, ty, c);
+        __syncthreads();
+        return;
+    }
     for (int i0 = 0; i0 < m; i0 += GT) {
         for (int j0 = 0; j0 < m; j0 += GT) {
             double c[4][4];
@@ -47,45 +109,33 @@ __device__ void wg_gemm(int m, int ld, double alpha, const double *__restrict__ 
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
-            for (int k0 = 0; k0 < m; k0 += GK) {
+            double ra[4], rb[4];
+            auto load_panel = [&](int k0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int e = t + q * NTHREADS;         // 0..1023
-                    const int ii = e & 63, kk = e >> 6;     // A tile: row ii, k kk
+                    const int ii = e & 63, kk = e >> 6;
                     const int gi = i0 + ii, gk = k0 + kk;
-                    As[kk * GT + ii] = (gi < m && gk < m) ? A[(size_t)gk * ld + gi] : 0.0;
-                    const int kb = e & 15, jj = e >> 4;     // B tile: k kb, col jj
+                    ra[q] = (gi < m && gk < m) ? A[(size_t)gk * ld + gi] : 0.0;
+                    const int kb = e & 15, jj = e >> 4;
                     const int gkb = k0 + kb, gj = j0 + jj;
-                    Bs[kb * GT + jj] = (gkb < m && gj < m) ? B[(size_t)gj * ld + gkb] : 0.0;
+                    rb[q] = (gkb < m && gj < m) ? B[(size_t)gj * ld + gkb] : 0.0;
+                }
+            };
+            load_panel(0);
+            for (int k0 = 0; k0 < m; k0 += GK) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = t + q * NTHREADS;
+                    As[(e >> 6) * GT + (e & 63)] = ra[q];
+                    Bs[(e & 15) * GT + (e >> 4)] = rb[q];
                 }
                 __syncthreads();
-#pragma unroll
-                for (int kk = 0; kk < GK; ++kk) {
-                    const double2 a01 = *reinterpret_cast<const double2 *>(&As[kk * GT + tx * 4]);
-                    const double2 a23 = *reinterpret_cast<const double2 *>(&As[kk * GT + tx * 4 + 2]);
-                    const double2 b01 = *reinterpret_cast<const double2 *>(&Bs[kk * GT + ty * 4]);
-                    const double2 b23 = *reinterpret_cast<const double2 *>(&Bs[kk * GT + ty * 4 + 2]);
-                    const double av[4] = {a01.x, a01.y, a23.x, a23.y};
-                    const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) c[a][b] += av[a] * bv[b];
-                }
+                if (k0 + GK < m) load_panel(k0 + GK);
+                tile_fma(As, Bs, GK, tx, ty, c);
                 __syncthreads();
             }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int gj = j0 + ty * 4 + b;
-                if (gj >= m) continue;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int gi = i0 + tx * 4 + a;
-                    if (gi >= m) continue;
-                    double *cp = C + (size_t)gj * ld + gi;
-                    *cp = (acc ? *cp : 0.0) + alpha * c[a][b];
-                }
-            }
+            tile_store(m, ld, alpha, acc, C, i0, j0, tx, ty, c);
         }
     }
     __syncthreads();
@@ -98,18 +148,19 @@ __device__ void wg_gemm(int m, int ld, double alpha, const double *__restrict__ 
 // the same way leaves P^{-1} in column-major order.  Returns nonzero (in
 // every thread) if a pivot column is zero or not finite.
 // ---------------------------------------------------------------------------
-__device__ int wg_invert(double *g, int m, int ld, double *lds)
+__device__ __forceinline__ int wg_invert(double *gptr, int m, int ld, double *lds)
 {
+    GAS double *g = gp(gptr);
     const int lda = m + 1;
     double *a = lds;                              // [m][lda]
     double *colc = a + m * lda;                   // [m]
     int *perm = reinterpret_cast<int *>(colc + m);   // [m]
     int *sh = perm + m;                           // [2]: pivot row, bad flag
     const int t = threadIdx.x;
-    for (int e = t; e < m * m; e += NTHREADS) {
-        const int r = e / m, c = e - r * m;
-        a[r * lda + c] = g[(size_t)r * ld + c];
-    }
+    // 2D mapping: thread owns column tc (+64, +128) and rows tr, tr+4, ...
+    const int tc = t & 63, tr = t >> 6;
+    for (int c0 = tc; c0 < m; c0 += 64)
+        for (int r = tr; r < m; r += NTHREADS / 64) a[r * lda + c0] = g[(size_t)r * ld + c0];
     if (t == 0) sh[1] = 0;
     __syncthreads();
     for (int c = 0; c < m; ++c) {
@@ -134,43 +185,182 @@ __device__ int wg_invert(double *g, int m, int ld, double *lds)
         }
         __syncthreads();
         const int p = sh[0];
-        if (p != c)
+        if (p != c) {
             for (int j = t; j < m; j += NTHREADS) {
                 const double tmp = a[c * lda + j];
                 a[c * lda + j] = a[p * lda + j];
                 a[p * lda + j] = tmp;
             }
-        __syncthreads();
+            __syncthreads();
+        }
         const double pinv = 1.0 / a[c * lda + c];
+        // pivot row scaled; every thread keeps the entries of its columns
+        // (read before the barrier: row c is rewritten after it)
+        double prow[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int j = tc + 64 * q;
+            prow[q] = (j < m) ? ((j == c) ? pinv : a[c * lda + j] * pinv) : 0.0;
+        }
         for (int r = t; r < m; r += NTHREADS) colc[r] = a[r * lda + c];
         __syncthreads();
-        for (int j = t; j < m; j += NTHREADS) a[c * lda + j] = (j == c) ? pinv : a[c * lda + j] * pinv;
-        __syncthreads();
-        for (int e = t; e < m * m; e += NTHREADS) {
-            const int r = e / m, j = e - r * m;
-            if (r == c) continue;
+        for (int r = tr; r < m; r += NTHREADS / 64) {
             const double f = colc[r];
-            a[r * lda + j] = (j == c) ? -f * pinv : a[r * lda + j] - f * a[c * lda + j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int j = tc + 64 * q;
+                if (j >= m) continue;
+                double v;
+                if (r == c) v = prow[q];
+                else if (j == c) v = -f * pinv;
+                else v = a[r * lda + j] - f * prow[q];
+                a[r * lda + j] = v;
+            }
         }
         __syncthreads();
     }
     for (int c = m - 1; c >= 0; --c) {
         const int p = perm[c];
-        if (p != c)
+        if (p != c) {
             for (int r = t; r < m; r += NTHREADS) {
                 const double tmp = a[r * lda + c];
                 a[r * lda + c] = a[r * lda + p];
                 a[r * lda + p] = tmp;
             }
-        __syncthreads();
+            __syncthreads();
+        }
     }
-    for (int e = t; e < m * m; e += NTHREADS) {
-        const int r = e / m, c = e - r * m;
-        g[(size_t)r * ld + c] = a[r * lda + c];
-    }
+    for (int c0 = tc; c0 < m; c0 += 64)
+        for (int r = tr; r < m; r += NTHREADS / 64) g[(size_t)r * ld + c0] = a[r * lda + c0];
     const int bad = sh[1];
     __syncthreads();
     return bad;
+}
+
+// ---------------------------------------------------------------------------
+// Register-tiled Gauss-Jordan for m <= 64 on the augmented matrix [Q | I]
+// (Q = memory image of the block, as above), with implicit partial
+// pivoting: at step c the pivot is the unused row p with the largest
+// |Q(p, c)|; row p is scaled and column c is eliminated from every other
+// row.  The left half ends as a permutation Pi (Pi e_c = e_{p_c}) and the
+// right half as Pi Q^{-1}, so row c of Q^{-1} is row p_c of the right half.
+// Thread (tx, ty) keeps rows 4tx..4tx+3 and columns 8ty..8ty+7 of the
+// 64 x 128 augmented matrix in registers; per step the pivot row and the
+// pivot column go through LDS (two barriers).  Rows/columns >= m are an
+// identity padding that never takes part.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wg_invert64(double *gptr, int m, int ld, double *lds)
+{
+    GAS double *g = gp(gptr);
+    double *prow = lds;                               // [128]
+    double *pcol = lds + 128;                         // [64]
+    int *sh = reinterpret_cast<int *>(lds + 192);     // [0] pivot row, [1] bad, [2..65] row -> step
+    const int t = threadIdx.x;
+    const int tx = t & 15, ty = t >> 4;
+    const int r0 = 4 * tx, c0 = 8 * ty;
+    double a[4][8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int gr = r0 + r, gc = c0 + j;
+            double v;
+            if (gc < 64) v = (gr < m && gc < m) ? g[(size_t)gr * ld + gc] : (gr == gc ? 1.0 : 0.0);
+            else v = (gr == gc - 64) ? 1.0 : 0.0;
+            a[r][j] = v;
+        }
+    if (t == 0) sh[1] = 0;
+    unsigned long long used = 0ull;
+    for (int c = 0; c < m; ++c) {
+        // (1) pivot search in column c by the 16 threads of its column tile
+        if (ty == (c >> 3)) {
+            const int cc = c & 7;
+            double best = -1.0;
+            int bi = 64;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gr = r0 + r;
+                double v = -1.0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (j == cc) v = fabs(a[r][j]);
+                if (gr < m && !((used >> gr) & 1ull) && v > best) { best = v; bi = gr; }
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) {
+                const double ob = __shfl_xor(best, o, 16);
+                const int oi = __shfl_xor(bi, o, 16);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (tx == 0) {
+                sh[0] = bi;
+                if (!(best > 0.0) || !isfinite(best)) sh[1] = 1;
+            }
+        }
+        __syncthreads();
+        int p = sh[0];
+        if (p >= 64) p = c;             // no usable pivot: flagged above; keep going so every
+                                        // thread runs the same barriers (result is discarded)
+        used |= 1ull << p;
+        // (2) publish pivot row p and column c
+        if (tx == (p >> 2)) {
+            const int pr = p & 3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == pr)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) prow[c0 + j] = a[r][j];
+        }
+        if (ty == (c >> 3)) {
+            const int cc = c & 7;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (j == cc)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) pcol[r0 + r] = a[r][j];
+        }
+        if (t == 0) sh[2 + p] = c;
+        __syncthreads();
+        // (3) scale row p, eliminate column c elsewhere
+        const double pinv = 1.0 / prow[c];
+        double pr8[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pr8[j] = prow[c0 + j] * pinv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r0 + r == p) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[r][j] = pr8[j];
+            } else {
+                const double f = pcol[r0 + r];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[r][j] -= f * pr8[j];
+            }
+        }
+    }
+    __syncthreads();
+    const int bad = sh[1];
+    // row r of the right half is row sh[2 + r] of Q^{-1}
+    if (ty >= 8) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gr = r0 + r;
+            if (gr >= m) continue;
+            const int dst = sh[2 + gr];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int gc = c0 - 64 + j;
+                if (gc < m) g[(size_t)dst * ld + gc] = a[r][j];
+            }
+        }
+    }
+    __syncthreads();
+    return bad;
+}
+
+__device__ __forceinline__ int wg_inverse(double *g, int m, int ld, double *lds)
+{
+    return (m <= 64) ? wg_invert64(g, m, ld, lds) : wg_invert(g, m, ld, lds);
 }
 
 __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
@@ -191,9 +381,11 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict
     double *Pk = d.P64 + ((long long)i * s + k) * bs;
     const double *Jk = d.Jc + (SHJ ? 0 : (long long)k * d.nnzb * bs);
     const double *Mi = d.Mc + (long long)i * bs;
-    const double *Jd = Jk + (long long)d.diag_pos[i] * bs;
+    const GAS int *diag_pos = gp(d.diag_pos), *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx),
+                  *tpos = gp(d.tpos);
+    const double *Jd = Jk + (long long)diag_pos[i] * bs;
     const double dk = d.dcoef[k], dt = d.dt;
-    for (long long e = threadIdx.x; e < bs; e += NTHREADS) Pk[e] = dk * Mi[e] - dt * Jd[e];
+    for (long long e = threadIdx.x; e < bs; e += NTHREADS) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
     if (COUPLED) {
         // column k of the cross blocks: C_{lk,i} = A^{-1}_lk M_i (l != k)
         for (int l = 0; l < s; ++l) {
@@ -201,20 +393,20 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict
             const int idx = l < k ? l : l - 1;
             double *Cl = d.C64 + (((long long)i * s + k) * (s - 1) + idx) * bs;
             const double al = d.Ainv[l * SMAX + k];
-            for (long long e = threadIdx.x; e < bs; e += NTHREADS) Cl[e] = al * Mi[e];
+            for (long long e = threadIdx.x; e < bs; e += NTHREADS) gp(Cl)[e] = al * gp(Mi)[e];
         }
     }
     __syncthreads();
     double *X = d.Fscr + ((long long)i * s + k) * bs;
-    const int p0 = d.row_ptr[i], pd = d.diag_pos[i];
+    const int p0 = row_ptr[i], pd = diag_pos[i];
     for (int p = p0; p < pd; ++p) {
-        const long long j = d.col_idx[p];
+        const long long j = col_idx[p];
         const double *Pinv_j = d.P64 + (j * s + k) * bs;
-        wg_gemm(m, ld, 1.0, Pinv_j, Jk + (long long)d.tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
+        wg_gemm(m, ld, 1.0, Pinv_j, Jk + (long long)tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
         wg_gemm(m, ld, -dt * dt, Jk + (long long)p * bs, X, true, Pk, lds);           // -= dt^2 J_ij X
     }
     if (!COUPLED) {
-        if (wg_invert(Pk, m, ld, lds)) flag_singular(d, i);
+        if (wg_inverse(Pk, m, ld, lds)) flag_singular(d, i);
     }
 }
 
@@ -236,8 +428,24 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict
         return d.C64 + (((long long)i * s + col) * sm1 + idx) * bs;
     };
     double *L = d.Fscr + ((long long)i * s) * bs;
+    double *X = d.Fscr + ((long long)i * s + 1) * bs;
+    const double *Mi = d.Mc + (long long)i * bs;
     for (int k = 0; k < s; ++k) {
-        if (wg_invert(P(k), m, ld, lds)) flag_singular(d, i);
+        if (wg_inverse(P(k), m, ld, lds)) flag_singular(d, i);
+        if (k == 0) {
+            // every cross block is still A^{-1}_kl M_i: with X = M_i P_0^{-1} M_i,
+            //   P_l  -= A^{-1}_l0 A^{-1}_0l X,   C_lq -= A^{-1}_l0 A^{-1}_0q X
+            wg_gemm(m, ld, 1.0, Mi, P(0), false, L, lds);
+            wg_gemm(m, ld, 1.0, L, Mi, false, X, lds);
+            for (int l = 1; l < s; ++l)
+                for (int q = 1; q < s; ++q) {
+                    double *D = (q == l) ? P(l) : C(l, q);
+                    const double f = d.Ainv[l * SMAX + 0] * d.Ainv[0 * SMAX + q];
+                    for (long long e = threadIdx.x; e < bs; e += NTHREADS) gp(D)[e] -= f * gp(X)[e];
+                }
+            __syncthreads();
+            continue;
+        }
         for (int l = k + 1; l < s; ++l) {
             wg_gemm(m, ld, 1.0, C(l, k), P(k), false, L, lds);          // L = C_lk P_k^{-1}
             wg_gemm(m, ld, -1.0, L, C(k, l), true, P(l), lds);          // P_l -= L C_kl

@@ -28,28 +28,36 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], int nv, double *lds /*[4
     __syncthreads();
 }
 
-// Last-workgroup reduction of part[b][p] (b < nblk, p < nv) into out[p].
-// Returns true in the workgroup that did it.
-__device__ bool last_block_reduce(const SysDesc &d, unsigned *ticket, int nv, double *out) {
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
+// Reduction of the partials part[b][p] (b < nblk, p < nv) into out[p] by one
+// workgroup: every thread adds the blocks b = t, t + 256, ... for all p
+// (independent loads, all in flight), then the per-thread sums go through
+// the fixed wave/LDS tree: deterministic.  Runs in a separate kernel after
+// the pass that wrote the partials, so the kernel boundary orders them.
+template <int NVMAX>
+__device__ void reduce_partials(const SysDesc &d, int nblk, int nv, double *out) {
+    __shared__ double red[4 * NVMAX];
     const int stride = RESTART_MAX + 2;
-    for (int p = threadIdx.x; p < nv; p += NTHREADS) {
-        double a = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) a += d.part[(size_t)b * stride + p];
-        out[p] = a;
+    double a[NVMAX];
+#pragma unroll
+    for (int p = 0; p < NVMAX; ++p) a[p] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += NTHREADS) {
+        const GAS double *row = gp(d.part) + (size_t)b * stride;
+#pragma unroll
+        for (int p = 0; p < NVMAX; ++p)
+            if (p < nv) a[p] += row[p];
     }
-    if (threadIdx.x == 0) *ticket = 0u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < NVMAX; ++p) {
+        if (p < nv) {
+            const double x = wave_sum(a[p]);
+            if (lane == 0) red[w * NVMAX + p] = x;
+        }
+    }
     __syncthreads();
-    return true;
+    for (int p = threadIdx.x; p < nv; p += NTHREADS)
+        out[p] = (red[p] + red[NVMAX + p]) + (red[2 * NVMAX + p] + red[3 * NVMAX + p]);
+    __syncthreads();
 }
 
 template <int NVMAX, int PASS>
@@ -57,13 +65,12 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
                                                   double tol_abs)
 {
     __shared__ double lds[4 * NVMAX];
-    __shared__ double outv[NVMAX + 1];
     __shared__ double cf[NVMAX];
     const SysDesc &d = sysv[sys];
     const long long N = d.N;
     const int nv = j + 1;
-    const double *V = reinterpret_cast<const double *>(d.vec[SL_V]);
-    double *w = reinterpret_cast<double *>(d.vec[SL_W]);
+    const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[SL_V]));
+    GAS double *w = gp(reinterpret_cast<double *>(d.vec[SL_W]));
     const int off2 = RESTART_MAX + 1;
     for (int p = threadIdx.x; p < NVMAX; p += NTHREADS)
         cf[p] = (PASS == 1) ? ((p < nv) ? d.hbuf[p] : 0.0)
@@ -103,9 +110,20 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
     for (int p = threadIdx.x; p < nred; p += NTHREADS) {
         double a = 0.0;
         for (int w2 = 0; w2 < NTHREADS / 64; ++w2) a += lds[w2 * NACC + p];
-        d.part[(size_t)blockIdx.x * pstride + p] = a;
+        gp(d.part)[(size_t)blockIdx.x * pstride + p] = a;
     }
-    if (!last_block_reduce(d, &d.st->tickets[PASS], nred, outv)) return;
+}
+
+template <int NVMAX, int PASS>
+__global__ __launch_bounds__(NTHREADS) void k_cgs_finish(const SysDesc *__restrict__ sysv, int sys,
+                                                         int j, int nblk, double tol_abs)
+{
+    __shared__ double outv[NVMAX];
+    const SysDesc &d = sysv[sys];
+    const int nv = j + 1;
+    const int off2 = RESTART_MAX + 1;
+    constexpr int NACC = (PASS == 2) ? 1 : NVMAX;
+    reduce_partials<NACC>(d, nblk, (PASS == 2) ? 1 : nv, outv);
     if (PASS == 0) {
         for (int p = threadIdx.x; p < nv; p += NTHREADS) d.hbuf[p] = outv[p];
         return;
@@ -114,7 +132,7 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
         for (int p = threadIdx.x; p < nv; p += NTHREADS) d.hbuf[off2 + p] = outv[p];
         return;
     }
-    // PASS 2: Hessenberg column j, Givens rotation, estimate, flags
+    // Hessenberg column j, Givens rotation, estimate, flags
     if (threadIdx.x == 0) {
         const int R = d.restart;
         double *H = d.H;
@@ -153,8 +171,8 @@ __global__ __launch_bounds__(NTHREADS) void k_scale(const SysDesc *__restrict__ 
 {
     const SysDesc &d = sysv[sys];
     const long long N = d.N;
-    double *dst = reinterpret_cast<double *>(d.vec[dst_slot]) + (long long)dst_index * N;
-    const double *src = reinterpret_cast<const double *>(d.vec[src_slot]);
+    GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot])) + (long long)dst_index * N;
+    const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
     const double dv = d.st->rnorm2;
     const double inv = (dv > 0.0 && use_norm) ? 1.0 / dv : 0.0;
     for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
@@ -162,24 +180,30 @@ __global__ __launch_bounds__(NTHREADS) void k_scale(const SysDesc *__restrict__ 
         dst[e] = src[e] * inv;
 }
 
-// ||slot||; which = 0: bnorm;  which = 1: start of a cycle (beta, g, flags)
+// partial sums of ||slot||^2
 __global__ __launch_bounds__(NTHREADS) void k_norm(const SysDesc *__restrict__ sysv, int sys,
-                                                   int slot, int which)
+                                                   int slot)
 {
     __shared__ double lds[4];
-    __shared__ double outv[2];
     const SysDesc &d = sysv[sys];
     const long long N = d.N;
-    const double *x = reinterpret_cast<const double *>(d.vec[slot]);
+    const GAS double *x = gp(reinterpret_cast<const double *>(d.vec[slot]));
     double a[1] = {0.0};
     for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
          e += (long long)gridDim.x * NTHREADS)
         a[0] += x[e] * x[e];
     wg_sum<1>(a, 1, lds);
-    if (threadIdx.x == 0) {
-        d.part[(size_t)blockIdx.x * (RESTART_MAX + 2)] = lds[0] + lds[1] + lds[2] + lds[3];
-    }
-    if (!last_block_reduce(d, &d.st->tickets[3], 1, outv)) return;
+    if (threadIdx.x == 0)
+        gp(d.part)[(size_t)blockIdx.x * (RESTART_MAX + 2)] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+// which = 0: bnorm;  which = 1: start of a cycle (beta, g, flags)
+__global__ __launch_bounds__(NTHREADS) void k_norm_finish(const SysDesc *__restrict__ sysv, int sys,
+                                                          int which, int nblk)
+{
+    __shared__ double outv[1];
+    const SysDesc &d = sysv[sys];
+    reduce_partials<1>(d, nblk, 1, outv);
     if (threadIdx.x == 0) {
         const double nrm = sqrt(outv[0]);
         DevState *st = d.st;
@@ -218,8 +242,8 @@ __global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restric
             for (int i = 0; i < nv; ++i) d.y[i] = ys[i];
     }
     __syncthreads();
-    const double *V = reinterpret_cast<const double *>(d.vec[SL_V]);
-    double *u = reinterpret_cast<double *>(d.vec[SL_U]);
+    const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[SL_V]));
+    GAS double *u = gp(reinterpret_cast<double *>(d.vec[SL_U]));
     for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
          e += (long long)gridDim.x * NTHREADS) {
         double a = 0.0;
@@ -235,8 +259,8 @@ __global__ __launch_bounds__(NTHREADS) void k_copy(const SysDesc *__restrict__ s
 {
     const SysDesc &d = sysv[sys];
     const long long N = d.N;
-    double *dst = reinterpret_cast<double *>(d.vec[dst_slot]);
-    const double *src = reinterpret_cast<const double *>(d.vec[src_slot]);
+    GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot]));
+    const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
     for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
          e += (long long)gridDim.x * NTHREADS)
         dst[e] = scale * src[e];
@@ -247,15 +271,16 @@ __global__ __launch_bounds__(NTHREADS) void k_axpy(const SysDesc *__restrict__ s
 {
     const SysDesc &d = sysv[sys];
     const long long N = d.N;
-    double *dst = reinterpret_cast<double *>(d.vec[dst_slot]);
-    const double *src = reinterpret_cast<const double *>(d.vec[src_slot]);
+    GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot]));
+    const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
     for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
          e += (long long)gridDim.x * NTHREADS)
         dst[e] += src[e];
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_fill_zero(double *p, long long n)
+__global__ __launch_bounds__(NTHREADS) void k_fill_zero(double *pp, long long n)
 {
+    GAS double *p = gp(pp);
     for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < n;
          e += (long long)gridDim.x * NTHREADS)
         p[e] = 0.0;
@@ -265,11 +290,17 @@ __global__ __launch_bounds__(NTHREADS) void k_fill_zero(double *p, long long n)
 template <int PASS>
 static void cgs_dispatch(const SysDesc *dsys, int j, int nblk, double tol, hipStream_t st) {
     const int nv = j + 1;
-    dim3 g(nblk), b(NTHREADS);
-    if (nv <= 8) hipLaunchKernelGGL((k_cgs<8, PASS>), g, b, 0, st, dsys, 0, j, tol);
-    else if (nv <= 16) hipLaunchKernelGGL((k_cgs<16, PASS>), g, b, 0, st, dsys, 0, j, tol);
-    else if (nv <= 32) hipLaunchKernelGGL((k_cgs<32, PASS>), g, b, 0, st, dsys, 0, j, tol);
-    else hipLaunchKernelGGL((k_cgs<64, PASS>), g, b, 0, st, dsys, 0, j, tol);
+    dim3 g(nblk), b(NTHREADS), one(1);
+#define CGS(NV)                                                                              \
+    do {                                                                                     \
+        hipLaunchKernelGGL((k_cgs<NV, PASS>), g, b, 0, st, dsys, 0, j, tol);                \
+        hipLaunchKernelGGL((k_cgs_finish<NV, PASS>), one, b, 0, st, dsys, 0, j, nblk, tol); \
+    } while (0)
+    if (nv <= 8) CGS(8);
+    else if (nv <= 16) CGS(16);
+    else if (nv <= 32) CGS(32);
+    else CGS(64);
+#undef CGS
 }
 
 void launch_cgs(int pass, const SysDesc *dsys, const SysDesc &hsys, int j, int nblk, hipStream_t st)
@@ -302,14 +333,16 @@ void launch_norm(const SysDesc *dsys, const SysDesc &hsys, int slot, int which, 
                  hipStream_t st)
 {
     (void)hsys;
-    hipLaunchKernelGGL(k_norm, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, slot, which);
+    hipLaunchKernelGGL(k_norm, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, slot);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NTHREADS), 0, st, dsys, 0, which, nblk);
 }
 
 void launch_start_cycle(const SysDesc *dsys, const SysDesc &hsys, int src_slot, int nblk,
                         hipStream_t st)
 {
     (void)hsys;
-    hipLaunchKernelGGL(k_norm, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, src_slot, 1);
+    hipLaunchKernelGGL(k_norm, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, src_slot);
+    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NTHREADS), 0, st, dsys, 0, 1, nblk);
     hipLaunchKernelGGL(k_scale, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, (int)SL_V, 0, src_slot, 1);
 }
 

@@ -40,15 +40,17 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
     const int row = it.first + tm;
     const bool has = tm < it.count;
     const long long n = (long long)T * m;
-    const TX *x = reinterpret_cast<const TX *>(d.vec[x_slot]);
+    const GAS TX *x = gp(reinterpret_cast<const TX *>(d.vec[x_slot]));
+    const GAS int *row_ptr = gp(d.row_ptr);
+    const GAS int *col_idx = gp(d.col_idx);
     int p0 = 0, p1 = 0, ncol = 0;
     if (has) {
-        p0 = d.row_ptr[row];
-        p1 = d.row_ptr[row + 1];
+        p0 = row_ptr[row];
+        p1 = row_ptr[row + 1];
         ncol = (p1 - p0) * m;
         for (int q = tid; q < ncol; q += team) {
             const int b = q / m, c = q - b * m;
-            const long long j = d.col_idx[p0 + b];
+            const long long j = col_idx[p0 + b];
 #pragma unroll
             for (int k = 0; k < S; ++k)
                 if (k < s) xg[k * maxcols + q] = (TC)x[k * n + j * m + c];
@@ -77,10 +79,10 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
         for (int v = 0; v < V; ++v) { aj[k][v] = 0; am[k][v] = 0; }
 
     if (has && grp < G) {
-        const typename Vec16<TM>::st *Jb = jac_of<TM>(d);
-        const typename Vec16<TM>::st *Mb = mass_of<TM>(d);
+        const auto Jb = jac_of<TM>(d);
+        const auto Mb = mass_of<TM>(d);
         if (SHJ) {
-            const typename Vec16<TM>::st *base = Jb + (size_t)p0 * m * ld + slot * V;
+            const auto base = Jb + (size_t)p0 * m * ld + slot * V;
 #pragma unroll 4
             for (int cg = grp; cg < ncol; cg += G) {
                 TC a[V];
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
 #pragma unroll
             for (int k = 0; k < S; ++k) {
                 if (k >= s) continue;
-                const typename Vec16<TM>::st *base =
+                const auto base =
                     Jb + ((size_t)k * d.nnzb + p0) * m * ld + slot * V;
 #pragma unroll 4
                 for (int cg = grp; cg < ncol; cg += G) {
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
                 }
             }
         }
-        const typename Vec16<TM>::st *mb = Mb + (size_t)row * m * ld + slot * V;
+        const auto mb = Mb + (size_t)row * m * ld + slot * V;
 #pragma unroll 2
         for (int c = grp; c < m; c += G) {
             TC a[V];
@@ -142,10 +144,10 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
             for (int g2 = 0; g2 < G; ++g2) sum += red[(g2 * S + k) * ld + r];
             const long long o = k * n + (long long)row * m + r;
             if (MODE == 0) {
-                reinterpret_cast<double *>(d.vec[y_slot])[o] = (double)sum;
+                gp(reinterpret_cast<double *>(d.vec[y_slot]))[o] = (double)sum;
             } else {
-                const double *b = reinterpret_cast<const double *>(d.vec[b_slot]);
-                reinterpret_cast<double *>(d.vec[y_slot])[o] = b[o] - (double)sum;
+                const GAS double *b = gp(reinterpret_cast<const double *>(d.vec[b_slot]));
+                gp(reinterpret_cast<double *>(d.vec[y_slot]))[o] = b[o] - (double)sum;
             }
         }
     }

@@ -34,13 +34,9 @@ __device__ __forceinline__ TC sum_groups(const TC *red, int G, int k, int ldr, i
 }
 
 template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
-__global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ sysv,
-                                                    const Item *__restrict__ items,
-                                                    int v_slot, int v_index, int acc_slot)
+__device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int v_slot, int v_index,
+                                           int acc_slot, unsigned char *smem_raw)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Item it = items[blockIdx.x];
-    const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, T = d.T;
     constexpr int VJ = Vec16<TJ>::V, VF = Vec16<TF>::V;
     const int ldJ = ld_of<TJ>(d), ldF = ld_of<TF>(d);
@@ -61,25 +57,28 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
 
     const bool has = tm < it.count;
     const long long n = (long long)T * m;
-    const int *lvl = FWD ? d.lvl_fwd : d.lvl_bwd;
+    const GAS int *lvl = gp(FWD ? d.lvl_fwd : d.lvl_bwd);
+    const GAS int *row_ptr = gp(d.row_ptr);
+    const GAS int *col_idx = gp(d.col_idx);
+    const GAS int *diag_pos = gp(d.diag_pos);
     const int i = has ? lvl[it.first + tm] : 0;
-    TC *yh = reinterpret_cast<TC *>(d.vec[SL_YH]);
+    GAS TC *yh = gp(reinterpret_cast<TC *>(d.vec[SL_YH]));
     const TC dt = (TC)d.dt;
 
     int pa = 0, ncol = 0;
     if (has) {
-        const int p0 = d.row_ptr[i], p1 = d.row_ptr[i + 1], pd = d.diag_pos[i];
+        const int p0 = row_ptr[i], p1 = row_ptr[i + 1], pd = diag_pos[i];
         pa = FWD ? p0 : pd + 1;
         ncol = (FWD ? (pd - p0) : (p1 - pd - 1)) * m;
         for (int q = tid; q < ncol; q += team) {
             const int b = q / m, c = q - b * m;
-            const long long j = d.col_idx[pa + b];
+            const long long j = col_idx[pa + b];
 #pragma unroll
             for (int k = 0; k < S; ++k)
                 if (k < s) xg[k * maxg + q] = yh[k * n + j * m + c];
         }
         if (FWD) {
-            const double *v = reinterpret_cast<const double *>(d.vec[v_slot]) + (long long)v_index * d.N;
+            const GAS double *v = gp(reinterpret_cast<const double *>(d.vec[v_slot])) + (long long)v_index * d.N;
             for (int q = tid; q < s * m; q += team) {
                 const int k = q / m, r = q - k * m;
                 yv[k * ldv + r] = (TC)v[k * n + (long long)i * m + r];
@@ -101,9 +100,9 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
 #pragma unroll
             for (int v = 0; v < VJ; ++v) aj[k][v] = 0;
         if (has && gJ < GJ && ncol > 0) {
-            const typename Vec16<TJ>::st *Jb = jac_of<TJ>(d);
+            const auto Jb = jac_of<TJ>(d);
             if (SHJ) {
-                const typename Vec16<TJ>::st *base = Jb + (size_t)pa * m * ldJ + sJ * VJ;
+                const auto base = Jb + (size_t)pa * m * ldJ + sJ * VJ;
 #pragma unroll 4
                 for (int cg = gJ; cg < ncol; cg += GJ) {
                     TC a[VJ];
@@ -120,7 +119,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
                     if (k >= s) continue;
-                    const typename Vec16<TJ>::st *base =
+                    const auto base =
                         Jb + ((size_t)k * d.nnzb + pa) * m * ldJ + sJ * VJ;
 #pragma unroll 4
                     for (int cg = gJ; cg < ncol; cg += GJ) {
@@ -154,7 +153,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
         __syncthreads();
     }
 
-    const typename Vec16<TF>::st *Pb = piv_of<TF>(d);
+    const auto Pb = piv_of<TF>(d);
     const long long bsF = (long long)m * ldF;
     TC *red = xg;
 
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
 #pragma unroll
             for (int k = 0; k < S; ++k) {
                 if (k >= s) continue;
-                const typename Vec16<TF>::st *pb = Pb + ((long long)i * s + k) * bsF + sF * VF;
+                const auto pb = Pb + ((long long)i * s + k) * bsF + sF * VF;
 #pragma unroll 4
                 for (int c = gF; c < m; c += GF) {
                     TC a[VF];
@@ -189,7 +188,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
         }
         __syncthreads();
         if (has) {
-            double *acc = acc_slot >= 0 ? reinterpret_cast<double *>(d.vec[acc_slot]) : nullptr;
+            GAS double *acc = acc_slot >= 0 ? gp(reinterpret_cast<double *>(d.vec[acc_slot])) : nullptr;
             for (int q = tid; q < s * m; q += team) {
                 const int k = q / m, r = q - k * m;
                 const TC sc = block_scale<TF, TC>(d.P16e, (long long)i * s + k);
@@ -204,9 +203,9 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
     }
 
     // ---- coupled: stage rounds inside the element ----
-    const typename Vec16<TF>::st *Cb = cross_of<TF>(d);
+    const auto Cb = cross_of<TF>(d);
     const int sm1 = s - 1;
-    double *acc = acc_slot >= 0 ? reinterpret_cast<double *>(d.vec[acc_slot]) : nullptr;
+    GAS double *acc = acc_slot >= 0 ? gp(reinterpret_cast<double *>(d.vec[acc_slot])) : nullptr;
 #pragma unroll 1
     for (int kk = 0; kk < S; ++kk) {
         const int k = FWD ? kk : (S - 1 - kk);
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
 #pragma unroll
             for (int v = 0; v < VF; ++v) ap[v] = 0;
             if (act && gF < GF) {
-                const typename Vec16<TF>::st *pb = Pb + ((long long)i * s + k) * bsF + sF * VF;
+                const auto pb = Pb + ((long long)i * s + k) * bsF + sF * VF;
 #pragma unroll 4
                 for (int c = gF; c < m; c += GF) {
                     TC a[VF];
@@ -259,7 +258,7 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
                 for (int l = 0; l < S; ++l) {
                     if (l >= s || l == k || (FWD ? (l < k) : (l > k))) continue;
                     const int idx = l < k ? l : l - 1;
-                    const typename Vec16<TF>::st *cb =
+                    const auto cb =
                         Cb + (((long long)i * s + k) * sm1 + idx) * bsF + sF * VF;
 #pragma unroll 2
                     for (int c = gF; c < m; c += GF) {
@@ -290,15 +289,94 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ 
     }
 }
 
+// One level per launch: workgroup b handles items[b].
+template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
+__global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ sysv,
+                                                    const Item *__restrict__ items,
+                                                    int v_slot, int v_index, int acc_slot)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const Item it = items[blockIdx.x];
+    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD>(sysv[it.sys], it, v_slot, v_index, acc_slot, smem_raw);
+}
+
+// Whole sweep in one launch.  Workgroups take the items of all levels in
+// level order from an atomic ticket; before an item runs, one thread per
+// team waits until every dependency of its element (lower neighbours in the
+// forward sweep, upper ones in the backward sweep) has published its flag
+// for this sweep (`epoch`).  Every dependency sits at an earlier level, so
+// its ticket was taken earlier by a workgroup that is already running and
+// only waits on still earlier tickets: the smallest unfinished ticket can
+// always proceed, and the grid drains.  A bounded spin turns a lost flag
+// into an error flag instead of a hang.  Results are written, then made
+// visible device-wide (release fence) before the flag is set; the waiting
+// side acquires before reading them.
+template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
+__global__ __launch_bounds__(NTHREADS) void k_sweep_persist(const SysDesc *__restrict__ sysv,
+                                                            const Item *__restrict__ items,
+                                                            int nitems, int v_slot, int v_index,
+                                                            int acc_slot, unsigned epoch)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int tk;
+    const SysDesc &d = sysv[items[0].sys];
+    unsigned *ticket = &d.st->tickets[FWD ? 4 : 5];
+    unsigned *flags = d.dep_flags;
+    const GAS int *lvl = gp(FWD ? d.lvl_fwd : d.lvl_bwd);
+    const GAS int *row_ptr = gp(d.row_ptr);
+    const GAS int *col_idx = gp(d.col_idx);
+    const GAS int *diag_pos = gp(d.diag_pos);
+    for (;;) {
+        if (threadIdx.x == 0) tk = (int)atomicAdd(ticket, 1u);
+        __syncthreads();
+        const int t = tk;
+        if (t >= nitems) {
+            // the last workgroup to leave resets the ticket for the next launch
+            if (threadIdx.x == 0 && t == nitems + (int)gridDim.x - 1) *ticket = 0u;
+            return;
+        }
+        const Item it = items[t];
+        const int team = NTHREADS / it.aux;
+        const int tm = threadIdx.x / team, tid = threadIdx.x - tm * team;
+        if (tid == 0 && tm < it.count) {
+            const int i = lvl[it.first + tm];
+            const int p0 = FWD ? row_ptr[i] : diag_pos[i] + 1;
+            const int p1 = FWD ? diag_pos[i] : row_ptr[i + 1];
+            for (int q = p0; q < p1; ++q) {
+                const int j = col_idx[q];
+                long long spins = 0;
+                while (__hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1LL << 22)) { d.st->spin_timeout = 1; break; }
+                }
+            }
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        }
+        __syncthreads();
+        sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD>(d, it, v_slot, v_index, acc_slot, smem_raw);
+        __syncthreads();
+        if (tid == 0 && tm < it.count) {
+            const int i = lvl[it.first + tm];
+            __hip_atomic_store(&flags[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int S, typename TJ, typename TF, typename TC>
 static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                            bool coupled, bool sharedJ, int v_slot, int v_index, int acc_slot,
-                           size_t shmem, hipStream_t st)
+                           size_t shmem, hipStream_t st, int pgrid, unsigned epoch)
 {
-    dim3 grid(nitems), block(NTHREADS);
-#define SW(C, SH, F) \
-    hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, dsys, items, \
-                       v_slot, v_index, acc_slot)
+    dim3 grid(pgrid > 0 ? pgrid : nitems), block(NTHREADS);
+#define SW(C, SH, F)                                                                             \
+    do {                                                                                         \
+        if (pgrid > 0)                                                                           \
+            hipLaunchKernelGGL((k_sweep_persist<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, \
+                               dsys, items, nitems, v_slot, v_index, acc_slot, epoch);           \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, dsys,   \
+                               items, v_slot, v_index, acc_slot);                                \
+    } while (0)
     if (forward) {
         if (coupled) { if (sharedJ) SW(true, true, true); else SW(true, false, true); }
         else { if (sharedJ) SW(false, true, true); else SW(false, false, true); }
@@ -312,34 +390,34 @@ static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items,
 template <int S>
 static void launch_sweep_s(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                            bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
-                           int v_index, int acc_slot, size_t shmem, hipStream_t st)
+                           int v_index, int acc_slot, size_t shmem, hipStream_t st, int pgrid,
+                           unsigned epoch)
 {
     if (fp64) {
         launch_sweep_t<S, double, double, double>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                  v_slot, v_index, acc_slot, shmem, st);
+                                                  v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
     } else if (ftype == FT_F32) {
         launch_sweep_t<S, float, float, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                               v_slot, v_index, acc_slot, shmem, st);
+                                               v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
     } else if (ftype == FT_BF16) {
         launch_sweep_t<S, float, bf16s, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                               v_slot, v_index, acc_slot, shmem, st);
+                                               v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
     } else {
         launch_sweep_t<S, float, f16s, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                              v_slot, v_index, acc_slot, shmem, st);
+                                              v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
     }
 }
 
 void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems, int s_max,
                   bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot, int v_index,
-                  int out_slot, int acc_slot, int tpw, size_t shmem, hipStream_t st)
+                  int acc_slot, size_t shmem, hipStream_t st, int pgrid, unsigned epoch)
 {
-    (void)out_slot; (void)tpw;
     switch (s_max) {
-    case 1: launch_sweep_s<1>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st); break;
-    case 2: launch_sweep_s<2>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st); break;
-    case 3: launch_sweep_s<3>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st); break;
-    case 4: launch_sweep_s<4>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st); break;
-    default: launch_sweep_s<5>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st); break;
+    case 1: launch_sweep_s<1>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
+    case 2: launch_sweep_s<2>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
+    case 3: launch_sweep_s<3>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
+    case 4: launch_sweep_s<4>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
+    default: launch_sweep_s<5>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
     }
 }
 
