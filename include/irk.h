@@ -187,6 +187,19 @@ typedef struct {
 irk_status irk_profile_enable(irk_handle *h, int on);
 irk_status irk_profile_read(irk_handle *h, irk_profile_stats *out);
 
+/* Quantize nblk blocks of m*m FP64 values with the library's factor
+ * quantizer (the kernel irk_factor_ilu uses for reduced-precision factors):
+ *   IRK_FP32: float, round to nearest even;
+ *   IRK_BF16: bfloat16 of the FP32 value, round to nearest even;
+ *   IRK_FP16_SCALED: per block, e = 14 - E where max|x| lies in
+ *     [2^(E-1), 2^E) (e clamped to [-100, 100], 0 for a zero block), stored
+ *     value fp16(fp32(x * 2^e)), round to nearest even.
+ * src: DEVICE nblk*m*m doubles; dst: DEVICE nblk*m*m elements of 4 (FP32)
+ * or 2 bytes, same element order; exps: DEVICE nblk ints (FP16_SCALED,
+ * else may be NULL).  Enqueued on `stream` and waited for. */
+irk_status irk_quantize_blocks(const double *src, long long nblk, int m, irk_prec prec,
+                               void *dst, int *exps, hipStream_t stream);
+
 /* Element of the last singular pivot, or -1. */
 int irk_last_bad_element(const irk_handle *h);
 

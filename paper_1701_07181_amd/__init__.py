@@ -82,13 +82,14 @@ _L.irk_last_bad_element.argtypes = [_vp]
 _L.irk_destroy.argtypes = [_vp]
 _L.irk_radau_iia.argtypes = [C.c_int, _vp, _vp, _vp]
 _L.irk_profile_enable.argtypes = [_vp, C.c_int]
+_L.irk_quantize_blocks.argtypes = [_vp, C.c_longlong, C.c_int, C.c_int, _vp, _vp, _vp]
 _L.irk_profile_read.argtypes = [_vp, C.POINTER(_Prof)]
 
 EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_update_values",
             "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
             "irk_apply_preconditioner", "irk_export_factors", "irk_last_bad_element",
             "irk_destroy", "irk_status_str", "irk_radau_iia", "irk_profile_enable",
-            "irk_profile_read"]
+            "irk_profile_read", "irk_quantize_blocks"]
 
 
 def _check(st: int, where: str):
@@ -105,6 +106,24 @@ def radau_iia(s: int):
     A = np.zeros((s, s)); b = np.zeros(s); c = np.zeros(s)
     _check(_L.irk_radau_iia(s, A.ctypes.data, b.ctypes.data, c.ctypes.data), "irk_radau_iia")
     return A, b, c
+
+
+def quantize_blocks(src: torch.Tensor, prec: str):
+    """Quantize FP64 blocks [nblk, m, m] (device tensor) with the library's
+    factor quantizer.  Returns (values as int16/float32 tensor, exponents or
+    None)."""
+    src = src.contiguous()
+    nblk, m = int(src.shape[0]), int(src.shape[1])
+    if prec == "fp32":
+        dst = torch.empty(src.shape, dtype=torch.float32, device=src.device)
+    else:
+        dst = torch.empty(src.shape, dtype=torch.int16, device=src.device)
+    ex = torch.zeros(nblk, dtype=torch.int32, device=src.device) if prec == "fp16s" else None
+    st = torch.cuda.current_stream(src.device).cuda_stream
+    _check(_L.irk_quantize_blocks(src.data_ptr(), nblk, m, PREC[prec], dst.data_ptr(),
+                                  ex.data_ptr() if ex is not None else None, _vp(st)),
+           "irk_quantize_blocks")
+    return dst, ex
 
 
 @dataclass

@@ -747,6 +747,21 @@ irk_status irk_factor_ilu(irk_handle *h)
 
 int irk_last_bad_element(const irk_handle *h) { return h ? h->bad_element : -1; }
 
+irk_status irk_quantize_blocks(const double *src, long long nblk, int m, irk_prec prec, void *dst,
+                               int *exps, hipStream_t stream)
+{
+    if (!src || !dst || nblk < 0 || m < 1 || m > MMAX) return IRK_ERR_ARG;
+    if (prec != IRK_FP32 && prec != IRK_BF16 && prec != IRK_FP16_SCALED) return IRK_ERR_ARG;
+    if (prec == IRK_FP16_SCALED && !exps) return IRK_ERR_ARG;
+    const int ft = prec == IRK_FP32 ? FT_F32 : (prec == IRK_BF16 ? FT_BF16 : FT_F16S);
+    // the element-wise quantizer does not depend on the block's layout: an
+    // m x m row-major block is passed as a column-major one with ld = m
+    quantize_blocks(src, dst, exps, nblk, m, m, m, ft, stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return IRK_OK;
+}
+
 irk_status irk_apply_operator(irk_handle *h, const double *x, double *y)
 {
     if (!h || !x || !y) return IRK_ERR_ARG;

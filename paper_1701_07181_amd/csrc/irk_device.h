@@ -92,12 +92,25 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
-// FP32 -> FP16 (IEEE round to nearest even, hardware conversion).
+// FP32 -> FP16 bits, IEEE round to nearest even with subnormals, overflow to
+// infinity.  Computed exactly in FP64: the FP32 magnitude d is scaled so
+// that its half-precision significand becomes an integer, rounded with rint
+// (round half to even), and re-encoded.
 __device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
-    _Float16 h = (_Float16)f;
-    uint16_t u;
-    __builtin_memcpy(&u, &h, 2);
-    return u;
+    const uint32_t u = __float_as_uint(f);
+    const uint16_t sign = (uint16_t)((u >> 16) & 0x8000u);
+    const double d = fabs((double)f);
+    if (d != d) return (uint16_t)(sign | 0x7e00u);                 // NaN
+    if (d >= 65520.0) return (uint16_t)(sign | 0x7c00u);           // rounds to infinity
+    if (d < 0x1p-14) {                                             // half subnormal (or zero)
+        const double q = rint(d * 0x1p24);                         // units of 2^-24, q <= 1024
+        return (uint16_t)(sign | (uint16_t)q);                     // q = 1024 is the smallest normal
+    }
+    int ex = ilogb(d);                                             // -14 .. 15
+    double r = rint(ldexp(d, 10 - ex));                            // [1024, 2048]
+    if (r == 2048.0) { r = 1024.0; ++ex; }
+    if (ex > 15) return (uint16_t)(sign | 0x7c00u);
+    return (uint16_t)(sign | (uint16_t)((ex + 15) << 10) | (uint16_t)(r - 1024.0));
 }
 
 // leading dimension and base pointers by storage type

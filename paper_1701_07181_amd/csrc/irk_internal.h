@@ -145,6 +145,9 @@ void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nite
 void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems,
                    bool coupled, bool sharedJ, size_t shmem, hipStream_t st);
 
+// Quantize nblk column-major blocks (leading dimensions ld in, ldq out).
+void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int m, int ld,
+                     int ldq, int ftype, hipStream_t st);
 // Quantize the FP64 factors to ftype (FP32 / BF16 / FP16 scaled).
 void launch_quantize(const SysDesc *dsys, const SysDesc &hsys, int ftype, hipStream_t st);
 

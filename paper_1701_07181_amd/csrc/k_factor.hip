@@ -571,8 +571,8 @@ __global__ __launch_bounds__(NTHREADS) void k_quantize(const double *__restrict_
     }
 }
 
-static void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int m, int ld,
-                            int ldq, int ftype, hipStream_t st)
+void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int m, int ld,
+                     int ldq, int ftype, hipStream_t st)
 {
     if (nblk <= 0) return;
     dim3 grid((unsigned)nblk), block(NTHREADS);
