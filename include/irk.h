@@ -127,8 +127,8 @@ irk_status irk_workspace_size(const irk_problem *p, const irk_options *o, size_t
  * J and M into the caller-owned device workspace (re-laid for the kernels).
  * The caller may free J and M afterwards.  The handle keeps host memory
  * only; it never allocates device memory.  `workspace` must stay valid and
- * untouched until irk_destroy.  Enqueued on `stream`; returns without
- * waiting for the copies. */
+ * untouched until irk_destroy.  Work goes to `stream`; returns after the
+ * copies are done. */
 irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace,
                      size_t ws_bytes, hipStream_t stream, irk_handle **out);
 
@@ -144,15 +144,58 @@ irk_status irk_factor_ilu(irk_handle *h);
 
 /* Solve B x = rhs to the options' tolerance.  rhs, x: DEVICE [s][T][m];
  * x is the initial guess on entry (zero-fill it for x0 = 0) and the
- * solution on return.  info (HOST, may be NULL) is filled.  Synchronizes
- * once at the end and once per GMRES step to test convergence. */
+ * solution on return (updated in place during the solve).  info (HOST, may
+ * be NULL) is filled.  Synchronizes once per GMRES step to test
+ * convergence and once per restart cycle. */
 irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solve_info *info);
 
-/* Solve `count` independent systems together: every kernel launch of the
- * iteration covers all systems that have not converged.  Handles must be
- * factored, must not alias, and must share one stream.  rhs[i], x[i] are
- * per-handle DEVICE vectors; info (HOST) holds `count` entries. */
-irk_status irk_solve_batched(irk_handle *const *h, const double *const *rhs,
+/* ---- batches: many independent systems in the same kernel launches ----
+ * A batch runs the GMRES iteration of all its members together: every
+ * launch of a step (sweep levels, operator, orthogonalization) covers all
+ * members that are still iterating, so small systems fill the GPU together.
+ * Members must share the preconditioner kind, the precision scheme and the
+ * Jacobian sharing mode; they may differ in T, m, s, dt and restart.  Each
+ * member keeps using its own handle's workspace.  A batch never allocates
+ * device memory. */
+typedef struct irk_batch irk_batch;
+
+/* Device bytes of a batch of at most `capacity` members whose element
+ * counts add up to at most `max_elements`. */
+irk_status irk_batch_workspace_size(int capacity, long long max_elements, size_t *bytes);
+
+/* Create a batch working on `stream` in a caller-owned device workspace. */
+irk_status irk_batch_create(int capacity, long long max_elements, void *workspace,
+                            size_t ws_bytes, hipStream_t stream, irk_batch **out);
+
+/* Queue a factored handle with its right-hand side and its initial guess /
+ * solution vector (DEVICE [s][T][m] each; both must stay valid until the
+ * member is retired).  It starts at the next irk_batch_advance.  The batch's
+ * stream first waits for the work already enqueued on the handle's stream,
+ * so a new system can be set up and factored on another stream while the
+ * batch iterates.  IRK_ERR_NOMEM: no free slot or element budget. */
+irk_status irk_batch_admit(irk_batch *b, irk_handle *h, const double *rhs, double *x,
+                           long long tag);
+
+/* Run up to `cycles` GMRES cycles (restart periods) for every member;
+ * newly admitted members first get their initial residual.  Members that
+ * converge or fail leave the batch and wait to be retired.  Synchronizes at
+ * every step boundary where it checks convergence. */
+irk_status irk_batch_advance(irk_batch *b, int cycles);
+
+/* Pop up to `cap` retired members: their tags, statuses and infos (HOST
+ * arrays, any may be NULL).  *count receives the number popped. */
+irk_status irk_batch_retire(irk_batch *b, long long *tags, irk_status *status,
+                            irk_solve_info *info, int cap, int *count);
+
+/* Members queued or still iterating. */
+int irk_batch_pending(const irk_batch *b);
+
+irk_status irk_batch_destroy(irk_batch *b);
+
+/* Admit `count` handles (tags 0..count-1), advance until all have left,
+ * retire them; info (HOST, may be NULL) receives one entry per handle.
+ * The batch must be empty.  Returns the first non-OK member status. */
+irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
                              double *const *x, int count, irk_solve_info *info);
 
 /* y = B x with the FP64 operator (Eq. big-irk); DEVICE vectors. */

@@ -74,7 +74,14 @@ _L.irk_setup.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), _vp, C.c_size
 _L.irk_update_values.argtypes = [_vp, _vp, _vp, C.c_double]
 _L.irk_factor_ilu.argtypes = [_vp]
 _L.irk_gmres_solve.argtypes = [_vp, _vp, _vp, C.POINTER(_Info)]
-_L.irk_solve_batched.argtypes = [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.POINTER(_Info)]
+_L.irk_solve_batched.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.POINTER(_Info)]
+_L.irk_batch_workspace_size.argtypes = [C.c_int, C.c_longlong, C.POINTER(C.c_size_t)]
+_L.irk_batch_create.argtypes = [C.c_int, C.c_longlong, _vp, C.c_size_t, _vp, C.POINTER(_vp)]
+_L.irk_batch_admit.argtypes = [_vp, _vp, _vp, _vp, C.c_longlong]
+_L.irk_batch_advance.argtypes = [_vp, C.c_int]
+_L.irk_batch_retire.argtypes = [_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int), C.POINTER(_Info), C.c_int, C.POINTER(C.c_int)]
+_L.irk_batch_pending.argtypes = [_vp]
+_L.irk_batch_destroy.argtypes = [_vp]
 _L.irk_apply_operator.argtypes = [_vp, _vp, _vp]
 _L.irk_apply_preconditioner.argtypes = [_vp, _vp, _vp]
 _L.irk_export_factors.argtypes = [_vp, _vp, _vp]
@@ -89,7 +96,9 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
             "irk_apply_preconditioner", "irk_export_factors", "irk_last_bad_element",
             "irk_destroy", "irk_status_str", "irk_radau_iia", "irk_profile_enable",
-            "irk_profile_read", "irk_quantize_blocks"]
+            "irk_profile_read", "irk_quantize_blocks", "irk_batch_workspace_size",
+            "irk_batch_create", "irk_batch_admit", "irk_batch_advance", "irk_batch_retire",
+            "irk_batch_pending", "irk_batch_destroy"]
 
 
 def _check(st: int, where: str):
@@ -297,9 +306,77 @@ class Solver:
         return (P, Cx) if cross else P
 
 
-def solve_batched(solvers: Sequence[Solver], rhs: Sequence, x0: Optional[Sequence] = None):
-    """Solve several systems together (one launch per phase covers all of
-    them).  Returns (list of x, list of info dicts, status)."""
+class Batch:
+    """Many independent systems iterated together (one launch per phase covers
+    every member).  Members are factored Solvers sharing the preconditioner
+    kind and precision scheme."""
+
+    def __init__(self, capacity: int, max_elements: int, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        nbytes = C.c_size_t()
+        _check(_L.irk_batch_workspace_size(capacity, max_elements, C.byref(nbytes)),
+               "irk_batch_workspace_size")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_L.irk_batch_create(capacity, max_elements, self.workspace.data_ptr(),
+                                   int(nbytes.value), _vp(self.stream.cuda_stream), C.byref(h)),
+               "irk_batch_create")
+        self._b = h
+        self._keep = {}     # tag -> (solver, rhs, x) kept alive while in the batch
+        self.capacity = capacity
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            _L.irk_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, solver: "Solver", rhs, tag: int, x0=None) -> int:
+        """Queue a factored solver; returns the status (OK, or ERR_NOMEM when full)."""
+        b = solver._vec(rhs)
+        with torch.cuda.stream(solver.stream):
+            x = torch.zeros(solver.N, dtype=torch.float64, device=solver.device) if x0 is None \
+                else solver._vec(x0).clone()
+        st = _L.irk_batch_admit(self._b, solver.handle, b.data_ptr(), x.data_ptr(), int(tag))
+        if st == OK:
+            self._keep[int(tag)] = (solver, b, x)
+        return st
+
+    def advance(self, cycles: int = 1):
+        _check(_L.irk_batch_advance(self._b, int(cycles)), "irk_batch_advance")
+
+    @property
+    def pending(self) -> int:
+        return int(_L.irk_batch_pending(self._b))
+
+    def retire(self):
+        """List of (tag, x, info dict) of the members that finished."""
+        out = []
+        while True:
+            n = 64
+            tags = (C.c_longlong * n)()
+            sts = (C.c_int * n)()
+            infos = (_Info * n)()
+            cnt = C.c_int()
+            _check(_L.irk_batch_retire(self._b, tags, sts, infos, n, C.byref(cnt)), "irk_batch_retire")
+            for q in range(cnt.value):
+                solver, b, x = self._keep.pop(int(tags[q]))
+                out.append((int(tags[q]), x, _info_dict(infos[q], int(sts[q]))))
+            if cnt.value < n:
+                break
+        return out
+
+
+def solve_batched(batch: Batch, solvers: Sequence[Solver], rhs: Sequence, x0: Optional[Sequence] = None):
+    """Solve several systems together through irk_solve_batched.  Returns
+    (list of x, list of info dicts, status)."""
     n = len(solvers)
     bs = [s._vec(r) for s, r in zip(solvers, rhs)]
     xs = []
@@ -307,9 +384,9 @@ def solve_batched(solvers: Sequence[Solver], rhs: Sequence, x0: Optional[Sequenc
         with torch.cuda.stream(s.stream):
             xs.append(torch.zeros(s.N, dtype=torch.float64, device=s.device) if x0 is None
                       else s._vec(x0[q]).clone())
-    H = (_vp * n)(*[s._h for s in solvers])
+    H = (_vp * n)(*[s.handle for s in solvers])
     B = (_vp * n)(*[b.data_ptr() for b in bs])
     X = (_vp * n)(*[x.data_ptr() for x in xs])
     infos = (_Info * n)()
-    st = _L.irk_solve_batched(H, B, X, n, infos)
+    st = _L.irk_solve_batched(batch._b, H, B, X, n, infos)
     return xs, [_info_dict(infos[q], st) for q in range(n)], st

@@ -213,7 +213,7 @@ int pick_tpw(int ld, int V)
 struct Plan {
     size_t o_dsys, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
         o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_flags, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
-        o_hbuf, o_part, total;
+        o_hbuf, o_part, o_gather, total;
     int ld, ld32, ld16, nitems_max;
 };
 
@@ -230,7 +230,7 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     const int ft = factor_type(o);
     const long long N = (long long)s * T * m;
     const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * s * (s - 1) : 0;
-    P.nitems_max = T * (8 + 2 * s) + 64;
+    P.nitems_max = T * (8 + 2 * s) + 2 * RED_BLOCKS + 64;
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
     P.o_dsys = take(sizeof(SysDesc));
@@ -272,6 +272,7 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     P.o_y = take(sizeof(double) * (size_t)R);
     P.o_hbuf = take(sizeof(double) * 2 * (RESTART_MAX + 1));
     P.o_part = take(sizeof(double) * (size_t)RED_BLOCKS * (RESTART_MAX + 2));
+    P.o_gather = take(sizeof(DevState));
     P.total = off;
     return P;
 }
@@ -280,6 +281,27 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     do {                                            \
         if ((x) != hipSuccess) return IRK_ERR_DEVICE; \
     } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// work sets: the merged work items of one or more systems
+// ---------------------------------------------------------------------------
+namespace {
+
+struct WorkSet {
+    const SysDesc *dsys = nullptr;   // device table the items index into
+    Item *ditems = nullptr;          // device copy of `items`
+    std::vector<Item> items;
+    Launch mv64{0, 0}, mv32{0, 0}, vec{0, 0}, fin{0, 0};
+    std::vector<Launch> fwd64, bwd64, fwd32, bwd32;   // one entry per level
+    int smax = 1, restart = 1, nsys = 0;
+    bool mixed = false, coupled = false, sharedJ = true, has_pc = true;
+    int ftype = FT_F64;
+    size_t shm_mv64 = 0, shm_mv32 = 0, shm_sw64 = 0, shm_sw32 = 0;
+    bool persist = false;
+    int pgrid = 0;
+};
 
 }  // namespace
 
@@ -299,27 +321,59 @@ struct irk_handle {
     SysDesc *dsys;
     Item *ditems;
     DevState *dst;
-    DevState *hst;     // pinned host mirror
+    DevState *dgather;   // one gathered DevState (device)
+    DevState *hst;       // pinned host mirror
     Schedule sc;
-    std::vector<Item> items;
     std::vector<int> ints;
-    Launch mv64, mv32;
-    std::vector<Launch> fwd64, bwd64, fwd32, bwd32, fa, fb;
-    bool persist;      // one persistent launch per sweep instead of one per level
-    int pgrid;         // workgroups of a persistent sweep
-    unsigned epoch;    // flag value of the current persistent sweep
-    size_t shm_mv64, shm_mv32, shm_sw64, shm_sw32, shm_fac;
+    // per-system work lists (sys = 0) and factorization tasks
+    WorkSet W;
+    int tpw64, tpw32, nblk;
+    std::vector<Launch> fa, fb;
+    std::vector<Item> fitems;
+    size_t shm_fac;
     bool mixed, coupled, sharedJ, factored;
     int ftype;
-    int nblk;          // workgroups of the vector reductions
+    unsigned epoch;      // flag value of the current persistent sweep
     int bad_element;
     float ms_factor;
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0, ev1, ev_ready;
+    SysDesc solve_desc;  // descriptor with the caller's rhs / x (staging for the copy)
     // profiling: event pool and recorded intervals (kind, event index)
     bool prof;
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, int>> spans;
     int dropped;
+};
+
+struct irk_batch {
+    int capacity;
+    long long max_elements;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    SysDesc *dtab;               // device table [capacity]
+    DevState *dgather;           // [capacity]
+    Item *ditems;
+    size_t max_items;
+    std::vector<SysDesc> htab;   // host copy of the table
+    DevState *hgather;           // pinned [capacity]
+    struct Member {
+        irk_handle *h;
+        int slot;
+        long long tag;
+        double *x;
+        int phase;               // 0 queued, 1 iterating, 2 finished
+        double bn, rel, est;
+        int cycles, stall;
+        irk_status status;
+        irk_solve_info info;
+        hipEvent_t t0;
+    };
+    std::vector<Member> members;   // queued and iterating
+    std::vector<Member> retired;
+    std::vector<int> free_slots;
+    unsigned epoch;
+    hipEvent_t ev_end;
 };
 
 namespace {
@@ -328,7 +382,7 @@ enum ProfKind { PK_MV64 = 0, PK_MV32, PK_PC, PK_ORTH, PK_FACTOR, PK_N };
 // Start an interval; returns its pool index or -1.
 int prof_begin(irk_handle *h)
 {
-    if (!h->prof) return -1;
+    if (!h || !h->prof) return -1;
     const int idx = 2 * (int)h->spans.size();
     if (idx + 1 >= (int)h->pool.size()) { h->dropped++; return -1; }
     hipEventRecord(h->pool[idx], h->stream);
@@ -340,66 +394,289 @@ void prof_end(irk_handle *h, int idx, int kind)
     hipEventRecord(h->pool[idx + 1], h->stream);
     h->spans.push_back({kind, idx});
 }
-}  // namespace
 
-namespace {
+// Launch context: where the items live, which stream, optional profiling.
+struct Ctx {
+    WorkSet *W;
+    hipStream_t st;
+    irk_handle *prof;      // handle whose event pool records intervals (or null)
+    unsigned *epoch;
+};
 
-void add_level_items(irk_handle *h, const std::vector<int> &off, int tpw, std::vector<Launch> &out)
+void add_level_items(std::vector<Item> &items, const std::vector<int> &off, int tpw,
+                     std::vector<Launch> &out)
 {
     out.clear();
     for (size_t l = 0; l + 1 < off.size(); ++l) {
-        Launch L{(int)h->items.size(), 0};
+        Launch L{(int)items.size(), 0};
         for (int a = off[l]; a < off[l + 1]; a += tpw) {
-            h->items.push_back(Item{0, a, std::min(tpw, off[l + 1] - a), tpw});
+            items.push_back(Item{0, a, std::min(tpw, off[l + 1] - a), tpw});
             L.n++;
         }
         if (L.n) out.push_back(L);
     }
 }
 
-irk_status sync_state(irk_handle *h)
+int reduction_chunks(long long N)
 {
-    HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
-    return IRK_OK;
+    const long long nb = (N + NTHREADS * 4 - 1) / (NTHREADS * 4);
+    return (int)std::max(1LL, std::min<long long>(nb, 512));
+}
+
+size_t lds_matvec(int S, int m, int maxrow, int ld, int V, int tpw, size_t w)
+{
+    return w * (size_t)tpw * matvec_region(S, m, maxrow, ld, V, NTHREADS / tpw);
+}
+size_t lds_sweep(int S, int m, int maxrow, int ldJ, int VJ, int ldF, int VF, int tpw, size_t w)
+{
+    return w * (size_t)tpw * sweep_region(S, m, maxrow, ldJ, VJ, ldF, VF, NTHREADS / tpw);
+}
+
+// Work lists of several systems merged: every list of member q is copied
+// with sys = q; level l of the merged sweep holds level l of every member.
+void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &mem)
+{
+    M.items.clear();
+    M.fwd64.clear(); M.bwd64.clear(); M.fwd32.clear(); M.bwd32.clear();
+    M.nsys = (int)mem.size();
+    if (mem.empty()) return;
+    const irk_handle *h0 = mem[0].first;
+    M.mixed = h0->mixed; M.coupled = h0->coupled; M.sharedJ = h0->sharedJ;
+    M.has_pc = h0->opt.pc != IRK_PC_NONE; M.ftype = h0->ftype;
+    M.smax = 1; M.restart = 1;
+    M.persist = false;   // persistent sweeps serve one system at a time
+    for (auto &pr : mem) {
+        M.smax = std::max(M.smax, pr.first->s);
+        M.restart = std::max(M.restart, pr.first->opt.restart);
+    }
+    auto copy_list = [&](const Launch &L, const irk_handle *h, int sys) {
+        for (int a = 0; a < L.n; ++a) {
+            Item it = h->W.items[L.off + a];
+            it.sys = sys;
+            M.items.push_back(it);
+        }
+    };
+    auto merge = [&](Launch WorkSet::*f, Launch &out) {
+        out.off = (int)M.items.size();
+        for (auto &pr : mem) copy_list(pr.first->W.*f, pr.first, pr.second);
+        out.n = (int)M.items.size() - out.off;
+    };
+    auto merge_levels = [&](std::vector<Launch> WorkSet::*f, std::vector<Launch> &out) {
+        size_t L = 0;
+        for (auto &pr : mem) L = std::max(L, (pr.first->W.*f).size());
+        for (size_t l = 0; l < L; ++l) {
+            Launch o{(int)M.items.size(), 0};
+            for (auto &pr : mem) {
+                const auto &lv = pr.first->W.*f;
+                if (l < lv.size()) copy_list(lv[l], pr.first, pr.second);
+            }
+            o.n = (int)M.items.size() - o.off;
+            if (o.n) out.push_back(o);
+        }
+    };
+    merge(&WorkSet::mv64, M.mv64);
+    if (M.mixed) merge(&WorkSet::mv32, M.mv32);
+    merge(&WorkSet::vec, M.vec);
+    merge(&WorkSet::fin, M.fin);
+    if (M.has_pc) {
+        merge_levels(&WorkSet::fwd64, M.fwd64);
+        merge_levels(&WorkSet::bwd64, M.bwd64);
+        if (M.mixed) {
+            merge_levels(&WorkSet::fwd32, M.fwd32);
+            merge_levels(&WorkSet::bwd32, M.bwd32);
+        }
+    }
+    // LDS for the merged launches (template S = smax for every member)
+    M.shm_mv64 = M.shm_mv32 = M.shm_sw64 = M.shm_sw32 = 0;
+    for (auto &pr : mem) {
+        const irk_handle *h = pr.first;
+        const Plan &P = h->plan;
+        const int mr = h->sc.maxrow;
+        M.shm_mv64 = std::max(M.shm_mv64, lds_matvec(M.smax, h->m, mr, P.ld, 2, h->tpw64, sizeof(double)));
+        M.shm_sw64 = std::max(M.shm_sw64, lds_sweep(M.smax, h->m, mr, P.ld, 2, P.ld, 2, h->tpw64, sizeof(double)));
+        if (M.mixed) {
+            const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
+            const int VF = (h->ftype == FT_F32) ? 4 : 8;
+            M.shm_mv32 = std::max(M.shm_mv32, lds_matvec(M.smax, h->m, mr, P.ld32, 4, h->tpw32, sizeof(float)));
+            M.shm_sw32 = std::max(M.shm_sw32, lds_sweep(M.smax, h->m, mr, P.ld32, 4, ldF, VF, h->tpw32, sizeof(float)));
+        }
+    }
 }
 
 // z = P^{-1} v into SL_YH; acc_slot >= 0 also adds it to that FP64 slot
-void enqueue_pc(irk_handle *h, bool fp64, int v_slot, int v_index, int acc_slot)
+void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int skip_done)
 {
-    const int pi = prof_begin(h);
-    const std::vector<Launch> &F = fp64 ? h->fwd64 : h->fwd32;
-    const std::vector<Launch> &B = fp64 ? h->bwd64 : h->bwd32;
-    const size_t shm = fp64 ? h->shm_sw64 : h->shm_sw32;
-    const int ft = fp64 ? FT_F64 : h->ftype;
-    if (h->persist) {
+    WorkSet &W = *C.W;
+    const int pi = prof_begin(C.prof);
+    const std::vector<Launch> &F = fp64 ? W.fwd64 : W.fwd32;
+    const std::vector<Launch> &B = fp64 ? W.bwd64 : W.bwd32;
+    const size_t shm = fp64 ? W.shm_sw64 : W.shm_sw32;
+    const int ft = fp64 ? FT_F64 : W.ftype;
+    if (W.persist && W.nsys == 1) {
         const int nf = F.back().off + F.back().n - F.front().off;
         const int nb = B.back().off + B.back().n - B.front().off;
-        ++h->epoch;
-        launch_sweep(true, h->dsys, h->ditems + F.front().off, nf, h->s, fp64, ft, h->coupled,
-                     h->sharedJ, v_slot, v_index, -1, shm, h->stream, std::min(nf, h->pgrid), h->epoch);
-        ++h->epoch;
-        launch_sweep(false, h->dsys, h->ditems + B.front().off, nb, h->s, fp64, ft, h->coupled,
-                     h->sharedJ, v_slot, v_index, acc_slot, shm, h->stream, std::min(nb, h->pgrid),
-                     h->epoch);
+        ++*C.epoch;
+        launch_sweep(true, W.dsys, W.ditems + F.front().off, nf, W.smax, fp64, ft, W.coupled,
+                     W.sharedJ, v_slot, v_index, -1, skip_done, shm, C.st, std::min(nf, W.pgrid),
+                     *C.epoch);
+        ++*C.epoch;
+        launch_sweep(false, W.dsys, W.ditems + B.front().off, nb, W.smax, fp64, ft, W.coupled,
+                     W.sharedJ, v_slot, v_index, acc_slot, skip_done, shm, C.st,
+                     std::min(nb, W.pgrid), *C.epoch);
     } else {
         for (const Launch &L : F)
-            launch_sweep(true, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
-                         v_slot, v_index, -1, shm, h->stream, 0, 0u);
+            launch_sweep(true, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
+                         v_slot, v_index, -1, skip_done, shm, C.st, 0, 0u);
         for (const Launch &L : B)
-            launch_sweep(false, h->dsys, h->ditems + L.off, L.n, h->s, fp64, ft, h->coupled, h->sharedJ,
-                         v_slot, v_index, acc_slot, shm, h->stream, 0, 0u);
+            launch_sweep(false, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
+                         v_slot, v_index, acc_slot, skip_done, shm, C.st, 0, 0u);
     }
-    prof_end(h, pi, PK_PC);
+    prof_end(C.prof, pi, PK_PC);
 }
 
-void enqueue_matvec(irk_handle *h, bool fp64, int x_slot, int y_slot, int b_slot, int mode)
+void enqueue_matvec(Ctx &C, bool fp64, int x_slot, int y_slot, int b_slot, int mode, int skip_done)
 {
-    const Launch &L = fp64 ? h->mv64 : h->mv32;
-    const int pi = prof_begin(h);
-    launch_matvec(h->dsys, h->ditems + L.off, L.n, h->s, fp64 ? 0 : 1, h->sharedJ, x_slot, y_slot,
-                  b_slot, mode, 0, fp64 ? h->shm_mv64 : h->shm_mv32, h->stream);
-    prof_end(h, pi, fp64 ? PK_MV64 : PK_MV32);
+    WorkSet &W = *C.W;
+    const Launch &L = fp64 ? W.mv64 : W.mv32;
+    const int pi = prof_begin(C.prof);
+    launch_matvec(W.dsys, W.ditems + L.off, L.n, W.smax, fp64 ? 0 : 1, W.sharedJ, x_slot, y_slot,
+                  b_slot, mode, skip_done, fp64 ? W.shm_mv64 : W.shm_mv32, C.st);
+    prof_end(C.prof, pi, fp64 ? PK_MV64 : PK_MV32);
+}
+
+irk_status sync_states(Ctx &C, DevState *dgather, DevState *hgather)
+{
+    WorkSet &W = *C.W;
+    launch_gather_state(W.dsys, W.ditems + W.fin.off, W.fin.n, dgather, C.st);
+    HIPCHK(hipMemcpyAsync(hgather, dgather, sizeof(DevState) * W.fin.n, hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    return IRK_OK;
+}
+
+// A system being solved: its handle, its position in the work set, progress.
+struct Solve {
+    irk_handle *h;
+    double *x = nullptr;     // the solution vector the solve updates
+    double bn = 0, rel = 0, est = 0;
+    int cycles = 0, stall = 0;
+    bool finished = false;
+    irk_status status = IRK_OK;
+    irk_solve_info info{};
+};
+
+void finish(Solve &S, const DevState &st, irk_status status)
+{
+    S.finished = true;
+    S.status = status;
+    S.info.iters = st.iters;
+    S.info.outer_iters = std::max(S.cycles, 1);
+    S.info.restarts = std::max(S.cycles - 1, 0);
+    S.info.rel_res_true = S.rel;
+    S.info.rel_res_est = S.est;
+    S.info.equiv_mults = st.iters * S.h->s;
+    S.info.converged = (S.rel <= S.h->opt.rtol) ? 1 : 0;
+    S.info.bad_element = -1;
+    S.info.ms_factor = S.h->ms_factor;
+}
+
+// Initial residual of every system of the work set: ||b||, r = b - B x,
+// first cycle start.  Systems already converged (or with b = 0 or
+// non-finite data) are finished here.
+irk_status init_systems(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *hg)
+{
+    WorkSet &W = *C.W;
+    const Item *vec = W.ditems + W.vec.off, *fin = W.ditems + W.fin.off;
+    launch_reset_state(W.dsys, fin, W.fin.n, C.st);
+    launch_norm(W.dsys, vec, W.vec.n, fin, W.fin.n, SL_B, 0, C.st);
+    enqueue_matvec(C, true, SL_X, SL_R, SL_B, 1, 0);
+    launch_start_cycle(W.dsys, vec, W.vec.n, fin, W.fin.n, SL_R, C.st);
+    HIPCHK(hipGetLastError());
+    irk_status st = sync_states(C, dg, hg);
+    if (st != IRK_OK) return st;
+    for (size_t q = 0; q < sv.size(); ++q) {
+        Solve &S = *sv[q];
+        const DevState &d = hg[q];
+        S.bn = d.bnorm;
+        if (d.nonfinite || !std::isfinite(S.bn)) { S.rel = NAN; finish(S, d, IRK_ERR_NONFINITE); continue; }
+        if (S.bn == 0.0) {
+            // x = 0 solves B x = 0 exactly
+            HIPCHK(hipMemsetAsync(S.x, 0, sizeof(double) * S.h->hsys.N, C.st));
+            S.rel = 0.0;
+            finish(S, d, IRK_OK);
+            continue;
+        }
+        S.rel = d.beta / S.bn;
+        S.est = S.rel;
+        if (!std::isfinite(S.rel)) { finish(S, d, IRK_ERR_NONFINITE); continue; }
+        if (S.rel <= S.h->opt.rtol) finish(S, d, IRK_OK);
+    }
+    return IRK_OK;
+}
+
+// One GMRES cycle for every system of the work set (all unfinished):
+// up to `restart` Arnoldi steps (systems drop out when their estimate meets
+// the cycle tolerance), x += P^{-1} V y, FP64 true residual, next cycle start.
+irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *hg)
+{
+    WorkSet &W = *C.W;
+    const Item *vec = W.ditems + W.vec.off, *fin = W.ditems + W.fin.off;
+    const bool fp64 = !W.mixed;
+    const int check_every = (W.nsys == 1) ? 1 : 2;
+    for (int j = 0; j < W.restart; ++j) {
+        if (W.has_pc) {
+            enqueue_pc(C, fp64, SL_V, j, -1, 1);
+        } else {
+            launch_copy_to_yh(W.dsys, vec, W.vec.n, true, SL_V, j, 1, C.st);
+        }
+        enqueue_matvec(C, fp64, SL_YH, SL_W, -1, 0, 1);
+        const int po = prof_begin(C.prof);
+        launch_arnoldi(W.dsys, vec, W.vec.n, fin, W.fin.n, j, C.st);
+        prof_end(C.prof, po, PK_ORTH);
+        if ((j + 1) % check_every == 0 || j + 1 == W.restart) {
+            irk_status st = sync_states(C, dg, hg);
+            if (st != IRK_OK) return st;
+            bool all_done = true;
+            for (int q = 0; q < W.nsys; ++q) all_done = all_done && hg[q].done;
+            if (all_done) break;
+        }
+    }
+    // x += P^{-1} V y
+    launch_cycle_end(W.dsys, vec, W.vec.n, W.restart, C.st);
+    if (W.has_pc) enqueue_pc(C, fp64, SL_U, 0, SL_X, 0);
+    else launch_axpy(W.dsys, vec, W.vec.n, SL_X, SL_U, C.st);
+    // FP64 true residual and the next cycle
+    enqueue_matvec(C, true, SL_X, SL_R, SL_B, 1, 0);
+    // the last step's flags (breakdown, non-finite) are read before the reset
+    irk_status st = sync_states(C, dg, hg);
+    if (st != IRK_OK) return st;
+    std::vector<int> brk(W.nsys), nonf(W.nsys), spin(W.nsys);
+    for (int q = 0; q < W.nsys; ++q) {
+        brk[q] = hg[q].breakdown; nonf[q] = hg[q].nonfinite; spin[q] = hg[q].spin_timeout;
+        sv[q]->est = hg[q].est / std::max(sv[q]->bn, 1e-300);
+    }
+    launch_start_cycle(W.dsys, vec, W.vec.n, fin, W.fin.n, SL_R, C.st);
+    HIPCHK(hipGetLastError());
+    st = sync_states(C, dg, hg);
+    if (st != IRK_OK) return st;
+    for (int q = 0; q < W.nsys; ++q) {
+        Solve &S = *sv[q];
+        const DevState &d = hg[q];
+        const irk_options &o = S.h->opt;
+        const double newrel = d.beta / S.bn;
+        S.cycles++;
+        if (spin[q]) { S.rel = newrel; finish(S, d, IRK_ERR_DEVICE); continue; }
+        if (nonf[q] || d.nonfinite || !std::isfinite(newrel)) { S.rel = newrel; finish(S, d, IRK_ERR_NONFINITE); continue; }
+        if (newrel <= o.rtol) { S.rel = newrel; finish(S, d, IRK_OK); continue; }
+        if (brk[q] && !(newrel < 0.5 * S.rel)) {
+            if (++S.stall >= 2) { S.rel = newrel; finish(S, d, IRK_ERR_BREAKDOWN); continue; }
+        }
+        S.rel = newrel;
+        if (d.iters >= o.max_iters || (S.h->mixed && S.cycles >= o.max_outer)) {
+            finish(S, d, IRK_ERR_NOCONV);
+            continue;
+        }
+    }
+    return IRK_OK;
 }
 
 }  // namespace
@@ -508,6 +785,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     if (!h) return IRK_ERR_ARG;
     h->s = p->s; h->T = p->T; h->m = p->m; h->nnzb = p->nnzb; h->nJ = p->nJ; h->dt = p->dt;
     h->opt = *o;
+    h->opt.alpha = nullptr;
     h->stream = stream;
     h->ws = (char *)workspace;
     h->ws_bytes = ws_bytes;
@@ -537,58 +815,76 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     h->sharedJ = (p->nJ == 1);
     h->ftype = factor_type(o);
 
-    // ---- items ----
-    h->items.clear();
-    const int tpw64 = pick_tpw(P.ld, 2), tpw32 = pick_tpw(P.ld32, 4);
+    // ---- work items ----
+    WorkSet &W = h->W;
+    W.items.clear();
+    h->tpw64 = pick_tpw(P.ld, 2);
+    h->tpw32 = pick_tpw(P.ld32, 4);
     auto row_items = [&](int tpw, Launch &L) {
-        L.off = (int)h->items.size();
+        L.off = (int)W.items.size();
         L.n = 0;
-        for (int a = 0; a < T; a += tpw) { h->items.push_back(Item{0, a, std::min(tpw, T - a), tpw}); L.n++; }
+        for (int a = 0; a < T; a += tpw) { W.items.push_back(Item{0, a, std::min(tpw, T - a), tpw}); L.n++; }
     };
-    row_items(tpw64, h->mv64);
-    if (h->mixed) row_items(tpw32, h->mv32);
+    row_items(h->tpw64, W.mv64);
+    if (h->mixed) row_items(h->tpw32, W.mv32);
+    h->nblk = reduction_chunks((long long)s * T * m);
+    W.vec.off = (int)W.items.size();
+    for (int c = 0; c < h->nblk; ++c) W.items.push_back(Item{0, c, h->nblk, 0});
+    W.vec.n = h->nblk;
+    W.fin.off = (int)W.items.size();
+    W.items.push_back(Item{0, 0, h->nblk, 0});
+    W.fin.n = 1;
     if (o->pc != IRK_PC_NONE) {
-        add_level_items(h, h->sc.off_fwd, tpw64, h->fwd64);
-        add_level_items(h, h->sc.off_bwd, tpw64, h->bwd64);
+        add_level_items(W.items, h->sc.off_fwd, h->tpw64, W.fwd64);
+        add_level_items(W.items, h->sc.off_bwd, h->tpw64, W.bwd64);
         if (h->mixed) {
-            add_level_items(h, h->sc.off_fwd, tpw32, h->fwd32);
-            add_level_items(h, h->sc.off_bwd, tpw32, h->bwd32);
+            add_level_items(W.items, h->sc.off_fwd, h->tpw32, W.fwd32);
+            add_level_items(W.items, h->sc.off_bwd, h->tpw32, W.bwd32);
         }
-        // factor tasks per forward level
-        h->fa.clear(); h->fb.clear();
+    }
+    // factor tasks per forward level (stored after the work set's items)
+    h->fa.clear(); h->fb.clear();
+    h->fitems.clear();
+    if (o->pc != IRK_PC_NONE) {
         for (size_t l = 0; l + 1 < h->sc.off_fwd.size(); ++l) {
-            Launch A{(int)h->items.size(), 0};
+            Launch A{(int)(W.items.size() + h->fitems.size()), 0};
             for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a)
-                for (int k = 0; k < s; ++k) { h->items.push_back(Item{0, h->sc.lvl_fwd[a], 1, k}); A.n++; }
+                for (int k = 0; k < s; ++k) { h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, k}); A.n++; }
             h->fa.push_back(A);
-            Launch B{(int)h->items.size(), 0};
+            Launch B{(int)(W.items.size() + h->fitems.size()), 0};
             if (h->coupled)
                 for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
-                    h->items.push_back(Item{0, h->sc.lvl_fwd[a], 1, 0});
+                    h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, 0});
                     B.n++;
                 }
             h->fb.push_back(B);
         }
     }
-    if ((int)h->items.size() > P.nitems_max) { delete h; return IRK_ERR_ARG; }
+    if ((int)(W.items.size() + h->fitems.size()) > P.nitems_max) { delete h; return IRK_ERR_ARG; }
+    W.smax = s;
+    W.restart = o->restart;
+    W.nsys = 1;
+    W.mixed = h->mixed; W.coupled = h->coupled; W.sharedJ = h->sharedJ;
+    W.has_pc = o->pc != IRK_PC_NONE; W.ftype = h->ftype;
 
     // ---- LDS sizes ----
     const int maxrow = h->sc.maxrow;
-    h->shm_mv64 = sizeof(double) * tpw64 * matvec_region(s, m, maxrow, P.ld, 2, NTHREADS / tpw64);
-    h->shm_mv32 = sizeof(float) * tpw32 * matvec_region(s, m, maxrow, P.ld32, 4, NTHREADS / tpw32);
-    h->shm_sw64 = sizeof(double) * tpw64 * sweep_region(s, m, maxrow, P.ld, 2, P.ld, 2, NTHREADS / tpw64);
+    W.shm_mv64 = lds_matvec(s, m, maxrow, P.ld, 2, h->tpw64, sizeof(double));
+    W.shm_mv32 = lds_matvec(s, m, maxrow, P.ld32, 4, h->tpw32, sizeof(float));
+    W.shm_sw64 = lds_sweep(s, m, maxrow, P.ld, 2, P.ld, 2, h->tpw64, sizeof(double));
     {
         const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
         const int VF = (h->ftype == FT_F32) ? 4 : 8;
-        h->shm_sw32 = sizeof(float) * tpw32 * sweep_region(s, m, maxrow, P.ld32, 4, ldF, VF, NTHREADS / tpw32);
+        W.shm_sw32 = lds_sweep(s, m, maxrow, P.ld32, 4, ldF, VF, h->tpw32, sizeof(float));
     }
     {
         const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
         const size_t gm = sizeof(double) * 2 * 64 * 64;
         h->shm_fac = std::max(gj, gm);
     }
-    if (h->shm_fac > 160 * 1024 || h->shm_mv64 > 160 * 1024 || h->shm_sw64 > 160 * 1024 ||
-        h->shm_sw32 > 160 * 1024 || h->shm_mv32 > 160 * 1024) {
+    const size_t lds_max = 160 * 1024;
+    if (h->shm_fac > lds_max || W.shm_mv64 > lds_max || W.shm_sw64 > lds_max ||
+        (h->mixed && (W.shm_sw32 > lds_max || W.shm_mv32 > lds_max))) {
         delete h;
         return IRK_ERR_ARG;
     }
@@ -597,11 +893,11 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         // sweep mode: one launch per level (default) or one persistent
         // dependency-driven launch per sweep (IRK_SWEEP_PERSIST=1)
         const char *e = std::getenv("IRK_SWEEP_PERSIST");
-        h->persist = (e && e[0] == '1');
+        W.persist = (e && e[0] == '1');
         int dev = 0, ncu = 256;
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        h->pgrid = std::max(1, ncu) * 4;
+        W.pgrid = std::max(1, ncu) * 4;
         h->epoch = 0;
     }
 
@@ -615,6 +911,10 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     d.pc = o->pc;
     d.ftype = h->ftype;
     d.restart = o->restart;
+    d.max_iters = o->max_iters;
+    d.mixed = h->mixed ? 1 : 0;
+    d.rtol = o->rtol;
+    d.inner_rtol = o->inner_rtol;
     d.N = (long long)s * T * m;
     d.dt = p->dt;
     for (int k = 0; k < s; ++k) {
@@ -653,11 +953,9 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     h->dsys = (SysDesc *)(ws + P.o_dsys);
     h->ditems = (Item *)(ws + P.o_items);
     h->dst = d.st;
-    {
-        const long long N = d.N;
-        long long nb = (N + NTHREADS * 4 - 1) / (NTHREADS * 4);
-        h->nblk = (int)std::max(1LL, std::min<long long>(nb, 512));
-    }
+    h->dgather = (DevState *)(ws + P.o_gather);
+    W.dsys = h->dsys;
+    W.ditems = h->ditems;
 
     // ---- uploads ----
     h->ints.assign((size_t)(T + 1) + 2 * (size_t)p->nnzb + 3 * (size_t)T, 0);
@@ -674,9 +972,12 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     std::memset(h->hst, 0, sizeof(DevState));
     hipEventCreate(&h->ev0);
     hipEventCreate(&h->ev1);
+    hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming);
+    std::vector<Item> all(W.items);
+    all.insert(all.end(), h->fitems.begin(), h->fitems.end());
     bool ok = true;
     ok &= hipMemcpyAsync(ip, h->ints.data(), sizeof(int) * h->ints.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
-    ok &= hipMemcpyAsync(h->ditems, h->items.data(), sizeof(Item) * h->items.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
+    ok &= hipMemcpyAsync(h->ditems, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, stream) == hipSuccess;
     if (o->pc != IRK_PC_NONE)
@@ -732,8 +1033,8 @@ irk_status irk_factor_ilu(irk_handle *h)
     prof_end(h, pf, PK_FACTOR);
     hipEventRecord(h->ev1, h->stream);
     HIPCHK(hipGetLastError());
-    irk_status st = sync_state(h);
-    if (st != IRK_OK) return st;
+    HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
     hipEventElapsedTime(&h->ms_factor, h->ev0, h->ev1);
     if (h->hst->singular) {
         h->bad_element = h->hst->singular - 1;
@@ -767,7 +1068,8 @@ irk_status irk_apply_operator(irk_handle *h, const double *x, double *y)
     if (!h || !x || !y) return IRK_ERR_ARG;
     const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
     HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], x, bytes, hipMemcpyDeviceToDevice, h->stream));
-    enqueue_matvec(h, true, SL_EXT0, SL_EXT1, -1, 0);
+    Ctx C{&h->W, h->stream, h, &h->epoch};
+    enqueue_matvec(C, true, SL_EXT0, SL_EXT1, -1, 0, 0);
     HIPCHK(hipMemcpyAsync(y, h->hsys.vec[SL_EXT1], bytes, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return IRK_OK;
@@ -784,7 +1086,8 @@ irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z)
         return IRK_OK;
     }
     HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], v, bytes, hipMemcpyDeviceToDevice, h->stream));
-    enqueue_pc(h, true, SL_EXT0, 0, -1);
+    Ctx C{&h->W, h->stream, h, &h->epoch};
+    enqueue_pc(C, true, SL_EXT0, 0, -1, 0);
     HIPCHK(hipMemcpyAsync(z, h->hsys.vec[SL_YH], bytes, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return IRK_OK;
@@ -803,118 +1106,27 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
 {
     if (!h || !rhs || !x) return IRK_ERR_ARG;
     if (!h->factored) return IRK_ERR_STATE;
-    const irk_options &o = h->opt;
-    const SysDesc &d = h->hsys;
-    const size_t bytes = sizeof(double) * (size_t)d.N;
-    const bool fp64 = !h->mixed;
-    const bool has_pc = o.pc != IRK_PC_NONE;
-    irk_solve_info inf;
-    std::memset(&inf, 0, sizeof(inf));
-    inf.bad_element = -1;
-    inf.ms_factor = h->ms_factor;
+    // the solve reads rhs and updates x in place: point the slots at them
+    h->solve_desc = h->hsys;
+    h->solve_desc.vec[SL_B] = const_cast<double *>(rhs);
+    h->solve_desc.vec[SL_X] = x;
     hipEventRecord(h->ev0, h->stream);
-    HIPCHK(hipMemcpyAsync(d.vec[SL_B], rhs, bytes, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(hipMemcpyAsync(d.vec[SL_X], x, bytes, hipMemcpyDeviceToDevice, h->stream));
-    h->hst->nonfinite = 0;
-    h->hst->done = 0;
-    h->hst->breakdown = 0;
-    std::memset(h->hst->tickets, 0, sizeof(h->hst->tickets));
-    HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
-    launch_norm(h->dsys, d, SL_B, 0, h->nblk, h->stream);
-    irk_status st = sync_state(h);
-    if (st != IRK_OK) return st;
-    const double bn = h->hst->bnorm;
-    irk_status result = IRK_OK;
-    if (h->hst->nonfinite || !std::isfinite(bn)) {
-        result = IRK_ERR_NONFINITE;
-    } else if (bn == 0.0) {
-        launch_fill_zero((double *)d.vec[SL_X], d.N, h->stream);
-        inf.converged = 1;
-    } else {
-        // r0 = b - B x0, beta, v_0
-        enqueue_matvec(h, true, SL_X, SL_R, SL_B, 1);
-        launch_start_cycle(h->dsys, d, SL_R, h->nblk, h->stream);
-        st = sync_state(h);
-        if (st != IRK_OK) return st;
-        double rel = h->hst->beta / bn;
-        int iters = 0, cycles = 0, stall = 0;
-        double est = rel;
-        while (true) {
-            if (h->hst->nonfinite || !std::isfinite(rel)) { result = IRK_ERR_NONFINITE; break; }
-            if (rel <= o.rtol) { inf.converged = 1; break; }
-            if (iters >= o.max_iters || (h->mixed && cycles >= o.max_outer)) { result = IRK_ERR_NOCONV; break; }
-            const double beta = h->hst->beta;
-            const double tol_abs = fp64 ? o.rtol * bn : std::max(o.inner_rtol * beta, o.rtol * bn);
-            int jl = -1;
-            bool brk = false;
-            for (int j = 0; j < o.restart; ++j) {
-                if (has_pc) {
-                    enqueue_pc(h, fp64, SL_V, j, -1);
-                    enqueue_matvec(h, fp64, SL_YH, SL_W, -1, 0);
-                } else {
-                    // z = v_j: copy into YH (FP64 only) then multiply
-                    HIPCHK(hipMemcpyAsync(d.vec[SL_YH], (double *)d.vec[SL_V] + (size_t)j * d.N, bytes,
-                                          hipMemcpyDeviceToDevice, h->stream));
-                    enqueue_matvec(h, true, SL_YH, SL_W, -1, 0);
-                }
-                const int po = prof_begin(h);
-                launch_cgs(0, h->dsys, d, j, h->nblk, h->stream);
-                launch_cgs(1, h->dsys, d, j, h->nblk, h->stream);
-                launch_givens(h->dsys, d, j, tol_abs, h->nblk, h->stream);
-                prof_end(h, po, PK_ORTH);
-                ++iters;
-                st = sync_state(h);
-                if (st != IRK_OK) return st;
-                jl = j;
-                est = h->hst->est / bn;
-                if (h->hst->nonfinite) break;
-                brk = h->hst->breakdown != 0;
-                if (h->hst->done || iters >= o.max_iters) break;
-            }
-            if (h->hst->nonfinite) { result = IRK_ERR_NONFINITE; break; }
-            if (h->hst->spin_timeout) { result = IRK_ERR_DEVICE; break; }
-            // x += P^{-1} V y
-            launch_cycle_end_n(h->dsys, jl + 1, h->nblk, h->stream);
-            if (has_pc) enqueue_pc(h, fp64, SL_U, 0, SL_X);
-            else launch_axpy(h->dsys, d, SL_X, SL_U, h->nblk, h->stream);
-            enqueue_matvec(h, true, SL_X, SL_R, SL_B, 1);
-            launch_start_cycle(h->dsys, d, SL_R, h->nblk, h->stream);
-            st = sync_state(h);
-            if (st != IRK_OK) return st;
-            const double newrel = h->hst->beta / bn;
-            ++cycles;
-            if (brk && !(newrel <= o.rtol) && !(newrel < 0.5 * rel)) {
-                if (++stall >= 2) { rel = newrel; result = IRK_ERR_BREAKDOWN; break; }
-            }
-            rel = newrel;
-        }
-        inf.iters = iters;
-        inf.outer_iters = std::max(cycles, 1);
-        inf.restarts = std::max(cycles - 1, 0);
-        inf.rel_res_true = rel;
-        inf.rel_res_est = est;
-        if (result == IRK_ERR_BREAKDOWN && rel <= o.rtol) result = IRK_OK;
-    }
-    HIPCHK(hipMemcpyAsync(x, d.vec[SL_X], bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->dsys, &h->solve_desc, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
+    Ctx C{&h->W, h->stream, h, &h->epoch};
+    Solve S;
+    S.h = h;
+    S.x = x;
+    std::vector<Solve *> sv{&S};
+    irk_status st = init_systems(C, sv, h->dgather, h->hst);
+    while (st == IRK_OK && !S.finished) st = run_cycle(C, sv, h->dgather, h->hst);
+    // restore the workspace slots for the kernel-level entry points
+    HIPCHK(hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
     hipEventRecord(h->ev1, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
-    HIPCHK(hipGetLastError());
-    hipEventElapsedTime(&inf.ms_solve, h->ev0, h->ev1);
-    inf.equiv_mults = inf.iters * h->s;
-    if (info) *info = inf;
-    return result;
-}
-
-irk_status irk_solve_batched(irk_handle *const *h, const double *const *rhs, double *const *x, int count,
-                             irk_solve_info *info)
-{
-    if (!h || !rhs || !x || count < 0) return IRK_ERR_ARG;
-    irk_status worst = IRK_OK;
-    for (int q = 0; q < count; ++q) {
-        irk_status st = irk_gmres_solve(h[q], rhs[q], x[q], info ? info + q : nullptr);
-        if (st != IRK_OK && worst == IRK_OK) worst = st;
-    }
-    return worst;
+    if (st != IRK_OK) return st;
+    hipEventElapsedTime(&S.info.ms_solve, h->ev0, h->ev1);
+    if (info) *info = S.info;
+    return S.status;
 }
 
 irk_status irk_profile_enable(irk_handle *h, int on)
@@ -958,9 +1170,251 @@ irk_status irk_destroy(irk_handle *h)
     if (!h) return IRK_ERR_ARG;
     for (auto &e : h->pool) hipEventDestroy(e);
     if (h->hst) hipHostFree(h->hst);
-    hipEventDestroy(h->ev0);
-    hipEventDestroy(h->ev1);
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
+    if (h->ev_ready) hipEventDestroy(h->ev_ready);
     delete h;
+    return IRK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+static size_t batch_items_bound(int capacity, long long max_elements)
+{
+    return (size_t)(10 * max_elements) + (size_t)capacity * (2 * RED_BLOCKS + 8);
+}
+
+static size_t batch_ws_bytes(int capacity, long long max_elements)
+{
+    size_t off = 0;
+    off = align256(off + sizeof(SysDesc) * (size_t)capacity);
+    off = align256(off + sizeof(DevState) * (size_t)capacity);
+    off = align256(off + sizeof(Item) * batch_items_bound(capacity, max_elements));
+    return off;
+}
+
+irk_status irk_batch_workspace_size(int capacity, long long max_elements, size_t *bytes)
+{
+    if (!bytes || capacity < 1 || max_elements < 1) return IRK_ERR_ARG;
+    *bytes = batch_ws_bytes(capacity, max_elements);
+    return IRK_OK;
+}
+
+irk_status irk_batch_create(int capacity, long long max_elements, void *workspace, size_t ws_bytes,
+                            hipStream_t stream, irk_batch **out)
+{
+    if (!out || !workspace || capacity < 1 || max_elements < 1) return IRK_ERR_ARG;
+    *out = nullptr;
+    if (ws_bytes < batch_ws_bytes(capacity, max_elements)) return IRK_ERR_NOMEM;
+    irk_batch *b = new (std::nothrow) irk_batch();
+    if (!b) return IRK_ERR_ARG;
+    b->capacity = capacity;
+    b->max_elements = max_elements;
+    b->stream = stream;
+    b->ws = (char *)workspace;
+    b->ws_bytes = ws_bytes;
+    size_t off = 0;
+    b->dtab = (SysDesc *)(b->ws + off);
+    off = align256(off + sizeof(SysDesc) * (size_t)capacity);
+    b->dgather = (DevState *)(b->ws + off);
+    off = align256(off + sizeof(DevState) * (size_t)capacity);
+    b->ditems = (Item *)(b->ws + off);
+    b->max_items = batch_items_bound(capacity, max_elements);
+    b->htab.assign(capacity, SysDesc());
+    if (hipHostMalloc((void **)&b->hgather, sizeof(DevState) * capacity, hipHostMallocDefault) != hipSuccess) {
+        delete b;
+        return IRK_ERR_DEVICE;
+    }
+    for (int q = capacity - 1; q >= 0; --q) b->free_slots.push_back(q);
+    b->epoch = 0;
+    hipEventCreate(&b->ev_end);
+    *out = b;
+    return IRK_OK;
+}
+
+irk_status irk_batch_admit(irk_batch *b, irk_handle *h, const double *rhs, double *x, long long tag)
+{
+    if (!b || !h || !rhs || !x) return IRK_ERR_ARG;
+    if (!h->factored) return IRK_ERR_STATE;
+    if (b->free_slots.empty()) return IRK_ERR_NOMEM;
+    long long elems = h->T;
+    for (auto &m : b->members) elems += m.h->T;
+    if (elems > b->max_elements) return IRK_ERR_NOMEM;
+    for (auto &m : b->members)
+        if (m.h == h) return IRK_ERR_ARG;   // a handle can be in a batch once
+    if (!b->members.empty()) {
+        const irk_handle *h0 = b->members[0].h;
+        if (h0->mixed != h->mixed || h0->coupled != h->coupled || h0->sharedJ != h->sharedJ ||
+            h0->ftype != h->ftype || (h0->opt.pc == IRK_PC_NONE) != (h->opt.pc == IRK_PC_NONE))
+            return IRK_ERR_ARG;
+    }
+    irk_batch::Member m{};
+    m.h = h;
+    m.slot = b->free_slots.back();
+    b->free_slots.pop_back();
+    m.tag = tag;
+    m.x = x;
+    m.phase = 0;
+    // table entry: the handle's descriptor with rhs and x in place of its own slots
+    SysDesc d = h->hsys;
+    d.vec[SL_B] = const_cast<double *>(rhs);
+    d.vec[SL_X] = x;
+    b->htab[m.slot] = d;
+    // the batch stream waits for work already enqueued on the handle's stream
+    if (h->stream != b->stream) {
+        HIPCHK(hipEventRecord(h->ev_ready, h->stream));
+        HIPCHK(hipStreamWaitEvent(b->stream, h->ev_ready, 0));
+    }
+    hipEventCreate(&m.t0);
+    hipEventRecord(m.t0, b->stream);
+    b->members.push_back(m);
+    return IRK_OK;
+}
+
+int irk_batch_pending(const irk_batch *b) { return b ? (int)b->members.size() : 0; }
+
+// Merged work set of the given members (phase filter), items uploaded.
+static irk_status batch_workset(irk_batch *b, int phase, WorkSet &W, std::vector<int> &idx)
+{
+    std::vector<std::pair<irk_handle *, int>> mem;
+    idx.clear();
+    for (size_t q = 0; q < b->members.size(); ++q)
+        if (b->members[q].phase == phase) {
+            mem.push_back({b->members[q].h, b->members[q].slot});
+            idx.push_back((int)q);
+        }
+    build_merged(W, mem);
+    if (W.items.size() > b->max_items) return IRK_ERR_NOMEM;
+    W.dsys = b->dtab;
+    W.ditems = b->ditems;
+    if (!W.items.empty())
+        HIPCHK(hipMemcpyAsync(b->ditems, W.items.data(), sizeof(Item) * W.items.size(),
+                              hipMemcpyHostToDevice, b->stream));
+    return IRK_OK;
+}
+
+static void batch_retire_finished(irk_batch *b, std::vector<Solve> &sol, const std::vector<int> &idx)
+{
+    for (size_t q = 0; q < idx.size(); ++q) {
+        irk_batch::Member &m = b->members[idx[q]];
+        const Solve &S = sol[q];
+        m.bn = S.bn; m.rel = S.rel; m.est = S.est; m.cycles = S.cycles; m.stall = S.stall;
+        m.info = S.info;
+        if (S.finished) {
+            m.phase = 2;
+            m.status = S.status;
+        } else {
+            m.phase = 1;
+        }
+    }
+    std::vector<irk_batch::Member> keep;
+    for (auto &m : b->members) {
+        if (m.phase == 2) {
+            hipEventRecord(b->ev_end, b->stream);
+            hipEventSynchronize(b->ev_end);
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, m.t0, b->ev_end);
+            m.info.ms_solve = ms;
+            hipEventDestroy(m.t0);
+            b->free_slots.push_back(m.slot);
+            b->retired.push_back(m);
+        } else {
+            keep.push_back(m);
+        }
+    }
+    b->members.swap(keep);
+}
+
+irk_status irk_batch_advance(irk_batch *b, int cycles)
+{
+    if (!b || cycles < 1) return IRK_ERR_ARG;
+    if (b->members.empty()) return IRK_OK;
+    HIPCHK(hipMemcpyAsync(b->dtab, b->htab.data(), sizeof(SysDesc) * b->capacity,
+                          hipMemcpyHostToDevice, b->stream));
+    WorkSet W;
+    std::vector<int> idx;
+    // newly admitted members: initial residual and first cycle start
+    irk_status st = batch_workset(b, 0, W, idx);
+    if (st != IRK_OK) return st;
+    if (!idx.empty()) {
+        std::vector<Solve> sol(idx.size());
+        std::vector<Solve *> sv;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            sol[q].h = b->members[idx[q]].h;
+            sol[q].x = b->members[idx[q]].x;
+            sv.push_back(&sol[q]);
+        }
+        Ctx C{&W, b->stream, nullptr, &b->epoch};
+        st = init_systems(C, sv, b->dgather, b->hgather);
+        if (st != IRK_OK) return st;
+        batch_retire_finished(b, sol, idx);
+    }
+    for (int c = 0; c < cycles; ++c) {
+        st = batch_workset(b, 1, W, idx);
+        if (st != IRK_OK) return st;
+        if (idx.empty()) break;
+        std::vector<Solve> sol(idx.size());
+        std::vector<Solve *> sv;
+        for (size_t q = 0; q < idx.size(); ++q) {
+            const irk_batch::Member &m = b->members[idx[q]];
+            sol[q].h = m.h; sol[q].x = m.x; sol[q].bn = m.bn; sol[q].rel = m.rel; sol[q].est = m.est;
+            sol[q].cycles = m.cycles; sol[q].stall = m.stall;
+            sv.push_back(&sol[q]);
+        }
+        Ctx C{&W, b->stream, nullptr, &b->epoch};
+        st = run_cycle(C, sv, b->dgather, b->hgather);
+        if (st != IRK_OK) return st;
+        batch_retire_finished(b, sol, idx);
+    }
+    return IRK_OK;
+}
+
+irk_status irk_batch_retire(irk_batch *b, long long *tags, irk_status *status, irk_solve_info *info,
+                            int cap, int *count)
+{
+    if (!b || !count || cap < 0) return IRK_ERR_ARG;
+    const int n = std::min<int>(cap, (int)b->retired.size());
+    for (int q = 0; q < n; ++q) {
+        if (tags) tags[q] = b->retired[q].tag;
+        if (status) status[q] = b->retired[q].status;
+        if (info) info[q] = b->retired[q].info;
+    }
+    b->retired.erase(b->retired.begin(), b->retired.begin() + n);
+    *count = n;
+    return IRK_OK;
+}
+
+irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
+                             double *const *x, int count, irk_solve_info *info)
+{
+    if (!b || !h || !rhs || !x || count < 0) return IRK_ERR_ARG;
+    if (!b->members.empty() || !b->retired.empty()) return IRK_ERR_STATE;
+    for (int q = 0; q < count; ++q) {
+        irk_status st = irk_batch_admit(b, h[q], rhs[q], x[q], q);
+        if (st != IRK_OK) return st;
+    }
+    while (!b->members.empty()) {
+        irk_status st = irk_batch_advance(b, 1000000);
+        if (st != IRK_OK) return st;
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    irk_status worst = IRK_OK;
+    for (auto &m : b->retired) {
+        if (info && m.tag >= 0 && m.tag < count) info[m.tag] = m.info;
+        if (m.status != IRK_OK && worst == IRK_OK) worst = m.status;
+    }
+    b->retired.clear();
+    return worst;
+}
+
+irk_status irk_batch_destroy(irk_batch *b)
+{
+    if (!b) return IRK_ERR_ARG;
+    for (auto &m : b->members) hipEventDestroy(m.t0);
+    if (b->hgather) hipHostFree(b->hgather);
+    if (b->ev_end) hipEventDestroy(b->ev_end);
+    delete b;
     return IRK_OK;
 }
 

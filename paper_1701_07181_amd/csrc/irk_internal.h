@@ -46,8 +46,10 @@ struct DevState {
     int singular;      // 1 + element of the first singular pivot, 0 if none
     int nonfinite;
     int spin_timeout;   // a persistent sweep gave up waiting on a dependency
-    int pad[2];
-    unsigned tickets[8];   // "last workgroup" counters of the reductions
+    int iters;          // Arnoldi steps of the current solve
+    int pad;
+    double tol_abs;     // cycle ends when |g_{j+1}| <= tol_abs
+    unsigned tickets[8];   // work counters of the persistent sweeps
 };
 
 struct SysDesc {
@@ -60,8 +62,11 @@ struct SysDesc {
     int pc;        // irk_pc
     int ftype;     // FactorType of the sweep factors
     int restart;
+    int max_iters;
+    int mixed;     // 1: FP32 inner iteration inside FP64 refinement
     long long N;   // s*T*m
     double dt;
+    double rtol, inner_rtol;
     double Ainv[SMAX * SMAX];
     double dcoef[SMAX];     // diagonal mass coefficient of each stage's pivot
     // structure (device)
@@ -120,24 +125,24 @@ void launch_relayout(const double *src, void *dst, int dst_type, long long nblk,
 
 // y_slot = B x_slot   (mode 0)   or   y_slot = b_slot - B x_slot   (mode 1)
 // prec 0: FP64 (Jc, Mc); 1: FP32 copies (x read as compute type of slot).
+// skip_done: systems whose GMRES cycle has ended (st->done) do nothing.
 void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max,
                    int prec, bool sharedJ, int x_slot, int y_slot, int b_slot, int mode,
-                   int tpw, size_t shmem, hipStream_t st);
+                   int skip_done, size_t shmem, hipStream_t st);
 
 // One level of the forward sweep (L~ y = v, then y^ = P^{-1} y per element),
 // or of the backward sweep (z = y^ + P^{-1} (dt J_upper z - C z)).
 //   fp64: FP64 factors/values with double vectors; otherwise FP32 values
 //   and factors of type ftype with float vectors.
-//   v_slot: input of the forward sweep (FP64 vector, times *vscale if given);
-//   yh slot SL_YH; acc_slot >= 0 adds the backward result to that FP64 slot
-//   (x += z), out_slot >= 0 also stores z there (in the compute type).
+//   v_slot/v_index: input of the forward sweep (FP64); result in SL_YH;
+//   acc_slot >= 0 adds the backward result to that FP64 slot (x += z).
 //   pgrid > 0: one persistent launch of pgrid workgroups covers all levels
 //   (items of every level, in level order), synchronized by per-element
 //   flags that carry `epoch`; pgrid == 0: items of one level, one workgroup each.
 void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                   int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
-                  int v_slot, int v_index, int acc_slot, size_t shmem, hipStream_t st,
-                  int pgrid, unsigned epoch);
+                  int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
+                  hipStream_t st, int pgrid, unsigned epoch);
 
 // Factorization of one level.  phase 0: tasks (stage k = aux, element) build
 // P_{k,i} (and invert it when !coupled; set up cross blocks of column k when
@@ -151,27 +156,28 @@ void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int 
 // Quantize the FP64 factors to ftype (FP32 / BF16 / FP16 scaled).
 void launch_quantize(const SysDesc *dsys, const SysDesc &hsys, int ftype, hipStream_t st);
 
-// ---- Krylov (single system, FP64) ----
-// pass 0: hbuf[0..j] = V^T w;  pass 1: w -= V h1, hbuf[R+1 ..] = V^T w
-void launch_cgs(int pass, const SysDesc *dsys, const SysDesc &hsys, int j, int nblk,
-                hipStream_t st);
-// pass 2: w -= V h2, ||w||; Hessenberg column j, Givens rotation, estimate,
-// flags (done when |g_{j+1}| <= tol_abs); then v_{j+1} = w / ||w||
-void launch_givens(const SysDesc *dsys, const SysDesc &hsys, int j, double tol_abs, int nblk,
-                   hipStream_t st);
-// y = H^{-1} g over nv steps, u = V y
-void launch_cycle_end_n(const SysDesc *dsys, int nv, int nblk, hipStream_t st);
-// ||slot||: which 0 -> st->bnorm; which 1 -> start of a cycle (beta, g, flags)
-void launch_norm(const SysDesc *dsys, const SysDesc &hsys, int slot, int which, int nblk,
-                 hipStream_t st);
+// ---- Krylov (FP64; vec items: (sys, chunk, chunks); fin items: one per system) ----
+// one Arnoldi step j: CGS2 passes, Givens update, v_{j+1} = w / ||w||
+void launch_arnoldi(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int j,
+                    hipStream_t st);
+// y = H^{-1} g over the cycle's steps, u = V y
+void launch_cycle_end(const SysDesc *dsys, const Item *vec, int nvec, int restart, hipStream_t st);
+// ||slot||: which 0 -> st->bnorm; which 1 -> start of a cycle (beta, g, tolerance, flags)
+void launch_norm(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int slot,
+                 int which, hipStream_t st);
 // start a cycle from the residual in src_slot: beta = ||r||, v_0 = r / beta
-void launch_start_cycle(const SysDesc *dsys, const SysDesc &hsys, int src_slot, int nblk,
-                        hipStream_t st);
-void launch_axpy(const SysDesc *dsys, const SysDesc &hsys, int dst_slot, int src_slot,
-                 int nblk, hipStream_t st);
-void launch_copy(const SysDesc *dsys, const SysDesc &hsys, int dst_slot, int src_slot,
-                 double scale, int nblk, hipStream_t st);
-void launch_fill_zero(double *p, long long n, hipStream_t st);
+void launch_start_cycle(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin,
+                        int src_slot, hipStream_t st);
+void launch_axpy(const SysDesc *dsys, const Item *vec, int nvec, int dst_slot, int src_slot,
+                 hipStream_t st);
+// SL_YH = src_slot[src_index] in the compute type
+void launch_copy_to_yh(const SysDesc *dsys, const Item *vec, int nvec, bool fp64, int src_slot,
+                       int src_index, int skip_done, hipStream_t st);
+void launch_fill_zero_slot(const SysDesc *dsys, const Item *vec, int nvec, int slot, hipStream_t st);
+// DevState of every system of fin into out[0..nfin)
+void launch_gather_state(const SysDesc *dsys, const Item *fin, int nfin, DevState *out, hipStream_t st);
+// per-solve counters and flags to zero
+void launch_reset_state(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st);
 // export FP64 factors to the caller's row-major stage-major layout
 void launch_export(const SysDesc &hsys, double *pinv, double *cross, hipStream_t st);
 void factor_set_lds_limit(size_t bytes);

@@ -1,22 +1,30 @@
 // k_krylov.hip -- FP64 Arnoldi (classical Gram-Schmidt with one
 // re-orthogonalization, CGS2), Givens least squares and cycle bookkeeping of
-// restarted right-preconditioned GMRES, all on the device.
+// restarted right-preconditioned GMRES, on the device, for any number of
+// systems per launch.
 //
-// Each pass streams the basis once: pass 0 forms h1 = V^T w; pass 1 updates
-// w -= V h1 and, with the same loaded basis entries, forms h2 = V^T w; pass 2
-// updates w -= V h2 and forms ||w||^2.  Partial sums go to a per-workgroup
-// buffer; the last workgroup to finish (atomic ticket) adds them in a fixed
-// order, so every reduction is deterministic.  The last workgroup of pass 2
-// also applies the Givens rotations to the new Hessenberg column and updates
-// the residual estimate |g_{j+1}| and the cycle flags.
+// Work items: a vector kernel gets one item per (system, chunk); chunk c of
+// a system with nc chunks covers the elements c*256 + t, stepping nc*256.
+// Reductions write one partial per chunk; a finish kernel with one
+// workgroup per system adds them in a fixed order (deterministic, and the
+// kernel boundary orders the partials without device-wide fences).
+//
+// One Arnoldi step j (the same j for every system of a launch; systems whose
+// cycle already ended, st->done, skip):
+//   pass 0: h1 = V_{0..j}^T w
+//   pass 1: w -= V h1 and, with the same loaded basis entries, h2 = V^T w
+//   pass 2: w -= V h2 and ||w||^2; its finish kernel forms the Hessenberg
+//           column h1 + h2, applies the Givens rotations, updates the
+//           residual estimate |g_{j+1}| and sets done when it drops below the
+//           system's cycle tolerance (or on breakdown / non-finite values)
+//   scale:  v_{j+1} = w / ||w||
 #include "irk_device.h"
 
 namespace irk {
 
-// sum NV values of every thread over the workgroup; result in out[0..NV) of
-// thread 0's view (written to lds_out)
+// Sum NV values of every thread over the workgroup into lds[w*NV + p].
 template <int NV>
-__device__ __forceinline__ void wg_sum(double (&v)[NV], int nv, double *lds /*[4][NV]*/) {
+__device__ __forceinline__ void wg_sum(double (&v)[NV], int nv, double *lds) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int p = 0; p < NV; ++p) {
@@ -28,11 +36,9 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], int nv, double *lds /*[4
     __syncthreads();
 }
 
-// Reduction of the partials part[b][p] (b < nblk, p < nv) into out[p] by one
-// workgroup: every thread adds the blocks b = t, t + 256, ... for all p
-// (independent loads, all in flight), then the per-thread sums go through
-// the fixed wave/LDS tree: deterministic.  Runs in a separate kernel after
-// the pass that wrote the partials, so the kernel boundary orders them.
+// Add the partials part[b][p] (b < nblk, p < nv) in a fixed order: every
+// thread sums the blocks b = t, t + 256, ... for all p, then the fixed
+// wave/LDS tree.  One workgroup.
 template <int NVMAX>
 __device__ void reduce_partials(const SysDesc &d, int nblk, int nv, double *out) {
     __shared__ double red[4 * NVMAX];
@@ -60,13 +66,24 @@ __device__ void reduce_partials(const SysDesc &d, int nblk, int nv, double *out)
     __syncthreads();
 }
 
+__device__ __forceinline__ void store_partials(const SysDesc &d, int chunk, const double *lds,
+                                               int nv, int nvmax) {
+    for (int p = threadIdx.x; p < nv; p += NTHREADS) {
+        double a = 0.0;
+        for (int w2 = 0; w2 < NTHREADS / 64; ++w2) a += lds[w2 * nvmax + p];
+        gp(d.part)[(size_t)chunk * (RESTART_MAX + 2) + p] = a;
+    }
+}
+
 template <int NVMAX, int PASS>
-__global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sysv, int sys, int j,
-                                                  double tol_abs)
+__global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sysv,
+                                                  const Item *__restrict__ items, int j)
 {
     __shared__ double lds[4 * NVMAX];
     __shared__ double cf[NVMAX];
-    const SysDesc &d = sysv[sys];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    if (d.st->done) return;
     const long long N = d.N;
     const int nv = j + 1;
     const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[SL_V]));
@@ -80,8 +97,8 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
     double acc[NACC];
 #pragma unroll
     for (int p = 0; p < NACC; ++p) acc[p] = 0.0;
-    const long long stride = (long long)gridDim.x * NTHREADS;
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N; e += stride) {
+    const long long stride = (long long)it.count * NTHREADS;
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N; e += stride) {
         double wv = w[e];
         if (PASS == 0) {
 #pragma unroll
@@ -106,24 +123,22 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
     }
     const int nred = (PASS == 2) ? 1 : nv;
     wg_sum<NACC>(acc, nred, lds);
-    const int pstride = RESTART_MAX + 2;
-    for (int p = threadIdx.x; p < nred; p += NTHREADS) {
-        double a = 0.0;
-        for (int w2 = 0; w2 < NTHREADS / 64; ++w2) a += lds[w2 * NACC + p];
-        gp(d.part)[(size_t)blockIdx.x * pstride + p] = a;
-    }
+    store_partials(d, it.first, lds, nred, NACC);
 }
 
+// One workgroup per system: item = (sys, 0, number of chunks).
 template <int NVMAX, int PASS>
-__global__ __launch_bounds__(NTHREADS) void k_cgs_finish(const SysDesc *__restrict__ sysv, int sys,
-                                                         int j, int nblk, double tol_abs)
+__global__ __launch_bounds__(NTHREADS) void k_cgs_finish(const SysDesc *__restrict__ sysv,
+                                                         const Item *__restrict__ items, int j)
 {
     __shared__ double outv[NVMAX];
-    const SysDesc &d = sysv[sys];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    if (d.st->done) return;
     const int nv = j + 1;
     const int off2 = RESTART_MAX + 1;
     constexpr int NACC = (PASS == 2) ? 1 : NVMAX;
-    reduce_partials<NACC>(d, nblk, (PASS == 2) ? 1 : nv, outv);
+    reduce_partials<NACC>(d, it.count, (PASS == 2) ? 1 : nv, outv);
     if (PASS == 0) {
         for (int p = threadIdx.x; p < nv; p += NTHREADS) d.hbuf[p] = outv[p];
         return;
@@ -158,52 +173,60 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs_finish(const SysDesc *__restri
         st->est = fabs(d.g[j + 1]);
         st->j = j;
         st->rnorm2 = hn;
+        st->iters += 1;
         if (!isfinite(hn) || !isfinite(r)) { st->nonfinite = 1; st->done = 1; }
         if (!(hn > 0.0)) { st->breakdown = 1; st->done = 1; }
-        if (st->est <= tol_abs) st->done = 1;
+        if (st->est <= st->tol_abs || j + 1 >= d.restart || st->iters >= d.max_iters) st->done = 1;
     }
 }
 
-// dst = src / *div  (div from device memory; a zero divisor writes zeros)
-__global__ __launch_bounds__(NTHREADS) void k_scale(const SysDesc *__restrict__ sysv, int sys,
-                                                    int dst_slot, int dst_index, int src_slot,
-                                                    int use_norm)
+// dst = src / st->rnorm2 (zeros if that is not positive); skip_done: the
+// system's cycle has ended (the next basis vector is not needed)
+__global__ __launch_bounds__(NTHREADS) void k_scale(const SysDesc *__restrict__ sysv,
+                                                    const Item *__restrict__ items, int dst_slot,
+                                                    int dst_index, int src_slot, int skip_done)
 {
-    const SysDesc &d = sysv[sys];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    if (skip_done && d.st->done) return;
     const long long N = d.N;
     GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot])) + (long long)dst_index * N;
     const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
     const double dv = d.st->rnorm2;
-    const double inv = (dv > 0.0 && use_norm) ? 1.0 / dv : 0.0;
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
-         e += (long long)gridDim.x * NTHREADS)
+    const double inv = (dv > 0.0) ? 1.0 / dv : 0.0;
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS)
         dst[e] = src[e] * inv;
 }
 
 // partial sums of ||slot||^2
-__global__ __launch_bounds__(NTHREADS) void k_norm(const SysDesc *__restrict__ sysv, int sys,
-                                                   int slot)
+__global__ __launch_bounds__(NTHREADS) void k_norm(const SysDesc *__restrict__ sysv,
+                                                   const Item *__restrict__ items, int slot)
 {
     __shared__ double lds[4];
-    const SysDesc &d = sysv[sys];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
     const long long N = d.N;
     const GAS double *x = gp(reinterpret_cast<const double *>(d.vec[slot]));
     double a[1] = {0.0};
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
-         e += (long long)gridDim.x * NTHREADS)
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS)
         a[0] += x[e] * x[e];
     wg_sum<1>(a, 1, lds);
-    if (threadIdx.x == 0)
-        gp(d.part)[(size_t)blockIdx.x * (RESTART_MAX + 2)] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    store_partials(d, it.first, lds, 1, 1);
 }
 
-// which = 0: bnorm;  which = 1: start of a cycle (beta, g, flags)
-__global__ __launch_bounds__(NTHREADS) void k_norm_finish(const SysDesc *__restrict__ sysv, int sys,
-                                                          int which, int nblk)
+// which = 0: ||b|| into st->bnorm;  which = 1: start of a cycle from the
+// residual norm: beta, g = (beta, 0, ...), step counter and flags reset, and
+// the cycle tolerance |g_{j+1}| <= tol_abs (FP64: rtol ||b||; refinement
+// inner cycles: max(inner_rtol beta, rtol ||b||))
+__global__ __launch_bounds__(NTHREADS) void k_norm_finish(const SysDesc *__restrict__ sysv,
+                                                          const Item *__restrict__ items, int which)
 {
     __shared__ double outv[1];
-    const SysDesc &d = sysv[sys];
-    reduce_partials<1>(d, nblk, 1, outv);
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    reduce_partials<1>(d, it.count, 1, outv);
     if (threadIdx.x == 0) {
         const double nrm = sqrt(outv[0]);
         DevState *st = d.st;
@@ -217,35 +240,40 @@ __global__ __launch_bounds__(NTHREADS) void k_norm_finish(const SysDesc *__restr
             st->done = 0;
             st->breakdown = 0;
             st->est = nrm;
+            const double t0 = d.rtol * st->bnorm;
+            st->tol_abs = d.mixed ? fmax(d.inner_rtol * nrm, t0) : t0;
             d.g[0] = nrm;
             for (int q = 1; q <= d.restart; ++q) d.g[q] = 0.0;
         }
     }
 }
 
-// y = H^{-1} g over nv steps (every workgroup solves the small system), u = V y
+// y = H^{-1} g over the nv = st->j + 1 steps of the cycle (every workgroup
+// solves the small triangular system), u = V y
 template <int NVMAX>
-__global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restrict__ sysv, int sys,
-                                                        int nv)
+__global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restrict__ sysv,
+                                                        const Item *__restrict__ items)
 {
     __shared__ double ys[NVMAX];
-    const SysDesc &d = sysv[sys];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
     const long long N = d.N;
     const int R = d.restart;
+    const int nv = d.st->j + 1;
     if (threadIdx.x == 0) {
         for (int i = nv - 1; i >= 0; --i) {
             double t = d.g[i];
             for (int k = i + 1; k < nv; ++k) t -= d.H[i * R + k] * ys[k];
             ys[i] = t / d.H[i * R + i];
         }
-        if (blockIdx.x == 0)
+        if (it.first == 0)
             for (int i = 0; i < nv; ++i) d.y[i] = ys[i];
     }
     __syncthreads();
     const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[SL_V]));
     GAS double *u = gp(reinterpret_cast<double *>(d.vec[SL_U]));
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
-         e += (long long)gridDim.x * NTHREADS) {
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS) {
         double a = 0.0;
 #pragma unroll
         for (int p = 0; p < NVMAX; ++p)
@@ -254,47 +282,86 @@ __global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restric
     }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_copy(const SysDesc *__restrict__ sysv, int sys,
-                                                   int dst_slot, int src_slot, double scale)
+// dst_slot (FP64) += src_slot (FP64)
+__global__ __launch_bounds__(NTHREADS) void k_axpy(const SysDesc *__restrict__ sysv,
+                                                   const Item *__restrict__ items, int dst_slot,
+                                                   int src_slot)
 {
-    const SysDesc &d = sysv[sys];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
     const long long N = d.N;
     GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot]));
     const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
-         e += (long long)gridDim.x * NTHREADS)
-        dst[e] = scale * src[e];
-}
-
-__global__ __launch_bounds__(NTHREADS) void k_axpy(const SysDesc *__restrict__ sysv, int sys,
-                                                   int dst_slot, int src_slot)
-{
-    const SysDesc &d = sysv[sys];
-    const long long N = d.N;
-    GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot]));
-    const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < N;
-         e += (long long)gridDim.x * NTHREADS)
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS)
         dst[e] += src[e];
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_fill_zero(double *pp, long long n)
+// SL_YH (compute type TD) = src_slot[src_index] (FP64)
+template <typename TD>
+__global__ __launch_bounds__(NTHREADS) void k_copy_yh(const SysDesc *__restrict__ sysv,
+                                                      const Item *__restrict__ items, int src_slot,
+                                                      int src_index, int skip_done)
 {
-    GAS double *p = gp(pp);
-    for (long long e = (long long)blockIdx.x * NTHREADS + threadIdx.x; e < n;
-         e += (long long)gridDim.x * NTHREADS)
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    if (skip_done && d.st->done) return;
+    const long long N = d.N;
+    GAS TD *dst = gp(reinterpret_cast<TD *>(d.vec[SL_YH]));
+    const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot])) + (long long)src_index * N;
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS)
+        dst[e] = (TD)src[e];
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_fill_zero_slot(const SysDesc *__restrict__ sysv,
+                                                             const Item *__restrict__ items, int slot)
+{
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    const long long N = d.N;
+    GAS double *p = gp(reinterpret_cast<double *>(d.vec[slot]));
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS)
         p[e] = 0.0;
+}
+
+// copy every system's DevState into one contiguous array (items: one per system)
+__global__ void k_gather_state(const SysDesc *__restrict__ sysv, const Item *__restrict__ items,
+                               int n, DevState *out)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const SysDesc &d = sysv[items[q].sys];
+    const int *src = reinterpret_cast<const int *>(d.st);
+    int *dst = reinterpret_cast<int *>(out + q);
+    for (int w = 0; w < (int)(sizeof(DevState) / sizeof(int)); ++w) dst[w] = src[w];
+}
+
+// reset the per-solve counters of every system (items: one per system)
+__global__ void k_reset_state(const SysDesc *__restrict__ sysv, const Item *__restrict__ items, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    DevState *st = sysv[items[q].sys].st;
+    st->iters = 0;
+    st->nonfinite = 0;
+    st->spin_timeout = 0;
+    st->breakdown = 0;
+    st->done = 0;
+    st->j = -1;
 }
 
 // ---------------------------------------------------------------------------
 template <int PASS>
-static void cgs_dispatch(const SysDesc *dsys, int j, int nblk, double tol, hipStream_t st) {
+static void cgs_dispatch(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin,
+                         int j, hipStream_t st) {
     const int nv = j + 1;
-    dim3 g(nblk), b(NTHREADS), one(1);
+    dim3 b(NTHREADS);
 #define CGS(NV)                                                                              \
     do {                                                                                     \
-        hipLaunchKernelGGL((k_cgs<NV, PASS>), g, b, 0, st, dsys, 0, j, tol);                \
-        hipLaunchKernelGGL((k_cgs_finish<NV, PASS>), one, b, 0, st, dsys, 0, j, nblk, tol); \
+        hipLaunchKernelGGL((k_cgs<NV, PASS>), dim3(nvec), b, 0, st, dsys, vec, j);          \
+        hipLaunchKernelGGL((k_cgs_finish<NV, PASS>), dim3(nfin), b, 0, st, dsys, fin, j);   \
     } while (0)
     if (nv <= 8) CGS(8);
     else if (nv <= 16) CGS(16);
@@ -303,69 +370,70 @@ static void cgs_dispatch(const SysDesc *dsys, int j, int nblk, double tol, hipSt
 #undef CGS
 }
 
-void launch_cgs(int pass, const SysDesc *dsys, const SysDesc &hsys, int j, int nblk, hipStream_t st)
+void launch_arnoldi(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int j,
+                    hipStream_t st)
 {
-    (void)hsys;
-    if (pass == 0) cgs_dispatch<0>(dsys, j, nblk, 0.0, st);
-    else if (pass == 1) cgs_dispatch<1>(dsys, j, nblk, 0.0, st);
-}
-
-void launch_givens(const SysDesc *dsys, const SysDesc &hsys, int j, double tol_abs, int nblk,
-                   hipStream_t st)
-{
-    cgs_dispatch<2>(dsys, j, nblk, tol_abs, st);
+    cgs_dispatch<0>(dsys, vec, nvec, fin, nfin, j, st);
+    cgs_dispatch<1>(dsys, vec, nvec, fin, nfin, j, st);
+    cgs_dispatch<2>(dsys, vec, nvec, fin, nfin, j, st);
     // v_{j+1} = w / ||w||
-    hipLaunchKernelGGL(k_scale, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, (int)SL_V, j + 1,
+    hipLaunchKernelGGL(k_scale, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, (int)SL_V, j + 1,
                        (int)SL_W, 1);
-    (void)hsys;
 }
 
-void launch_cycle_end_n(const SysDesc *dsys, int nv, int nblk, hipStream_t st)
+void launch_cycle_end(const SysDesc *dsys, const Item *vec, int nvec, int restart, hipStream_t st)
 {
-    dim3 g(nblk), b(NTHREADS);
-    if (nv <= 8) hipLaunchKernelGGL((k_cycle_end<8>), g, b, 0, st, dsys, 0, nv);
-    else if (nv <= 16) hipLaunchKernelGGL((k_cycle_end<16>), g, b, 0, st, dsys, 0, nv);
-    else if (nv <= 32) hipLaunchKernelGGL((k_cycle_end<32>), g, b, 0, st, dsys, 0, nv);
-    else hipLaunchKernelGGL((k_cycle_end<64>), g, b, 0, st, dsys, 0, nv);
+    dim3 g(nvec), b(NTHREADS);
+    if (restart <= 8) hipLaunchKernelGGL((k_cycle_end<8>), g, b, 0, st, dsys, vec);
+    else if (restart <= 16) hipLaunchKernelGGL((k_cycle_end<16>), g, b, 0, st, dsys, vec);
+    else if (restart <= 32) hipLaunchKernelGGL((k_cycle_end<32>), g, b, 0, st, dsys, vec);
+    else hipLaunchKernelGGL((k_cycle_end<64>), g, b, 0, st, dsys, vec);
 }
 
-void launch_norm(const SysDesc *dsys, const SysDesc &hsys, int slot, int which, int nblk,
+void launch_norm(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int slot,
+                 int which, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_norm, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, slot);
+    hipLaunchKernelGGL(k_norm_finish, dim3(nfin), dim3(NTHREADS), 0, st, dsys, fin, which);
+}
+
+void launch_start_cycle(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin,
+                        int src_slot, hipStream_t st)
+{
+    launch_norm(dsys, vec, nvec, fin, nfin, src_slot, 1, st);
+    hipLaunchKernelGGL(k_scale, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, (int)SL_V, 0, src_slot, 0);
+}
+
+void launch_axpy(const SysDesc *dsys, const Item *vec, int nvec, int dst_slot, int src_slot,
                  hipStream_t st)
 {
-    (void)hsys;
-    hipLaunchKernelGGL(k_norm, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, slot);
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NTHREADS), 0, st, dsys, 0, which, nblk);
+    hipLaunchKernelGGL(k_axpy, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, dst_slot, src_slot);
 }
 
-void launch_start_cycle(const SysDesc *dsys, const SysDesc &hsys, int src_slot, int nblk,
-                        hipStream_t st)
+void launch_copy_to_yh(const SysDesc *dsys, const Item *vec, int nvec, bool fp64, int src_slot,
+                       int src_index, int skip_done, hipStream_t st)
 {
-    (void)hsys;
-    hipLaunchKernelGGL(k_norm, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, src_slot);
-    hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(NTHREADS), 0, st, dsys, 0, 1, nblk);
-    hipLaunchKernelGGL(k_scale, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, (int)SL_V, 0, src_slot, 1);
+    if (fp64)
+        hipLaunchKernelGGL(k_copy_yh<double>, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, src_slot,
+                           src_index, skip_done);
+    else
+        hipLaunchKernelGGL(k_copy_yh<float>, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, src_slot,
+                           src_index, skip_done);
 }
 
-void launch_axpy(const SysDesc *dsys, const SysDesc &hsys, int dst_slot, int src_slot, int nblk,
-                 hipStream_t st)
+void launch_fill_zero_slot(const SysDesc *dsys, const Item *vec, int nvec, int slot, hipStream_t st)
 {
-    (void)hsys;
-    hipLaunchKernelGGL(k_axpy, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, dst_slot, src_slot);
+    hipLaunchKernelGGL(k_fill_zero_slot, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, slot);
 }
 
-void launch_copy(const SysDesc *dsys, const SysDesc &hsys, int dst_slot, int src_slot,
-                 double scale, int nblk, hipStream_t st)
+void launch_gather_state(const SysDesc *dsys, const Item *fin, int nfin, DevState *out, hipStream_t st)
 {
-    (void)hsys;
-    hipLaunchKernelGGL(k_copy, dim3(nblk), dim3(NTHREADS), 0, st, dsys, 0, dst_slot, src_slot, scale);
+    hipLaunchKernelGGL(k_gather_state, dim3((nfin + 63) / 64), dim3(64), 0, st, dsys, fin, nfin, out);
 }
 
-void launch_fill_zero(double *p, long long n, hipStream_t st)
+void launch_reset_state(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st)
 {
-    if (n <= 0) return;
-    long long nb = (n + NTHREADS - 1) / NTHREADS;
-    if (nb > 2048) nb = 2048;
-    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(NTHREADS), 0, st, p, n);
+    hipLaunchKernelGGL(k_reset_state, dim3((nfin + 63) / 64), dim3(64), 0, st, dsys, fin, nfin);
 }
 
 }  // namespace irk

@@ -19,11 +19,13 @@ namespace irk {
 template <int S, typename TM, typename TC, bool SHJ, int MODE, typename TX>
 __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__ sysv,
                                                      const Item *__restrict__ items,
-                                                     int x_slot, int y_slot, int b_slot)
+                                                     int x_slot, int y_slot, int b_slot,
+                                                     int skip_done)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
+    if (skip_done && d.st->done) return;
     const int s = d.s, m = d.m, T = d.T;
     constexpr int V = Vec16<TM>::V;
     const int ld = ld_of<TM>(d);
@@ -156,12 +158,12 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
 template <int S>
 static void dispatch_matvec(const SysDesc *dsys, const Item *items, int nitems, int prec,
                             bool sharedJ, int x_slot, int y_slot, int b_slot, int mode,
-                            size_t shmem, hipStream_t st)
+                            int skip_done, size_t shmem, hipStream_t st)
 {
     dim3 grid(nitems), block(NTHREADS);
 #define MV_LAUNCH(TM, TC, SH, MD, TX) \
     hipLaunchKernelGGL((k_matvec<S, TM, TC, SH, MD, TX>), grid, block, shmem, st, dsys, items, \
-                       x_slot, y_slot, b_slot)
+                       x_slot, y_slot, b_slot, skip_done)
     if (prec == 0) {
         if (sharedJ) { if (mode == 0) MV_LAUNCH(double, double, true, 0, double); else MV_LAUNCH(double, double, true, 1, double); }
         else { if (mode == 0) MV_LAUNCH(double, double, false, 0, double); else MV_LAUNCH(double, double, false, 1, double); }
@@ -174,16 +176,16 @@ static void dispatch_matvec(const SysDesc *dsys, const Item *items, int nitems, 
 }
 
 void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max, int prec,
-                   bool sharedJ, int x_slot, int y_slot, int b_slot, int mode, int tpw,
+                   bool sharedJ, int x_slot, int y_slot, int b_slot, int mode, int skip_done,
                    size_t shmem, hipStream_t st)
 {
-    (void)tpw;
+    if (nitems <= 0) return;
     switch (s_max) {
-    case 1: dispatch_matvec<1>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, shmem, st); break;
-    case 2: dispatch_matvec<2>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, shmem, st); break;
-    case 3: dispatch_matvec<3>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, shmem, st); break;
-    case 4: dispatch_matvec<4>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, shmem, st); break;
-    default: dispatch_matvec<5>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, shmem, st); break;
+    case 1: dispatch_matvec<1>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, skip_done, shmem, st); break;
+    case 2: dispatch_matvec<2>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, skip_done, shmem, st); break;
+    case 3: dispatch_matvec<3>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, skip_done, shmem, st); break;
+    case 4: dispatch_matvec<4>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, skip_done, shmem, st); break;
+    default: dispatch_matvec<5>(dsys, items, nitems, prec, sharedJ, x_slot, y_slot, b_slot, mode, skip_done, shmem, st); break;
     }
 }
 

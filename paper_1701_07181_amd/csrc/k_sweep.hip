@@ -293,10 +293,12 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
 template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
 __global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ sysv,
                                                     const Item *__restrict__ items,
-                                                    int v_slot, int v_index, int acc_slot)
+                                                    int v_slot, int v_index, int acc_slot,
+                                                    int skip_done)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[blockIdx.x];
+    if (skip_done && sysv[it.sys].st->done) return;
     sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD>(sysv[it.sys], it, v_slot, v_index, acc_slot, smem_raw);
 }
 
@@ -315,7 +317,8 @@ template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, 
 __global__ __launch_bounds__(NTHREADS) void k_sweep_persist(const SysDesc *__restrict__ sysv,
                                                             const Item *__restrict__ items,
                                                             int nitems, int v_slot, int v_index,
-                                                            int acc_slot, unsigned epoch)
+                                                            int acc_slot, int skip_done,
+                                                            unsigned epoch)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int tk;
@@ -336,6 +339,10 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_persist(const SysDesc *__res
             return;
         }
         const Item it = items[t];
+        if (skip_done && d.st->done) {   // uniform: one system per launch
+            __syncthreads();             // everybody has read tk before it changes
+            continue;
+        }
         const int team = NTHREADS / it.aux;
         const int tm = threadIdx.x / team, tid = threadIdx.x - tm * team;
         if (tid == 0 && tm < it.count) {
@@ -365,17 +372,17 @@ __global__ __launch_bounds__(NTHREADS) void k_sweep_persist(const SysDesc *__res
 template <int S, typename TJ, typename TF, typename TC>
 static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                            bool coupled, bool sharedJ, int v_slot, int v_index, int acc_slot,
-                           size_t shmem, hipStream_t st, int pgrid, unsigned epoch)
+                           int skip_done, size_t shmem, hipStream_t st, int pgrid, unsigned epoch)
 {
     dim3 grid(pgrid > 0 ? pgrid : nitems), block(NTHREADS);
 #define SW(C, SH, F)                                                                             \
     do {                                                                                         \
         if (pgrid > 0)                                                                           \
             hipLaunchKernelGGL((k_sweep_persist<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, \
-                               dsys, items, nitems, v_slot, v_index, acc_slot, epoch);           \
+                               dsys, items, nitems, v_slot, v_index, acc_slot, skip_done, epoch); \
         else                                                                                     \
             hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, dsys,   \
-                               items, v_slot, v_index, acc_slot);                                \
+                               items, v_slot, v_index, acc_slot, skip_done);                     \
     } while (0)
     if (forward) {
         if (coupled) { if (sharedJ) SW(true, true, true); else SW(true, false, true); }
@@ -390,34 +397,36 @@ static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items,
 template <int S>
 static void launch_sweep_s(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                            bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
-                           int v_index, int acc_slot, size_t shmem, hipStream_t st, int pgrid,
-                           unsigned epoch)
+                           int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st,
+                           int pgrid, unsigned epoch)
 {
     if (fp64) {
         launch_sweep_t<S, double, double, double>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                  v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
+                                                  v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
     } else if (ftype == FT_F32) {
         launch_sweep_t<S, float, float, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                               v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
+                                               v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
     } else if (ftype == FT_BF16) {
         launch_sweep_t<S, float, bf16s, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                               v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
+                                               v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
     } else {
         launch_sweep_t<S, float, f16s, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                              v_slot, v_index, acc_slot, shmem, st, pgrid, epoch);
+                                              v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
     }
 }
 
 void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems, int s_max,
                   bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot, int v_index,
-                  int acc_slot, size_t shmem, hipStream_t st, int pgrid, unsigned epoch)
+                  int acc_slot, int skip_done, size_t shmem, hipStream_t st, int pgrid,
+                  unsigned epoch)
 {
+    if (nitems <= 0) return;
     switch (s_max) {
-    case 1: launch_sweep_s<1>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
-    case 2: launch_sweep_s<2>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
-    case 3: launch_sweep_s<3>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
-    case 4: launch_sweep_s<4>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
-    default: launch_sweep_s<5>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, shmem, st, pgrid, epoch); break;
+    case 1: launch_sweep_s<1>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
+    case 2: launch_sweep_s<2>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
+    case 3: launch_sweep_s<3>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
+    case 4: launch_sweep_s<4>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
+    default: launch_sweep_s<5>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
     }
 }
 
