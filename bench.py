@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--N", type=int, default=64, help="mesh side (64 = the full workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around kernels")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the "
+                         "known-size kernel that scales the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -70,6 +73,15 @@ def main():
     import paper_1701_07181_amd as irk
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
+        return
     t0 = time.time()
     sy = dgsynth.config_system("cfg1", dt=args.dt, N=args.N)
     print(f"# generated T={sy.T} m={sy.m} s={sy.s} nnzb={sy.nnzb} in {time.time()-t0:.1f}s",
@@ -88,9 +100,9 @@ def main():
 
     for _ in range(args.warmup):
         info = step()
+        print(f"# warmup: iters={info['iters']} rel_res={info['rel_res_true']:.2e}",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    print(f"# warmup done: iters={info['iters']} rel_res={info['rel_res_true']:.2e}",
-          file=sys.stderr, flush=True)
     if not args.no_profile:
         solver.profile(True)
     lat = []
@@ -160,7 +172,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"cfg1: s=3 Radau IIA, periodic {args.N}x{args.N} quad mesh "
+        "config": {"workload": f"s=3 Radau IIA, periodic {args.N}x{args.N} quad mesh "
                                f"(T={sy.T}), m={sy.m}, shared J, FP64, {args.pc} block ILU(0), "
                                f"GMRES(30), rtol 1e-10, dt={args.dt}",
                    "s": sy.s, "T": sy.T, "m": sy.m, "nnzb": sy.nnzb, "pc": args.pc,

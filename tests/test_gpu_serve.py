@@ -1,0 +1,46 @@
+"""Serving: requests of different sizes arrive while others iterate; each
+served result equals the result of solving the same system alone (bitwise),
+re-used operators are not set up again, and every request completes."""
+import numpy as np
+import pytest
+
+import dgsynth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def test_served_results_equal_solo():
+    import paper_1701_07181_amd as irk
+    from paper_1701_07181_amd.serve import Request, Server, latency_stats
+
+    stream = dgsynth.serve_requests(16, seed=4100, N2max=10, N3max=4, reuse_frac=0.3)
+    opts = irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="fp32",
+                       rtol=1e-8, restart=10)
+    systems = {}
+    reqs = []
+    for rid, (spec, reuse_of, rhs_seed) in enumerate(stream):
+        op = rid if reuse_of is None else reuse_of
+        if op not in systems:
+            sy = spec.build()
+            sy.J = torch.from_numpy(sy.J).cuda()
+            sy.M = torch.from_numpy(sy.M).cuda()
+            systems[op] = sy
+        sy = systems[op]
+        rhs = torch.from_numpy(dgsynth.fresh_rhs(rhs_seed, sy.s, sy.T, sy.m)).cuda()
+        reqs.append(Request(rid, op, sy, rhs, arrival=0.002 * rid))
+    srv = Server(opts, capacity=4, max_elements=1 << 16, budget_bytes=8 << 30)
+    results = srv.run(reqs)
+    stats = latency_stats(results)
+    srv.close()
+    print(stats, flush=True)
+    assert len(results) == len(reqs) and stats["converged"] == len(reqs)
+    assert stats["reused"] >= 1
+    for r in results:
+        sy = systems[r.op_id]
+        solo = irk.Solver(sy, opts)
+        solo.factor()
+        x, info = solo.solve(reqs[r.rid].rhs)
+        assert info["iters"] == r.info["iters"], (r.rid, info["iters"], r.info["iters"])
+        assert torch.equal(x, r.x), r.rid
+        solo.close()
