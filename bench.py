@@ -40,11 +40,36 @@ def matvec_bytes(s, T, m, nnzb, nJ=1, w=8):
 
 def sweep_bytes(s, T, m, nnzb, coupled, w=8):
     """Algorithmic bytes of one preconditioner application (both sweeps):
-    off-diagonal Jacobian blocks once, every pivot inverse twice, the
-    cross-stage blocks twice (coupled), and four stage-vector passes."""
+    off-diagonal Jacobian blocks once (lower ones forward, upper ones
+    backward), every pivot inverse twice, each cross-stage block once (C_kl
+    with l < k forward, l > k backward), and four stage-vector passes."""
     r_blocks = nnzb - T
-    cross = s * (s - 1) * T * m * m * w * 2 if coupled and s > 1 else 0
+    cross = s * (s - 1) * T * m * m * w if coupled and s > 1 else 0
     return r_blocks * m * m * w + 2 * s * T * m * m * w + cross + 4 * s * T * m * 8
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_matvec_s3_64x64_m64_hbm_traffic.txt")
+TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_matvec.hip", "paper_1701_07181_amd/csrc/irk_device.h"]
+
+
+def measured_traffic():
+    """HBM bytes per k_matvec launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a known-size copy), or None
+    when the kernel sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in txt.splitlines()
+                if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    h = hashlib.sha256()
+    for p in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    if vals.get("source_sha256", "").split()[0:1] != [h.hexdigest()]:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def main():
@@ -131,7 +156,8 @@ def main():
         mv_ms = prof["matvec_ms"] / prof["matvec_count"]
         ach = mv_bytes / (mv_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if args.N == 64 else None,
                 "kernel": "k_matvec (BSR multi-stage matvec, FP64)",
                 "avg_launch_us": round(mv_ms * 1e3, 2), "launches": prof["matvec_count"],
                 "bytes_per_launch": mv_bytes}
