@@ -2,6 +2,7 @@
 // workspace plan, and the factor / GMRES drivers that enqueue the kernels.
 #include "irk.h"
 #include "irk_internal.h"
+#include "dense64.h"
 
 #include <algorithm>
 #include <cmath>
@@ -879,8 +880,11 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     }
     {
         const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
-        const size_t gm = sizeof(double) * 2 * 64 * 64;
-        h->shm_fac = std::max(gj, gm);
+        // m <= 64: matrix-core products and register Gauss-Jordan (dense64.h);
+        // larger blocks: LDS-tiled products and LDS Gauss-Jordan
+        const size_t gm = (m <= 64) ? sizeof(double) * (size_t)D64_LDS_DOUBLES
+                                    : sizeof(double) * 2 * 64 * 64;
+        h->shm_fac = (m <= 64) ? gm : std::max(gj, gm);
     }
     const size_t lds_max = 160 * 1024;
     if (h->shm_fac > lds_max || W.shm_mv64 > lds_max || W.shm_sw64 > lds_max ||

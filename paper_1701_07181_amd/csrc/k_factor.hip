@@ -23,6 +23,7 @@
 // column k for the coupled form).  Phase 1 (coupled only) -- one workgroup
 // per element: the stage rounds above.
 #include "irk_device.h"
+#include "dense64.h"
 
 namespace irk {
 
@@ -237,130 +238,17 @@ __device__ __forceinline__ int wg_invert(double *gptr, int m, int ld, double *ld
     return bad;
 }
 
-// ---------------------------------------------------------------------------
-// Register-tiled Gauss-Jordan for m <= 64 on the augmented matrix [Q | I]
-// (Q = memory image of the block, as above), with implicit partial
-// pivoting: at step c the pivot is the unused row p with the largest
-// |Q(p, c)|; row p is scaled and column c is eliminated from every other
-// row.  The left half ends as a permutation Pi (Pi e_c = e_{p_c}) and the
-// right half as Pi Q^{-1}, so row c of Q^{-1} is row p_c of the right half.
-// Thread (tx, ty) keeps rows 4tx..4tx+3 and columns 8ty..8ty+7 of the
-// 64 x 128 augmented matrix in registers; per step the pivot row and the
-// pivot column go through LDS (two barriers).  Rows/columns >= m are an
-// identity padding that never takes part.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int wg_invert64(double *gptr, int m, int ld, double *lds)
+// Block product: the matrix-core path for m <= 64, the LDS-tiled one above.
+__device__ __forceinline__ void blk_gemm(int m, int ld, double alpha, const double *A, const double *B,
+                                         bool acc, double *C, double *lds)
 {
-    GAS double *g = gp(gptr);
-    double *prow = lds;                               // [128]
-    double *pcol = lds + 128;                         // [64]
-    int *sh = reinterpret_cast<int *>(lds + 192);     // [0] pivot row, [1] bad, [2..65] row -> step
-    const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
-    const int r0 = 4 * tx, c0 = 8 * ty;
-    double a[4][8];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int gr = r0 + r, gc = c0 + j;
-            double v;
-            if (gc < 64) v = (gr < m && gc < m) ? g[(size_t)gr * ld + gc] : (gr == gc ? 1.0 : 0.0);
-            else v = (gr == gc - 64) ? 1.0 : 0.0;
-            a[r][j] = v;
-        }
-    if (t == 0) sh[1] = 0;
-    unsigned long long used = 0ull;
-    for (int c = 0; c < m; ++c) {
-        // (1) pivot search in column c by the 16 threads of its column tile
-        if (ty == (c >> 3)) {
-            const int cc = c & 7;
-            double best = -1.0;
-            int bi = 64;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gr = r0 + r;
-                double v = -1.0;
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (j == cc) v = fabs(a[r][j]);
-                if (gr < m && !((used >> gr) & 1ull) && v > best) { best = v; bi = gr; }
-            }
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 16);
-                const int oi = __shfl_xor(bi, o, 16);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if (tx == 0) {
-                sh[0] = bi;
-                if (!(best > 0.0) || !isfinite(best)) sh[1] = 1;
-            }
-        }
-        __syncthreads();
-        int p = sh[0];
-        if (p >= 64) p = c;             // no usable pivot: flagged above; keep going so every
-                                        // thread runs the same barriers (result is discarded)
-        used |= 1ull << p;
-        // (2) publish pivot row p and column c
-        if (tx == (p >> 2)) {
-            const int pr = p & 3;
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r == pr)
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) prow[c0 + j] = a[r][j];
-        }
-        if (ty == (c >> 3)) {
-            const int cc = c & 7;
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j == cc)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) pcol[r0 + r] = a[r][j];
-        }
-        if (t == 0) sh[2 + p] = c;
-        __syncthreads();
-        // (3) scale row p, eliminate column c elsewhere
-        const double pinv = 1.0 / prow[c];
-        double pr8[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) pr8[j] = prow[c0 + j] * pinv;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            if (r0 + r == p) {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) a[r][j] = pr8[j];
-            } else {
-                const double f = pcol[r0 + r];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) a[r][j] -= f * pr8[j];
-            }
-        }
-    }
-    __syncthreads();
-    const int bad = sh[1];
-    // row r of the right half is row sh[2 + r] of Q^{-1}
-    if (ty >= 8) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int gr = r0 + r;
-            if (gr >= m) continue;
-            const int dst = sh[2 + gr];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int gc = c0 - 64 + j;
-                if (gc < m) g[(size_t)dst * ld + gc] = a[r][j];
-            }
-        }
-    }
-    __syncthreads();
-    return bad;
+    if (m <= 64) d64_gemm(m, ld, alpha, A, B, acc, C, lds);
+    else wg_gemm(m, ld, alpha, A, B, acc, C, lds);
 }
 
 __device__ __forceinline__ int wg_inverse(double *g, int m, int ld, double *lds)
 {
-    return (m <= 64) ? wg_invert64(g, m, ld, lds) : wg_invert(g, m, ld, lds);
+    return (m <= 64) ? d64_invert(g, m, ld, lds) : wg_invert(g, m, ld, lds);
 }
 
 __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
@@ -402,8 +290,8 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict
     for (int p = p0; p < pd; ++p) {
         const long long j = col_idx[p];
         const double *Pinv_j = d.P64 + (j * s + k) * bs;
-        wg_gemm(m, ld, 1.0, Pinv_j, Jk + (long long)tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
-        wg_gemm(m, ld, -dt * dt, Jk + (long long)p * bs, X, true, Pk, lds);           // -= dt^2 J_ij X
+        blk_gemm(m, ld, 1.0, Pinv_j, Jk + (long long)tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
+        blk_gemm(m, ld, -dt * dt, Jk + (long long)p * bs, X, true, Pk, lds);           // -= dt^2 J_ij X
     }
     if (!COUPLED) {
         if (wg_inverse(Pk, m, ld, lds)) flag_singular(d, i);
@@ -435,8 +323,8 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict
         if (k == 0) {
             // every cross block is still A^{-1}_kl M_i: with X = M_i P_0^{-1} M_i,
             //   P_l  -= A^{-1}_l0 A^{-1}_0l X,   C_lq -= A^{-1}_l0 A^{-1}_0q X
-            wg_gemm(m, ld, 1.0, Mi, P(0), false, L, lds);
-            wg_gemm(m, ld, 1.0, L, Mi, false, X, lds);
+            blk_gemm(m, ld, 1.0, Mi, P(0), false, L, lds);
+            blk_gemm(m, ld, 1.0, L, Mi, false, X, lds);
             for (int l = 1; l < s; ++l)
                 for (int q = 1; q < s; ++q) {
                     double *D = (q == l) ? P(l) : C(l, q);
@@ -447,11 +335,11 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict
             continue;
         }
         for (int l = k + 1; l < s; ++l) {
-            wg_gemm(m, ld, 1.0, C(l, k), P(k), false, L, lds);          // L = C_lk P_k^{-1}
-            wg_gemm(m, ld, -1.0, L, C(k, l), true, P(l), lds);          // P_l -= L C_kl
+            blk_gemm(m, ld, 1.0, C(l, k), P(k), false, L, lds);          // L = C_lk P_k^{-1}
+            blk_gemm(m, ld, -1.0, L, C(k, l), true, P(l), lds);          // P_l -= L C_kl
             for (int q = k + 1; q < s; ++q) {
                 if (q == l) continue;
-                wg_gemm(m, ld, -1.0, L, C(k, q), true, C(l, q), lds);   // C_lq -= L C_kq
+                blk_gemm(m, ld, -1.0, L, C(k, q), true, C(l, q), lds);   // C_lq -= L C_kq
             }
         }
     }
