@@ -211,9 +211,43 @@ int pick_tpw(int ld, int V)
     return tpw;
 }
 
+// Register budget of the prefetching sweep: the pivot blocks (and, coupled,
+// the cross blocks one sweep reads) of an element plus the first Jacobian
+// columns, 8 compute-type values per thread and block (VGPRs of 32 bits).
+bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF)
+{
+    const int blocks = S + (coupled ? S * (S - 1) / 2 : 0);
+    const int per_block = (VF == 2) ? 16 : 8;        // FP64: 8 doubles; float: 8 floats
+    const int jac = (VJ == 2) ? 64 : 32;             // 16 FP64 or 8 FP32 column loads
+    return blocks * per_block + jac <= 176;
+}
+
+// Elements per sweep workgroup (SW_THREADS threads) and whether the
+// prefetching form applies: the most elements per workgroup (up to 16) for
+// which each thread covers at most 8 / VF columns of a factor block and the
+// team spans at least one column group of the Jacobian and factor blocks.
+// Otherwise the streaming form, with teams of at least 8 column groups.
+void pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupled, int &tps, bool &pf)
+{
+    const int RF = ldF / VF, RJ = ldJ / VJ, NQ = 8 / VF;
+    tps = 0;
+    for (int tpw = 1; tpw <= 16; tpw *= 2) {
+        const int team = SW_THREADS / tpw;
+        if (team < RF || team < RJ) break;
+        const int G = team / RF;
+        if ((m + G - 1) / G <= NQ) tps = tpw;
+    }
+    pf = tps > 0 && sweep_prefetch_fits(s, coupled, VJ, VF);
+    if (!pf) {
+        tps = 1;
+        const int R = std::max(RF, RJ);
+        while (tps < 8 && SW_THREADS / (tps * 2) >= R * 8) tps *= 2;
+    }
+}
+
 struct Plan {
     size_t o_dsys, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
-        o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_flags, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
+        o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
         o_hbuf, o_part, o_gather, total;
     int ld, ld32, ld16, nitems_max;
 };
@@ -248,7 +282,6 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
         P.o_P64 = take(sizeof(double) * (size_t)nblkP * m * P.ld);
         if (coupled) P.o_C64 = take(sizeof(double) * (size_t)nblkC * m * P.ld);
         P.o_Fscr = take(sizeof(double) * (size_t)nblkP * m * P.ld);
-        P.o_flags = take(sizeof(unsigned) * (size_t)T);
         if (mixed && ft == FT_F32) {
             P.o_P32 = take(sizeof(float) * (size_t)nblkP * m * P.ld32);
             if (coupled) P.o_C32 = take(sizeof(float) * (size_t)nblkC * m * P.ld32);
@@ -300,8 +333,7 @@ struct WorkSet {
     bool mixed = false, coupled = false, sharedJ = true, has_pc = true;
     int ftype = FT_F64;
     size_t shm_mv64 = 0, shm_mv32 = 0, shm_sw64 = 0, shm_sw32 = 0;
-    bool persist = false;
-    int pgrid = 0;
+    bool pf64 = false, pf32 = false;   // sweeps in the prefetching form
 };
 
 }  // namespace
@@ -329,12 +361,13 @@ struct irk_handle {
     // per-system work lists (sys = 0) and factorization tasks
     WorkSet W;
     int tpw64, tpw32, nblk;
+    int tps64, tps32;    // elements per sweep workgroup (FP64, mixed inner)
+    bool pf64, pf32;     // sweep blocks fit the prefetching form
     std::vector<Launch> fa, fb;
     std::vector<Item> fitems;
     size_t shm_fac;
     bool mixed, coupled, sharedJ, factored;
     int ftype;
-    unsigned epoch;      // flag value of the current persistent sweep
     int bad_element;
     float ms_factor;
     hipEvent_t ev0, ev1, ev_ready;
@@ -373,7 +406,6 @@ struct irk_batch {
     std::vector<Member> members;   // queued and iterating
     std::vector<Member> retired;
     std::vector<int> free_slots;
-    unsigned epoch;
     hipEvent_t ev_end;
 };
 
@@ -401,7 +433,6 @@ struct Ctx {
     WorkSet *W;
     hipStream_t st;
     irk_handle *prof;      // handle whose event pool records intervals (or null)
-    unsigned *epoch;
 };
 
 void add_level_items(std::vector<Item> &items, const std::vector<int> &off, int tpw,
@@ -430,7 +461,7 @@ size_t lds_matvec(int S, int m, int maxrow, int ld, int V, int tpw, size_t w)
 }
 size_t lds_sweep(int S, int m, int maxrow, int ldJ, int VJ, int ldF, int VF, int tpw, size_t w)
 {
-    return w * (size_t)tpw * sweep_region(S, m, maxrow, ldJ, VJ, ldF, VF, NTHREADS / tpw);
+    return w * (size_t)tpw * sweep_region(S, m, maxrow, ldJ, VJ, ldF, VF, SW_THREADS / tpw);
 }
 
 // Work lists of several systems merged: every list of member q is copied
@@ -445,10 +476,17 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
     M.mixed = h0->mixed; M.coupled = h0->coupled; M.sharedJ = h0->sharedJ;
     M.has_pc = h0->opt.pc != IRK_PC_NONE; M.ftype = h0->ftype;
     M.smax = 1; M.restart = 1;
-    M.persist = false;   // persistent sweeps serve one system at a time
+    M.pf64 = M.pf32 = true;
     for (auto &pr : mem) {
         M.smax = std::max(M.smax, pr.first->s);
         M.restart = std::max(M.restart, pr.first->opt.restart);
+    }
+    for (auto &pr : mem) {
+        // every member's blocks must fit the prefetching form with S = smax
+        const irk_handle *h = pr.first;
+        M.pf64 = M.pf64 && h->pf64 && sweep_prefetch_fits(M.smax, M.coupled, 2, 2);
+        M.pf32 = M.pf32 && h->pf32 &&
+                 sweep_prefetch_fits(M.smax, M.coupled, 4, (h->ftype == FT_F32) ? 4 : 8);
     }
     auto copy_list = [&](const Launch &L, const irk_handle *h, int sys) {
         for (int a = 0; a < L.n; ++a) {
@@ -494,12 +532,12 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         const Plan &P = h->plan;
         const int mr = h->sc.maxrow;
         M.shm_mv64 = std::max(M.shm_mv64, lds_matvec(M.smax, h->m, mr, P.ld, 2, h->tpw64, sizeof(double)));
-        M.shm_sw64 = std::max(M.shm_sw64, lds_sweep(M.smax, h->m, mr, P.ld, 2, P.ld, 2, h->tpw64, sizeof(double)));
+        M.shm_sw64 = std::max(M.shm_sw64, lds_sweep(M.smax, h->m, mr, P.ld, 2, P.ld, 2, h->tps64, sizeof(double)));
         if (M.mixed) {
             const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
             const int VF = (h->ftype == FT_F32) ? 4 : 8;
             M.shm_mv32 = std::max(M.shm_mv32, lds_matvec(M.smax, h->m, mr, P.ld32, 4, h->tpw32, sizeof(float)));
-            M.shm_sw32 = std::max(M.shm_sw32, lds_sweep(M.smax, h->m, mr, P.ld32, 4, ldF, VF, h->tpw32, sizeof(float)));
+            M.shm_sw32 = std::max(M.shm_sw32, lds_sweep(M.smax, h->m, mr, P.ld32, 4, ldF, VF, h->tps32, sizeof(float)));
         }
     }
 }
@@ -513,25 +551,13 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
     const std::vector<Launch> &B = fp64 ? W.bwd64 : W.bwd32;
     const size_t shm = fp64 ? W.shm_sw64 : W.shm_sw32;
     const int ft = fp64 ? FT_F64 : W.ftype;
-    if (W.persist && W.nsys == 1) {
-        const int nf = F.back().off + F.back().n - F.front().off;
-        const int nb = B.back().off + B.back().n - B.front().off;
-        ++*C.epoch;
-        launch_sweep(true, W.dsys, W.ditems + F.front().off, nf, W.smax, fp64, ft, W.coupled,
-                     W.sharedJ, v_slot, v_index, -1, skip_done, shm, C.st, std::min(nf, W.pgrid),
-                     *C.epoch);
-        ++*C.epoch;
-        launch_sweep(false, W.dsys, W.ditems + B.front().off, nb, W.smax, fp64, ft, W.coupled,
-                     W.sharedJ, v_slot, v_index, acc_slot, skip_done, shm, C.st,
-                     std::min(nb, W.pgrid), *C.epoch);
-    } else {
-        for (const Launch &L : F)
-            launch_sweep(true, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
-                         v_slot, v_index, -1, skip_done, shm, C.st, 0, 0u);
-        for (const Launch &L : B)
-            launch_sweep(false, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
-                         v_slot, v_index, acc_slot, skip_done, shm, C.st, 0, 0u);
-    }
+    const bool pf = fp64 ? W.pf64 : W.pf32;
+    for (const Launch &L : F)
+        launch_sweep(true, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
+                     v_slot, v_index, -1, skip_done, shm, C.st, pf);
+    for (const Launch &L : B)
+        launch_sweep(false, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
+                     v_slot, v_index, acc_slot, skip_done, shm, C.st, pf);
     prof_end(C.prof, pi, PK_PC);
 }
 
@@ -650,9 +676,9 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
     // the last step's flags (breakdown, non-finite) are read before the reset
     irk_status st = sync_states(C, dg, hg);
     if (st != IRK_OK) return st;
-    std::vector<int> brk(W.nsys), nonf(W.nsys), spin(W.nsys);
+    std::vector<int> brk(W.nsys), nonf(W.nsys);
     for (int q = 0; q < W.nsys; ++q) {
-        brk[q] = hg[q].breakdown; nonf[q] = hg[q].nonfinite; spin[q] = hg[q].spin_timeout;
+        brk[q] = hg[q].breakdown; nonf[q] = hg[q].nonfinite;
         sv[q]->est = hg[q].est / std::max(sv[q]->bn, 1e-300);
     }
     launch_start_cycle(W.dsys, vec, W.vec.n, fin, W.fin.n, SL_R, C.st);
@@ -665,7 +691,6 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
         const irk_options &o = S.h->opt;
         const double newrel = d.beta / S.bn;
         S.cycles++;
-        if (spin[q]) { S.rel = newrel; finish(S, d, IRK_ERR_DEVICE); continue; }
         if (nonf[q] || d.nonfinite || !std::isfinite(newrel)) { S.rel = newrel; finish(S, d, IRK_ERR_NONFINITE); continue; }
         if (newrel <= o.rtol) { S.rel = newrel; finish(S, d, IRK_OK); continue; }
         if (brk[q] && !(newrel < 0.5 * S.rel)) {
@@ -835,12 +860,18 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     W.fin.off = (int)W.items.size();
     W.items.push_back(Item{0, 0, h->nblk, 0});
     W.fin.n = 1;
+    {
+        const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
+        const int VF = (h->ftype == FT_F32) ? 4 : 8;
+        pick_sweep(m, P.ld, 2, P.ld, 2, s, h->coupled, h->tps64, h->pf64);
+        pick_sweep(m, P.ld32, 4, ldF, VF, s, h->coupled, h->tps32, h->pf32);
+    }
     if (o->pc != IRK_PC_NONE) {
-        add_level_items(W.items, h->sc.off_fwd, h->tpw64, W.fwd64);
-        add_level_items(W.items, h->sc.off_bwd, h->tpw64, W.bwd64);
+        add_level_items(W.items, h->sc.off_fwd, h->tps64, W.fwd64);
+        add_level_items(W.items, h->sc.off_bwd, h->tps64, W.bwd64);
         if (h->mixed) {
-            add_level_items(W.items, h->sc.off_fwd, h->tpw32, W.fwd32);
-            add_level_items(W.items, h->sc.off_bwd, h->tpw32, W.bwd32);
+            add_level_items(W.items, h->sc.off_fwd, h->tps32, W.fwd32);
+            add_level_items(W.items, h->sc.off_bwd, h->tps32, W.bwd32);
         }
     }
     // factor tasks per forward level (stored after the work set's items)
@@ -867,16 +898,17 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     W.nsys = 1;
     W.mixed = h->mixed; W.coupled = h->coupled; W.sharedJ = h->sharedJ;
     W.has_pc = o->pc != IRK_PC_NONE; W.ftype = h->ftype;
+    W.pf64 = h->pf64; W.pf32 = h->pf32;
 
     // ---- LDS sizes ----
     const int maxrow = h->sc.maxrow;
     W.shm_mv64 = lds_matvec(s, m, maxrow, P.ld, 2, h->tpw64, sizeof(double));
     W.shm_mv32 = lds_matvec(s, m, maxrow, P.ld32, 4, h->tpw32, sizeof(float));
-    W.shm_sw64 = lds_sweep(s, m, maxrow, P.ld, 2, P.ld, 2, h->tpw64, sizeof(double));
+    W.shm_sw64 = lds_sweep(s, m, maxrow, P.ld, 2, P.ld, 2, h->tps64, sizeof(double));
     {
         const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
         const int VF = (h->ftype == FT_F32) ? 4 : 8;
-        W.shm_sw32 = lds_sweep(s, m, maxrow, P.ld32, 4, ldF, VF, h->tpw32, sizeof(float));
+        W.shm_sw32 = lds_sweep(s, m, maxrow, P.ld32, 4, ldF, VF, h->tps32, sizeof(float));
     }
     {
         const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
@@ -893,18 +925,6 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         return IRK_ERR_ARG;
     }
     factor_set_lds_limit(h->shm_fac);
-    {
-        // sweep mode: one launch per level (default) or one persistent
-        // dependency-driven launch per sweep (IRK_SWEEP_PERSIST=1)
-        const char *e = std::getenv("IRK_SWEEP_PERSIST");
-        W.persist = (e && e[0] == '1');
-        int dev = 0, ncu = 256;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        W.pgrid = std::max(1, ncu) * 4;
-        h->epoch = 0;
-    }
-
     // ---- device pointers ----
     char *ws = h->ws;
     SysDesc &d = h->hsys;
@@ -939,7 +959,6 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         d.P64 = (double *)(ws + P.o_P64);
         d.Fscr = (double *)(ws + P.o_Fscr);
         if (h->coupled) d.C64 = (double *)(ws + P.o_C64);
-        d.dep_flags = (unsigned *)(ws + P.o_flags);
         if (P.o_P32) d.P32 = (float *)(ws + P.o_P32);
         if (P.o_C32) d.C32 = (float *)(ws + P.o_C32);
         if (P.o_P16) { d.P16 = (uint16_t *)(ws + P.o_P16); d.P16e = (int *)(ws + P.o_P16e); }
@@ -984,8 +1003,6 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     ok &= hipMemcpyAsync(h->ditems, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, stream) == hipSuccess;
-    if (o->pc != IRK_PC_NONE)
-        ok &= hipMemsetAsync(ws + P.o_flags, 0, sizeof(unsigned) * (size_t)T, stream) == hipSuccess;
     if (!ok) { irk_destroy(h); return IRK_ERR_DEVICE; }
     *out = h;
     st = irk_update_values(h, p->J, p->M, p->dt);
@@ -1021,7 +1038,6 @@ irk_status irk_factor_ilu(irk_handle *h)
     if (h->opt.pc == IRK_PC_NONE) { h->factored = true; return IRK_OK; }
     h->hst->singular = 0;
     h->hst->nonfinite = 0;
-    std::memset(h->hst->tickets, 0, sizeof(h->hst->tickets));
     HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
     hipEventRecord(h->ev0, h->stream);
     const int pf = prof_begin(h);
@@ -1072,7 +1088,7 @@ irk_status irk_apply_operator(irk_handle *h, const double *x, double *y)
     if (!h || !x || !y) return IRK_ERR_ARG;
     const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
     HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], x, bytes, hipMemcpyDeviceToDevice, h->stream));
-    Ctx C{&h->W, h->stream, h, &h->epoch};
+    Ctx C{&h->W, h->stream, h};
     enqueue_matvec(C, true, SL_EXT0, SL_EXT1, -1, 0, 0);
     HIPCHK(hipMemcpyAsync(y, h->hsys.vec[SL_EXT1], bytes, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1090,7 +1106,7 @@ irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z)
         return IRK_OK;
     }
     HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], v, bytes, hipMemcpyDeviceToDevice, h->stream));
-    Ctx C{&h->W, h->stream, h, &h->epoch};
+    Ctx C{&h->W, h->stream, h};
     enqueue_pc(C, true, SL_EXT0, 0, -1, 0);
     HIPCHK(hipMemcpyAsync(z, h->hsys.vec[SL_YH], bytes, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1116,7 +1132,7 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
     h->solve_desc.vec[SL_X] = x;
     hipEventRecord(h->ev0, h->stream);
     HIPCHK(hipMemcpyAsync(h->dsys, &h->solve_desc, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
-    Ctx C{&h->W, h->stream, h, &h->epoch};
+    Ctx C{&h->W, h->stream, h};
     Solve S;
     S.h = h;
     S.x = x;
@@ -1231,7 +1247,6 @@ irk_status irk_batch_create(int capacity, long long max_elements, void *workspac
         return IRK_ERR_DEVICE;
     }
     for (int q = capacity - 1; q >= 0; --q) b->free_slots.push_back(q);
-    b->epoch = 0;
     hipEventCreate(&b->ev_end);
     *out = b;
     return IRK_OK;
@@ -1349,7 +1364,7 @@ irk_status irk_batch_advance(irk_batch *b, int cycles)
             sol[q].x = b->members[idx[q]].x;
             sv.push_back(&sol[q]);
         }
-        Ctx C{&W, b->stream, nullptr, &b->epoch};
+        Ctx C{&W, b->stream, nullptr};
         st = init_systems(C, sv, b->dgather, b->hgather);
         if (st != IRK_OK) return st;
         batch_retire_finished(b, sol, idx);
@@ -1366,7 +1381,7 @@ irk_status irk_batch_advance(irk_batch *b, int cycles)
             sol[q].cycles = m.cycles; sol[q].stall = m.stall;
             sv.push_back(&sol[q]);
         }
-        Ctx C{&W, b->stream, nullptr, &b->epoch};
+        Ctx C{&W, b->stream, nullptr};
         st = run_cycle(C, sv, b->dgather, b->hgather);
         if (st != IRK_OK) return st;
         batch_retire_finished(b, sol, idx);

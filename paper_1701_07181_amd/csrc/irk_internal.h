@@ -16,6 +16,7 @@ constexpr int SMAX = 5;          // most stages handled
 constexpr int MMAX = 160;        // largest block size
 constexpr int RESTART_MAX = 64;  // largest Krylov dimension
 constexpr int NTHREADS = 256;    // threads per workgroup of the element kernels
+constexpr int SW_THREADS = 512;  // threads per workgroup of the sweep kernels
 constexpr int RED_BLOCKS = 1024; // workgroups of the vector reduction kernels (max)
 
 enum Slot : int {
@@ -45,11 +46,8 @@ struct DevState {
     int breakdown;
     int singular;      // 1 + element of the first singular pivot, 0 if none
     int nonfinite;
-    int spin_timeout;   // a persistent sweep gave up waiting on a dependency
     int iters;          // Arnoldi steps of the current solve
-    int pad;
     double tol_abs;     // cycle ends when |g_{j+1}| <= tol_abs
-    unsigned tickets[8];   // work counters of the persistent sweeps
 };
 
 struct SysDesc {
@@ -82,7 +80,6 @@ struct SysDesc {
     uint16_t *P16; uint16_t *C16;             // ld16
     int *P16e; int *C16e;                     // per-block exponents (FP16S)
     double *Fscr;                             // per-element factor scratch [T][s] blocks (ld)
-    unsigned *dep_flags;                      // [T] completion flags of the persistent sweeps
     // vectors
     void *vec[NSLOT];
     // Krylov state
@@ -136,13 +133,12 @@ void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max
 //   and factors of type ftype with float vectors.
 //   v_slot/v_index: input of the forward sweep (FP64); result in SL_YH;
 //   acc_slot >= 0 adds the backward result to that FP64 slot (x += z).
-//   pgrid > 0: one persistent launch of pgrid workgroups covers all levels
-//   (items of every level, in level order), synchronized by per-element
-//   flags that carry `epoch`; pgrid == 0: items of one level, one workgroup each.
+//   prefetch: every item's blocks fit the prefetching form (see k_sweep.hip).
+//   Items of one level, one workgroup (SW_THREADS threads) each.
 void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                   int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                   int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
-                  hipStream_t st, int pgrid, unsigned epoch);
+                  hipStream_t st, bool prefetch);
 
 // Factorization of one level.  phase 0: tasks (stage k = aux, element) build
 // P_{k,i} (and invert it when !coupled; set up cross blocks of column k when

@@ -346,7 +346,6 @@ __global__ void k_reset_state(const SysDesc *__restrict__ sysv, const Item *__re
     DevState *st = sysv[items[q].sys].st;
     st->iters = 0;
     st->nonfinite = 0;
-    st->spin_timeout = 0;
     st->breakdown = 0;
     st->done = 0;
     st->j = -1;

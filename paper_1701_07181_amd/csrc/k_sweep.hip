@@ -14,13 +14,22 @@
 //       z_{k,i} = y^_{k,i} + P_{k,i}^{-1} ( dt sum_{j>i} J_ij z_{k,j}
 //                                           - sum_{l>k} C_{kl,i} z_{l,i} )
 //
-// Elements of one level are independent; each team handles one element and
-// all s stages of it: the shared Jacobian blocks of the element's row are
-// streamed once and applied to the s stage vectors, then the stage-local
-// pivot (and cross-stage) products follow.  The element-major order reaches
-// every unknown after its dependencies in the stage-major elimination order,
-// so the coupled form needs the same number of levels as the uncoupled one.
-// The backward sweep overwrites y^ with z in place.
+// Elements of one level are independent; a team of threads handles one
+// element and all s stages of it: the shared Jacobian blocks of the
+// element's row are streamed once and applied to the s stage vectors, then
+// the stage-local pivot (and cross-stage) products follow.  The element-major
+// order reaches every unknown after its dependencies in the stage-major
+// elimination order, so the coupled form needs the same number of levels as
+// the uncoupled one.  The backward sweep overwrites y^ with z in place.
+//
+// A level holds roughly one element per compute unit, so the time of a level
+// is the latency of one element's chain of dependent products.  When the
+// blocks are small enough (prefetching form, PF), every thread issues the
+// loads of all its pivot and cross-block pieces and of the first columns of
+// the Jacobian row before anything else, so the element pays about one
+// memory latency; the products then run from registers and LDS.  Larger
+// blocks stream each product's matrix in its turn.  Both forms accumulate in
+// the same order, so they give identical results.
 #include "irk_device.h"
 
 namespace irk {
@@ -33,16 +42,61 @@ __device__ __forceinline__ TC sum_groups(const TC *red, int G, int k, int ldr, i
     return a;
 }
 
-template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
+// acc[v] += column c of a block (rows slot*V .. slot*V+V-1) times x, for the
+// columns c = g, g + G, ... of this thread; the first NQ come from registers
+// (prefetching form), the rest are loaded here.
+template <typename TF, typename TC, int NQ, bool PF>
+__device__ __forceinline__ void col_product(const GAS typename Vec16<TF>::st *blk, int ld, int m,
+                                            int g, int G, const TC (&pre)[NQ][Vec16<TF>::V],
+                                            const TC *x, TC (&acc)[Vec16<TF>::V])
+{
+    constexpr int V = Vec16<TF>::V;
+    int c0 = g;
+    if (PF) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int c = g + G * q;
+            if (c < m) {
+                const TC xv = x[c];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] += pre[q][v] * xv;
+            }
+        }
+        c0 = g + G * NQ;
+    }
+#pragma unroll 4
+    for (int c = c0; c < m; c += G) {
+        TC a[V];
+        Vec16<TF>::load(blk + (size_t)c * ld, a);
+        const TC xv = x[c];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] += a[v] * xv;
+    }
+}
+
+template <typename TF, typename TC, int NQ>
+__device__ __forceinline__ void prefetch_block(const GAS typename Vec16<TF>::st *blk, int ld, int m,
+                                               int g, int G, TC (&pre)[NQ][Vec16<TF>::V])
+{
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int c = g + G * q;
+        Vec16<TF>::load(blk + (size_t)min(c, m - 1) * ld, pre[q]);
+    }
+}
+
+template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
 __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int v_slot, int v_index,
                                            int acc_slot, unsigned char *smem_raw)
 {
     const int s = d.s, m = d.m, T = d.T;
     constexpr int VJ = Vec16<TJ>::V, VF = Vec16<TF>::V;
+    constexpr int NQ = 8 / VF;        // prefetched loads per thread and factor block
+    constexpr int QJ = 32 / VJ;       // prefetched loads per thread of the Jacobian row
     const int ldJ = ld_of<TJ>(d), ldF = ld_of<TF>(d);
     const int ldv = round_up(m, 8);
     const int tpw = it.aux;
-    const int team = NTHREADS / tpw;
+    const int team = SW_THREADS / tpw;
     const int tm = threadIdx.x / team, tid = threadIdx.x - tm * team;
     const int RJ = ldJ / VJ, GJ = team / RJ;
     const int gJ = tid / RJ, sJ = tid - gJ * RJ;
@@ -64,12 +118,54 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
     const int i = has ? lvl[it.first + tm] : 0;
     GAS TC *yh = gp(reinterpret_cast<TC *>(d.vec[SL_YH]));
     const TC dt = (TC)d.dt;
+    const auto Jb = jac_of<TJ>(d);
+    const auto Pb = piv_of<TF>(d);
+    const auto Cb = cross_of<TF>(d);
+    const long long bsF = (long long)m * ldF;
+    const int sm1 = s - 1;
+    const bool fact = has && gF < GF;
 
     int pa = 0, ncol = 0;
     if (has) {
         const int p0 = row_ptr[i], p1 = row_ptr[i + 1], pd = diag_pos[i];
         pa = FWD ? p0 : pd + 1;
         ncol = (FWD ? (pd - p0) : (p1 - pd - 1)) * m;
+    }
+    const auto jrow = Jb + (size_t)pa * m * ldJ + sJ * VJ;
+
+    // ---- prefetch: Jacobian row (first QJ column loads), pivots, cross blocks ----
+    TC rJ[QJ][VJ];
+    TC rP[S][NQ][VF];
+    TC rC[S][S][NQ][VF];   // [k][l]: block C_{lk} used by round k
+    if (PF) {
+        if (SHJ && has && gJ < GJ && ncol > 0) {
+#pragma unroll
+            for (int q = 0; q < QJ; ++q) {
+                const int cg = gJ + GJ * q;
+                Vec16<TJ>::load(jrow + (size_t)min(cg, ncol - 1) * ldJ, rJ[q]);
+            }
+        }
+        if (fact) {
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                if (k >= s) continue;
+                prefetch_block<TF, TC, NQ>(Pb + ((long long)i * s + k) * bsF + sF * VF, ldF, m, gF, GF,
+                                           rP[k]);
+                if (COUPLED) {
+#pragma unroll
+                    for (int l = 0; l < S; ++l) {
+                        if (l >= s || l == k || (FWD ? (l < k) : (l > k))) continue;
+                        const int idx = l < k ? l : l - 1;
+                        prefetch_block<TF, TC, NQ>(Cb + (((long long)i * s + k) * sm1 + idx) * bsF + sF * VF,
+                                                   ldF, m, gF, GF, rC[k][l]);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- gather the neighbours' vectors and this element's input ----
+    if (has) {
         for (int q = tid; q < ncol; q += team) {
             const int b = q / m, c = q - b * m;
             const long long j = col_idx[pa + b];
@@ -100,13 +196,28 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
 #pragma unroll
             for (int v = 0; v < VJ; ++v) aj[k][v] = 0;
         if (has && gJ < GJ && ncol > 0) {
-            const auto Jb = jac_of<TJ>(d);
             if (SHJ) {
-                const auto base = Jb + (size_t)pa * m * ldJ + sJ * VJ;
+                int c0 = gJ;
+                if (PF) {
+#pragma unroll
+                    for (int q = 0; q < QJ; ++q) {
+                        const int cg = gJ + GJ * q;
+                        if (cg < ncol) {
+#pragma unroll
+                            for (int k = 0; k < S; ++k) {
+                                if (k >= s) continue;
+                                const TC xv = xg[k * maxg + cg];
+#pragma unroll
+                                for (int v = 0; v < VJ; ++v) aj[k][v] += rJ[q][v] * xv;
+                            }
+                        }
+                    }
+                    c0 = gJ + GJ * QJ;
+                }
 #pragma unroll 4
-                for (int cg = gJ; cg < ncol; cg += GJ) {
+                for (int cg = c0; cg < ncol; cg += GJ) {
                     TC a[VJ];
-                    Vec16<TJ>::load(base + (size_t)cg * ldJ, a);
+                    Vec16<TJ>::load(jrow + (size_t)cg * ldJ, a);
 #pragma unroll
                     for (int k = 0; k < S; ++k) {
                         if (k >= s) continue;
@@ -119,8 +230,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
                     if (k >= s) continue;
-                    const auto base =
-                        Jb + ((size_t)k * d.nnzb + pa) * m * ldJ + sJ * VJ;
+                    const auto base = Jb + ((size_t)k * d.nnzb + pa) * m * ldJ + sJ * VJ;
 #pragma unroll 4
                     for (int cg = gJ; cg < ncol; cg += GJ) {
                         TC a[VJ];
@@ -153,42 +263,27 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
         __syncthreads();
     }
 
-    const auto Pb = piv_of<TF>(d);
-    const long long bsF = (long long)m * ldF;
     TC *red = xg;
+    GAS double *acc = acc_slot >= 0 ? gp(reinterpret_cast<double *>(d.vec[acc_slot])) : nullptr;
 
     if (!COUPLED) {
         // all stages at once: out_k = P_k^{-1} in_k
         const TC *in = FWD ? yv : uv;
-        TC ap[S][VF];
-#pragma unroll
-        for (int k = 0; k < S; ++k)
-#pragma unroll
-            for (int v = 0; v < VF; ++v) ap[k][v] = 0;
-        if (has && gF < GF) {
+        if (fact) {
 #pragma unroll
             for (int k = 0; k < S; ++k) {
                 if (k >= s) continue;
-                const auto pb = Pb + ((long long)i * s + k) * bsF + sF * VF;
-#pragma unroll 4
-                for (int c = gF; c < m; c += GF) {
-                    TC a[VF];
-                    Vec16<TF>::load(pb + (size_t)c * ldF, a);
-                    const TC xv = in[k * ldv + c];
+                TC ap[VF];
 #pragma unroll
-                    for (int v = 0; v < VF; ++v) ap[k][v] += a[v] * xv;
-                }
-            }
+                for (int v = 0; v < VF; ++v) ap[v] = 0;
+                col_product<TF, TC, NQ, PF>(Pb + ((long long)i * s + k) * bsF + sF * VF, ldF, m, gF, GF,
+                                            rP[k], in + k * ldv, ap);
 #pragma unroll
-            for (int k = 0; k < S; ++k) {
-                if (k >= s) continue;
-#pragma unroll
-                for (int v = 0; v < VF; ++v) red[(gF * S + k) * ldF + sF * VF + v] = ap[k][v];
+                for (int v = 0; v < VF; ++v) red[(gF * S + k) * ldF + sF * VF + v] = ap[v];
             }
         }
         __syncthreads();
         if (has) {
-            GAS double *acc = acc_slot >= 0 ? gp(reinterpret_cast<double *>(d.vec[acc_slot])) : nullptr;
             for (int q = tid; q < s * m; q += team) {
                 const int k = q / m, r = q - k * m;
                 const TC sc = block_scale<TF, TC>(d.P16e, (long long)i * s + k);
@@ -203,10 +298,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
     }
 
     // ---- coupled: stage rounds inside the element ----
-    const auto Cb = cross_of<TF>(d);
-    const int sm1 = s - 1;
-    GAS double *acc = acc_slot >= 0 ? gp(reinterpret_cast<double *>(d.vec[acc_slot])) : nullptr;
-#pragma unroll 1
+#pragma unroll
     for (int kk = 0; kk < S; ++kk) {
         const int k = FWD ? kk : (S - 1 - kk);
         const bool act = has && k < s;
@@ -217,15 +309,8 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
 #pragma unroll
             for (int v = 0; v < VF; ++v) ap[v] = 0;
             if (act && gF < GF) {
-                const auto pb = Pb + ((long long)i * s + k) * bsF + sF * VF;
-#pragma unroll 4
-                for (int c = gF; c < m; c += GF) {
-                    TC a[VF];
-                    Vec16<TF>::load(pb + (size_t)c * ldF, a);
-                    const TC xv = in[k * ldv + c];
-#pragma unroll
-                    for (int v = 0; v < VF; ++v) ap[v] += a[v] * xv;
-                }
+                col_product<TF, TC, NQ, PF>(Pb + ((long long)i * s + k) * bsF + sF * VF, ldF, m, gF, GF,
+                                            rP[k], in + k * ldv, ap);
 #pragma unroll
                 for (int v = 0; v < VF; ++v) red[gF * ldF + sF * VF + v] = ap[v];
             }
@@ -247,29 +332,19 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
         }
         // (b) cross-stage update of the stages not yet done:
         //     forward: y_l -= C_{lk} y^_k (l > k);  backward: u_l -= C_{lk} z_k (l < k)
-        {
-            TC ac[S][VF];
-#pragma unroll
-            for (int l = 0; l < S; ++l)
-#pragma unroll
-                for (int v = 0; v < VF; ++v) ac[l][v] = 0;
+        if (kk + 1 < S) {
             if (act && gF < GF) {
 #pragma unroll
                 for (int l = 0; l < S; ++l) {
                     if (l >= s || l == k || (FWD ? (l < k) : (l > k))) continue;
                     const int idx = l < k ? l : l - 1;
-                    const auto cb =
-                        Cb + (((long long)i * s + k) * sm1 + idx) * bsF + sF * VF;
-#pragma unroll 2
-                    for (int c = gF; c < m; c += GF) {
-                        TC a[VF];
-                        Vec16<TF>::load(cb + (size_t)c * ldF, a);
-                        const TC xv = yv[k * ldv + c];
+                    TC ac[VF];
 #pragma unroll
-                        for (int v = 0; v < VF; ++v) ac[l][v] += a[v] * xv;
-                    }
+                    for (int v = 0; v < VF; ++v) ac[v] = 0;
+                    col_product<TF, TC, NQ, PF>(Cb + (((long long)i * s + k) * sm1 + idx) * bsF + sF * VF,
+                                                ldF, m, gF, GF, rC[k][l], yv + k * ldv, ac);
 #pragma unroll
-                    for (int v = 0; v < VF; ++v) red[(gF * S + l) * ldF + sF * VF + v] = ac[l][v];
+                    for (int v = 0; v < VF; ++v) red[(gF * S + l) * ldF + sF * VF + v] = ac[v];
                 }
             }
             __syncthreads();
@@ -290,100 +365,35 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
 }
 
 // One level per launch: workgroup b handles items[b].
-template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
-__global__ __launch_bounds__(NTHREADS) void k_sweep(const SysDesc *__restrict__ sysv,
-                                                    const Item *__restrict__ items,
-                                                    int v_slot, int v_index, int acc_slot,
-                                                    int skip_done)
+template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
+__global__ __launch_bounds__(SW_THREADS) void k_sweep(const SysDesc *__restrict__ sysv,
+                                                      const Item *__restrict__ items,
+                                                      int v_slot, int v_index, int acc_slot,
+                                                      int skip_done)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const Item it = items[blockIdx.x];
     if (skip_done && sysv[it.sys].st->done) return;
-    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD>(sysv[it.sys], it, v_slot, v_index, acc_slot, smem_raw);
+    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PF>(sysv[it.sys], it, v_slot, v_index, acc_slot,
+                                                     smem_raw);
 }
 
-// Whole sweep in one launch.  Workgroups take the items of all levels in
-// level order from an atomic ticket; before an item runs, one thread per
-// team waits until every dependency of its element (lower neighbours in the
-// forward sweep, upper ones in the backward sweep) has published its flag
-// for this sweep (`epoch`).  Every dependency sits at an earlier level, so
-// its ticket was taken earlier by a workgroup that is already running and
-// only waits on still earlier tickets: the smallest unfinished ticket can
-// always proceed, and the grid drains.  A bounded spin turns a lost flag
-// into an error flag instead of a hang.  Results are written, then made
-// visible device-wide (release fence) before the flag is set; the waiting
-// side acquires before reading them.
-template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD>
-__global__ __launch_bounds__(NTHREADS) void k_sweep_persist(const SysDesc *__restrict__ sysv,
-                                                            const Item *__restrict__ items,
-                                                            int nitems, int v_slot, int v_index,
-                                                            int acc_slot, int skip_done,
-                                                            unsigned epoch)
+// Same register budget as the host's choice of form: variants beyond it are
+// never selected and are not instantiated.
+constexpr bool pf_fits(int S, bool coupled, bool fp64)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int tk;
-    const SysDesc &d = sysv[items[0].sys];
-    unsigned *ticket = &d.st->tickets[FWD ? 4 : 5];
-    unsigned *flags = d.dep_flags;
-    const GAS int *lvl = gp(FWD ? d.lvl_fwd : d.lvl_bwd);
-    const GAS int *row_ptr = gp(d.row_ptr);
-    const GAS int *col_idx = gp(d.col_idx);
-    const GAS int *diag_pos = gp(d.diag_pos);
-    for (;;) {
-        if (threadIdx.x == 0) tk = (int)atomicAdd(ticket, 1u);
-        __syncthreads();
-        const int t = tk;
-        if (t >= nitems) {
-            // the last workgroup to leave resets the ticket for the next launch
-            if (threadIdx.x == 0 && t == nitems + (int)gridDim.x - 1) *ticket = 0u;
-            return;
-        }
-        const Item it = items[t];
-        if (skip_done && d.st->done) {   // uniform: one system per launch
-            __syncthreads();             // everybody has read tk before it changes
-            continue;
-        }
-        const int team = NTHREADS / it.aux;
-        const int tm = threadIdx.x / team, tid = threadIdx.x - tm * team;
-        if (tid == 0 && tm < it.count) {
-            const int i = lvl[it.first + tm];
-            const int p0 = FWD ? row_ptr[i] : diag_pos[i] + 1;
-            const int p1 = FWD ? diag_pos[i] : row_ptr[i + 1];
-            for (int q = p0; q < p1; ++q) {
-                const int j = col_idx[q];
-                long long spins = 0;
-                while (__hip_atomic_load(&flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > (1LL << 22)) { d.st->spin_timeout = 1; break; }
-                }
-            }
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
-        }
-        __syncthreads();
-        sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD>(d, it, v_slot, v_index, acc_slot, smem_raw);
-        __syncthreads();
-        if (tid == 0 && tm < it.count) {
-            const int i = lvl[it.first + tm];
-            __hip_atomic_store(&flags[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    return (S + (coupled ? S * (S - 1) / 2 : 0)) * (fp64 ? 16 : 8) + (fp64 ? 64 : 32) <= 176;
 }
 
-template <int S, typename TJ, typename TF, typename TC>
+template <int S, typename TJ, typename TF, typename TC, bool PF>
 static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                            bool coupled, bool sharedJ, int v_slot, int v_index, int acc_slot,
-                           int skip_done, size_t shmem, hipStream_t st, int pgrid, unsigned epoch)
+                           int skip_done, size_t shmem, hipStream_t st)
 {
-    dim3 grid(pgrid > 0 ? pgrid : nitems), block(NTHREADS);
-#define SW(C, SH, F)                                                                             \
-    do {                                                                                         \
-        if (pgrid > 0)                                                                           \
-            hipLaunchKernelGGL((k_sweep_persist<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, \
-                               dsys, items, nitems, v_slot, v_index, acc_slot, skip_done, epoch); \
-        else                                                                                     \
-            hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F>), grid, block, shmem, st, dsys,   \
-                               items, v_slot, v_index, acc_slot, skip_done);                     \
-    } while (0)
+    dim3 grid(nitems), block(SW_THREADS);
+#define SW(C, SH, F)                                                                                   \
+    hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F, PF && pf_fits(S, C, sizeof(TC) == 8)>), grid, \
+                       block, shmem, st, dsys, items, v_slot, v_index, acc_slot, skip_done)
     if (forward) {
         if (coupled) { if (sharedJ) SW(true, true, true); else SW(true, false, true); }
         else { if (sharedJ) SW(false, true, true); else SW(false, false, true); }
@@ -394,39 +404,54 @@ static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items,
 #undef SW
 }
 
+template <int S, bool PF>
+static void launch_sweep_p(bool forward, const SysDesc *dsys, const Item *items, int nitems,
+                           bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
+                           int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st)
+{
+    if (fp64) {
+        launch_sweep_t<S, double, double, double, PF>(forward, dsys, items, nitems, coupled, sharedJ,
+                                                      v_slot, v_index, acc_slot, skip_done, shmem, st);
+    } else if (ftype == FT_F32) {
+        launch_sweep_t<S, float, float, float, PF>(forward, dsys, items, nitems, coupled, sharedJ,
+                                                   v_slot, v_index, acc_slot, skip_done, shmem, st);
+    } else if (ftype == FT_BF16) {
+        launch_sweep_t<S, float, bf16s, float, PF>(forward, dsys, items, nitems, coupled, sharedJ,
+                                                   v_slot, v_index, acc_slot, skip_done, shmem, st);
+    } else {
+        launch_sweep_t<S, float, f16s, float, PF>(forward, dsys, items, nitems, coupled, sharedJ,
+                                                  v_slot, v_index, acc_slot, skip_done, shmem, st);
+    }
+}
+
 template <int S>
 static void launch_sweep_s(bool forward, const SysDesc *dsys, const Item *items, int nitems,
                            bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
                            int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st,
-                           int pgrid, unsigned epoch)
+                           bool pf)
 {
-    if (fp64) {
-        launch_sweep_t<S, double, double, double>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                  v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
-    } else if (ftype == FT_F32) {
-        launch_sweep_t<S, float, float, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                               v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
-    } else if (ftype == FT_BF16) {
-        launch_sweep_t<S, float, bf16s, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                               v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
-    } else {
-        launch_sweep_t<S, float, f16s, float>(forward, dsys, items, nitems, coupled, sharedJ,
-                                              v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch);
-    }
+    if (pf)
+        launch_sweep_p<S, true>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot,
+                                v_index, acc_slot, skip_done, shmem, st);
+    else
+        launch_sweep_p<S, false>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot,
+                                 v_index, acc_slot, skip_done, shmem, st);
 }
 
 void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems, int s_max,
                   bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot, int v_index,
-                  int acc_slot, int skip_done, size_t shmem, hipStream_t st, int pgrid,
-                  unsigned epoch)
+                  int acc_slot, int skip_done, size_t shmem, hipStream_t st, bool prefetch)
 {
     if (nitems <= 0) return;
     switch (s_max) {
-    case 1: launch_sweep_s<1>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
-    case 2: launch_sweep_s<2>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
-    case 3: launch_sweep_s<3>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
-    case 4: launch_sweep_s<4>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
-    default: launch_sweep_s<5>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st, pgrid, epoch); break;
+#define SWS(SS) launch_sweep_s<SS>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, \
+                                   v_index, acc_slot, skip_done, shmem, st, prefetch)
+    case 1: SWS(1); break;
+    case 2: SWS(2); break;
+    case 3: SWS(3); break;
+    case 4: SWS(4); break;
+    default: SWS(5); break;
+#undef SWS
     }
 }
 
