@@ -17,6 +17,9 @@ using namespace irk;
 namespace {
 
 struct Launch { int off, n; };
+// sweep launch: n SwItem records starting at item `off`, tps elements per
+// workgroup, prefetching form or not
+struct SwLaunch { int off, n, tps; bool pf; int region; };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -222,27 +225,32 @@ bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF)
     return blocks * per_block + jac <= 176;
 }
 
-// Elements per sweep workgroup (SW_THREADS threads) and whether the
-// prefetching form applies: the most elements per workgroup (up to 16) for
-// which each thread covers at most 8 / VF columns of a factor block and the
-// team spans at least one column group of the Jacobian and factor blocks.
-// Otherwise the streaming form, with teams of at least 8 column groups.
-void pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupled, int &tps, bool &pf)
+// Shape of the sweep launches of one system.  Small levels are latency
+// bound: one element per workgroup of SW_THREADS threads in the prefetching
+// form when its register budget allows (the most elements per workgroup,
+// up to 16, for which each thread covers at most 8 / VF columns of a factor
+// block).  Levels of at least big_min elements are bandwidth bound and use
+// the streaming form with teams of at least 8 column groups, which keeps
+// several elements in flight per compute unit.
+struct SweepShape { int tps_pf; bool pf; int tps_st; int big_min; };
+
+SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupled)
 {
+    SweepShape sh{0, false, 1, 0};
     const int RF = ldF / VF, RJ = ldJ / VJ, NQ = 8 / VF;
-    tps = 0;
     for (int tpw = 1; tpw <= 16; tpw *= 2) {
         const int team = SW_THREADS / tpw;
         if (team < RF || team < RJ) break;
         const int G = team / RF;
-        if ((m + G - 1) / G <= NQ) tps = tpw;
+        if ((m + G - 1) / G <= NQ) sh.tps_pf = tpw;
     }
-    pf = tps > 0 && sweep_prefetch_fits(s, coupled, VJ, VF);
-    if (!pf) {
-        tps = 1;
-        const int R = std::max(RF, RJ);
-        while (tps < 8 && SW_THREADS / (tps * 2) >= R * 8) tps *= 2;
-    }
+    sh.pf = sh.tps_pf > 0 && sweep_prefetch_fits(s, coupled, VJ, VF);
+    const int R = std::max(RF, RJ);
+    while (sh.tps_st < 8 && SW_THREADS / (sh.tps_st * 2) >= R * 8) sh.tps_st *= 2;
+    sh.big_min = 384;
+    if (const char *e = std::getenv("IRK_SWEEP_BIG")) sh.big_min = std::max(1, std::atoi(e));
+    if (!sh.pf) { sh.tps_pf = sh.tps_st; sh.big_min = 1; }
+    return sh;
 }
 
 struct Plan {
@@ -265,7 +273,7 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     const int ft = factor_type(o);
     const long long N = (long long)s * T * m;
     const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * s * (s - 1) : 0;
-    P.nitems_max = T * (8 + 2 * s) + 2 * RED_BLOCKS + 64;
+    P.nitems_max = T * (16 + 2 * s) + 2 * RED_BLOCKS + 64;
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
     P.o_dsys = take(sizeof(SysDesc));
@@ -328,12 +336,11 @@ struct WorkSet {
     Item *ditems = nullptr;          // device copy of `items`
     std::vector<Item> items;
     Launch mv64{0, 0}, mv32{0, 0}, vec{0, 0}, fin{0, 0};
-    std::vector<Launch> fwd64, bwd64, fwd32, bwd32;   // one entry per level
+    std::vector<SwLaunch> fwd64, bwd64, fwd32, bwd32;   // one or more per level
     int smax = 1, restart = 1, nsys = 0;
     bool mixed = false, coupled = false, sharedJ = true, has_pc = true;
     int ftype = FT_F64;
     size_t shm_mv64 = 0, shm_mv32 = 0, shm_sw64 = 0, shm_sw32 = 0;
-    bool pf64 = false, pf32 = false;   // sweeps in the prefetching form
 };
 
 }  // namespace
@@ -361,8 +368,7 @@ struct irk_handle {
     // per-system work lists (sys = 0) and factorization tasks
     WorkSet W;
     int tpw64, tpw32, nblk;
-    int tps64, tps32;    // elements per sweep workgroup (FP64, mixed inner)
-    bool pf64, pf32;     // sweep blocks fit the prefetching form
+    SweepShape sw64, sw32;   // sweep launch shapes (FP64, mixed inner)
     std::vector<Launch> fa, fb;
     std::vector<Item> fitems;
     size_t shm_fac;
@@ -435,14 +441,31 @@ struct Ctx {
     irk_handle *prof;      // handle whose event pool records intervals (or null)
 };
 
-void add_level_items(std::vector<Item> &items, const std::vector<int> &off, int tpw,
-                     std::vector<Launch> &out)
+// Sweep records of every level (in level order) of one system, one launch
+// per level; region = LDS elements of one team.
+void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32_t *rp,
+                       const int32_t *ci, bool fwd, const SweepShape &sh, int region_pf,
+                       int region_st, std::vector<SwLaunch> &out)
 {
     out.clear();
+    const std::vector<int> &off = fwd ? sc.off_fwd : sc.off_bwd;
+    const std::vector<int> &lst = fwd ? sc.lvl_fwd : sc.lvl_bwd;
     for (size_t l = 0; l + 1 < off.size(); ++l) {
-        Launch L{(int)items.size(), 0};
-        for (int a = off[l]; a < off[l + 1]; a += tpw) {
-            items.push_back(Item{0, a, std::min(tpw, off[l + 1] - a), tpw});
+        const bool big = off[l + 1] - off[l] >= sh.big_min;
+        SwLaunch L{(int)items.size(), 0, big ? sh.tps_st : sh.tps_pf, sh.pf && !big,
+                   big ? region_st : region_pf};
+        for (int a = off[l]; a < off[l + 1]; ++a) {
+            const int i = lst[a];
+            SwItem r;
+            std::memset(&r, 0, sizeof(r));
+            r.sys = 0;
+            r.i = i;
+            r.pa = fwd ? rp[i] : sc.diag[i] + 1;
+            r.nb = fwd ? sc.diag[i] - rp[i] : rp[i + 1] - sc.diag[i] - 1;
+            for (int b = 0; b < r.nb && b < SW_NB; ++b) r.col[b] = ci[r.pa + b];
+            Item it[3];
+            std::memcpy(it, &r, sizeof(r));
+            items.insert(items.end(), it, it + 3);
             L.n++;
         }
         if (L.n) out.push_back(L);
@@ -459,9 +482,14 @@ size_t lds_matvec(int S, int m, int maxrow, int ld, int V, int tpw, size_t w)
 {
     return w * (size_t)tpw * matvec_region(S, m, maxrow, ld, V, NTHREADS / tpw);
 }
-size_t lds_sweep(int S, int m, int maxrow, int ldJ, int VJ, int ldF, int VF, int tpw, size_t w)
+// LDS elements of one sweep team (FP64 sweep, or the mixed inner sweep with
+// FP32 Jacobian and factors of type ftype)
+int sw_region(int S, int m, int maxrow, const Plan &P, bool fp64, int ftype, int tps)
 {
-    return w * (size_t)tpw * sweep_region(S, m, maxrow, ldJ, VJ, ldF, VF, SW_THREADS / tpw);
+    const int team = SW_THREADS / tps;
+    if (fp64) return sweep_region(S, m, maxrow, team, P.ld, 2, P.ld, 2);
+    const int ldF = (ftype == FT_F32) ? P.ld32 : P.ld16, VF = (ftype == FT_F32) ? 4 : 8;
+    return sweep_region(S, m, maxrow, team, P.ld32, 4, ldF, VF);
 }
 
 // Work lists of several systems merged: every list of member q is copied
@@ -476,17 +504,9 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
     M.mixed = h0->mixed; M.coupled = h0->coupled; M.sharedJ = h0->sharedJ;
     M.has_pc = h0->opt.pc != IRK_PC_NONE; M.ftype = h0->ftype;
     M.smax = 1; M.restart = 1;
-    M.pf64 = M.pf32 = true;
     for (auto &pr : mem) {
         M.smax = std::max(M.smax, pr.first->s);
         M.restart = std::max(M.restart, pr.first->opt.restart);
-    }
-    for (auto &pr : mem) {
-        // every member's blocks must fit the prefetching form with S = smax
-        const irk_handle *h = pr.first;
-        M.pf64 = M.pf64 && h->pf64 && sweep_prefetch_fits(M.smax, M.coupled, 2, 2);
-        M.pf32 = M.pf32 && h->pf32 &&
-                 sweep_prefetch_fits(M.smax, M.coupled, 4, (h->ftype == FT_F32) ? 4 : 8);
     }
     auto copy_list = [&](const Launch &L, const irk_handle *h, int sys) {
         for (int a = 0; a < L.n; ++a) {
@@ -500,17 +520,48 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         for (auto &pr : mem) copy_list(pr.first->W.*f, pr.first, pr.second);
         out.n = (int)M.items.size() - out.off;
     };
-    auto merge_levels = [&](std::vector<Launch> WorkSet::*f, std::vector<Launch> &out) {
+    // Sweep levels: level l of every member; members with the same elements
+    // per workgroup share a launch.  Records are copied with their system
+    // index; the team region is the largest one of the launch (S = smax).
+    auto merge_sweeps = [&](std::vector<SwLaunch> WorkSet::*f, bool fp64, std::vector<SwLaunch> &out) {
         size_t L = 0;
         for (auto &pr : mem) L = std::max(L, (pr.first->W.*f).size());
         for (size_t l = 0; l < L; ++l) {
-            Launch o{(int)M.items.size(), 0};
-            for (auto &pr : mem) {
-                const auto &lv = pr.first->W.*f;
-                if (l < lv.size()) copy_list(lv[l], pr.first, pr.second);
+            std::vector<int> seen;
+            for (auto &pr0 : mem) {
+                const auto &lv0 = pr0.first->W.*f;
+                if (l >= lv0.size()) continue;
+                const int tps = lv0[l].tps;
+                if (std::find(seen.begin(), seen.end(), tps) != seen.end()) continue;
+                seen.push_back(tps);
+                SwLaunch o{(int)M.items.size(), 0, tps, true, 0};
+                for (auto &pr : mem) {
+                    const irk_handle *h = pr.first;
+                    const auto &lv = h->W.*f;
+                    if (l >= lv.size() || lv[l].tps != tps) continue;
+                    const SwLaunch &src = lv[l];
+                    const int padded = (src.n + tps - 1) / tps * tps;   // whole workgroups per system
+                    for (int a = 0; a < padded; ++a) {
+                        SwItem r;
+                        if (a < src.n) {
+                            std::memcpy(&r, &h->W.items[src.off + 3 * a], sizeof(r));
+                        } else {
+                            std::memset(&r, 0, sizeof(r));
+                            r.i = -1;
+                        }
+                        r.sys = pr.second;
+                        Item it[3];
+                        std::memcpy(it, &r, sizeof(r));
+                        M.items.insert(M.items.end(), it, it + 3);
+                    }
+                    o.n += padded;
+                    const int VF = fp64 ? 2 : ((h->ftype == FT_F32) ? 4 : 8);
+                    o.pf = o.pf && src.pf && sweep_prefetch_fits(M.smax, M.coupled, fp64 ? 2 : 4, VF);
+                    o.region = std::max(o.region, sw_region(M.smax, h->m, h->sc.maxrow, h->plan, fp64,
+                                                            h->ftype, tps));
+                }
+                if (o.n) out.push_back(o);
             }
-            o.n = (int)M.items.size() - o.off;
-            if (o.n) out.push_back(o);
         }
     };
     merge(&WorkSet::mv64, M.mv64);
@@ -518,11 +569,11 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
     merge(&WorkSet::vec, M.vec);
     merge(&WorkSet::fin, M.fin);
     if (M.has_pc) {
-        merge_levels(&WorkSet::fwd64, M.fwd64);
-        merge_levels(&WorkSet::bwd64, M.bwd64);
+        merge_sweeps(&WorkSet::fwd64, true, M.fwd64);
+        merge_sweeps(&WorkSet::bwd64, true, M.bwd64);
         if (M.mixed) {
-            merge_levels(&WorkSet::fwd32, M.fwd32);
-            merge_levels(&WorkSet::bwd32, M.bwd32);
+            merge_sweeps(&WorkSet::fwd32, false, M.fwd32);
+            merge_sweeps(&WorkSet::bwd32, false, M.bwd32);
         }
     }
     // LDS for the merged launches (template S = smax for every member)
@@ -532,12 +583,14 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         const Plan &P = h->plan;
         const int mr = h->sc.maxrow;
         M.shm_mv64 = std::max(M.shm_mv64, lds_matvec(M.smax, h->m, mr, P.ld, 2, h->tpw64, sizeof(double)));
-        M.shm_sw64 = std::max(M.shm_sw64, lds_sweep(M.smax, h->m, mr, P.ld, 2, P.ld, 2, h->tps64, sizeof(double)));
+        for (int tps : {h->sw64.tps_pf, h->sw64.tps_st})
+            M.shm_sw64 = std::max(M.shm_sw64, sizeof(double) * tps * (size_t)sw_region(M.smax, h->m, mr, P, true, h->ftype, tps));
         if (M.mixed) {
             const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
             const int VF = (h->ftype == FT_F32) ? 4 : 8;
             M.shm_mv32 = std::max(M.shm_mv32, lds_matvec(M.smax, h->m, mr, P.ld32, 4, h->tpw32, sizeof(float)));
-            M.shm_sw32 = std::max(M.shm_sw32, lds_sweep(M.smax, h->m, mr, P.ld32, 4, ldF, VF, h->tps32, sizeof(float)));
+            for (int tps : {h->sw32.tps_pf, h->sw32.tps_st})
+                M.shm_sw32 = std::max(M.shm_sw32, sizeof(float) * tps * (size_t)sw_region(M.smax, h->m, mr, P, false, h->ftype, tps));
         }
     }
 }
@@ -547,17 +600,18 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
 {
     WorkSet &W = *C.W;
     const int pi = prof_begin(C.prof);
-    const std::vector<Launch> &F = fp64 ? W.fwd64 : W.fwd32;
-    const std::vector<Launch> &B = fp64 ? W.bwd64 : W.bwd32;
-    const size_t shm = fp64 ? W.shm_sw64 : W.shm_sw32;
+    const std::vector<SwLaunch> &F = fp64 ? W.fwd64 : W.fwd32;
+    const std::vector<SwLaunch> &B = fp64 ? W.bwd64 : W.bwd32;
     const int ft = fp64 ? FT_F64 : W.ftype;
-    const bool pf = fp64 ? W.pf64 : W.pf32;
-    for (const Launch &L : F)
-        launch_sweep(true, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
-                     v_slot, v_index, -1, skip_done, shm, C.st, pf);
-    for (const Launch &L : B)
-        launch_sweep(false, W.dsys, W.ditems + L.off, L.n, W.smax, fp64, ft, W.coupled, W.sharedJ,
-                     v_slot, v_index, acc_slot, skip_done, shm, C.st, pf);
+    const size_t w = fp64 ? sizeof(double) : sizeof(float);
+    for (const SwLaunch &L : F)
+        launch_sweep(true, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + L.off), L.n, L.tps,
+                     L.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, -1, skip_done,
+                     w * L.tps * L.region, C.st, L.pf);
+    for (const SwLaunch &L : B)
+        launch_sweep(false, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + L.off), L.n, L.tps,
+                     L.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, acc_slot,
+                     skip_done, w * L.tps * L.region, C.st, L.pf);
     prof_end(C.prof, pi, PK_PC);
 }
 
@@ -863,15 +917,21 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     {
         const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
         const int VF = (h->ftype == FT_F32) ? 4 : 8;
-        pick_sweep(m, P.ld, 2, P.ld, 2, s, h->coupled, h->tps64, h->pf64);
-        pick_sweep(m, P.ld32, 4, ldF, VF, s, h->coupled, h->tps32, h->pf32);
+        h->sw64 = pick_sweep(m, P.ld, 2, P.ld, 2, s, h->coupled);
+        h->sw32 = pick_sweep(m, P.ld32, 4, ldF, VF, s, h->coupled);
     }
     if (o->pc != IRK_PC_NONE) {
-        add_level_items(W.items, h->sc.off_fwd, h->tps64, W.fwd64);
-        add_level_items(W.items, h->sc.off_bwd, h->tps64, W.bwd64);
+        const int mr = h->sc.maxrow;
+        const SweepShape &a = h->sw64, &b = h->sw32;
+        const int pa = sw_region(s, m, mr, P, true, h->ftype, a.tps_pf);
+        const int sa = sw_region(s, m, mr, P, true, h->ftype, a.tps_st);
+        add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, true, a, pa, sa, W.fwd64);
+        add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, false, a, pa, sa, W.bwd64);
         if (h->mixed) {
-            add_level_items(W.items, h->sc.off_fwd, h->tps32, W.fwd32);
-            add_level_items(W.items, h->sc.off_bwd, h->tps32, W.bwd32);
+            const int pb = sw_region(s, m, mr, P, false, h->ftype, b.tps_pf);
+            const int sb = sw_region(s, m, mr, P, false, h->ftype, b.tps_st);
+            add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, true, b, pb, sb, W.fwd32);
+            add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, false, b, pb, sb, W.bwd32);
         }
     }
     // factor tasks per forward level (stored after the work set's items)
@@ -898,17 +958,18 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     W.nsys = 1;
     W.mixed = h->mixed; W.coupled = h->coupled; W.sharedJ = h->sharedJ;
     W.has_pc = o->pc != IRK_PC_NONE; W.ftype = h->ftype;
-    W.pf64 = h->pf64; W.pf32 = h->pf32;
 
     // ---- LDS sizes ----
     const int maxrow = h->sc.maxrow;
     W.shm_mv64 = lds_matvec(s, m, maxrow, P.ld, 2, h->tpw64, sizeof(double));
     W.shm_mv32 = lds_matvec(s, m, maxrow, P.ld32, 4, h->tpw32, sizeof(float));
-    W.shm_sw64 = lds_sweep(s, m, maxrow, P.ld, 2, P.ld, 2, h->tps64, sizeof(double));
+    W.shm_sw64 = sizeof(double) * std::max(h->sw64.tps_pf * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_pf),
+                                           h->sw64.tps_st * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_st));
     {
         const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
         const int VF = (h->ftype == FT_F32) ? 4 : 8;
-        W.shm_sw32 = lds_sweep(s, m, maxrow, P.ld32, 4, ldF, VF, h->tps32, sizeof(float));
+        W.shm_sw32 = sizeof(float) * std::max(h->sw32.tps_pf * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_pf),
+                                              h->sw32.tps_st * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_st));
     }
     {
         const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
@@ -1202,7 +1263,7 @@ irk_status irk_destroy(irk_handle *h)
 // ---------------------------------------------------------------------------
 static size_t batch_items_bound(int capacity, long long max_elements)
 {
-    return (size_t)(10 * max_elements) + (size_t)capacity * (2 * RED_BLOCKS + 8);
+    return (size_t)(24 * max_elements) + (size_t)capacity * (2 * RED_BLOCKS + 8);
 }
 
 static size_t batch_ws_bytes(int capacity, long long max_elements)
@@ -1305,6 +1366,7 @@ static irk_status batch_workset(irk_batch *b, int phase, WorkSet &W, std::vector
         }
     build_merged(W, mem);
     if (W.items.size() > b->max_items) return IRK_ERR_NOMEM;
+    if (W.shm_sw64 > 160 * 1024 || W.shm_sw32 > 160 * 1024) return IRK_ERR_ARG;
     W.dsys = b->dtab;
     W.ditems = b->ditems;
     if (!W.items.empty())

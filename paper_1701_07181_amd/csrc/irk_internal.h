@@ -95,6 +95,15 @@ struct SysDesc {
 // one workgroup's work: system, first task, task count, aux
 struct Item { int sys, first, count, aux; };
 
+// One element of a sweep level: system, element, position of the first
+// off-diagonal block of its row in the sweep's direction (lower blocks in the
+// forward sweep, upper ones in the backward sweep), their count, and the
+// columns of the first SW_NB of them (more are read from col_idx).  Stored
+// in the item array, three Items per record.
+constexpr int SW_NB = 8;
+struct SwItem { int sys, i, pa, nb; int col[SW_NB]; };
+static_assert(sizeof(SwItem) == 3 * sizeof(Item), "SwItem spans three Items");
+
 // LDS elements (of the compute type) one team needs; host and device must agree.
 __host__ __device__ inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 __host__ __device__ inline int imax(int a, int b) { return a > b ? a : b; }
@@ -103,9 +112,11 @@ __host__ __device__ inline int matvec_region(int S, int m, int maxrow, int ld, i
     const int G = team / (ld / V);
     return imax(S * (maxrow + 1) * m, G * S * ld);
 }
-// sweep: gather / partials region, then y and u vectors [S][round_up(m, 8)]
-__host__ __device__ inline int sweep_region(int S, int m, int maxrow, int ldJ, int VJ, int ldF,
-                                            int VF, int team) {
+// sweep: gather of the neighbours' stage vectors [S][maxrow*m], reused for
+// the [G][S][ld] partial sums of the Jacobian and factor products, then the
+// y and u vectors [S][round_up(m, 8)] of one element
+__host__ __device__ inline int sweep_region(int S, int m, int maxrow, int team, int ldJ, int VJ,
+                                            int ldF, int VF) {
     const int GJ = team / (ldJ / VJ), GF = team / (ldF / VF);
     const int r = imax(S * maxrow * m, imax(GJ * S * ldJ, GF * S * ldF));
     return r + 2 * S * round_up(m, 8);
@@ -129,14 +140,15 @@ void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max
 
 // One level of the forward sweep (L~ y = v, then y^ = P^{-1} y per element),
 // or of the backward sweep (z = y^ + P^{-1} (dt J_upper z - C z)).
+//   recs: nrec SwItem records of the level; tps elements per workgroup
+//   (SW_THREADS / tps threads each), region LDS elements per team.
 //   fp64: FP64 factors/values with double vectors; otherwise FP32 values
 //   and factors of type ftype with float vectors.
 //   v_slot/v_index: input of the forward sweep (FP64); result in SL_YH;
 //   acc_slot >= 0 adds the backward result to that FP64 slot (x += z).
-//   prefetch: every item's blocks fit the prefetching form (see k_sweep.hip).
-//   Items of one level, one workgroup (SW_THREADS threads) each.
-void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems,
-                  int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
+//   prefetch: every record's blocks fit the prefetching form (k_sweep.hip).
+void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
+                  int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                   int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
                   hipStream_t st, bool prefetch);
 

@@ -23,7 +23,9 @@
 // the uncoupled one.  The backward sweep overwrites y^ with z in place.
 //
 // A level holds roughly one element per compute unit, so the time of a level
-// is the latency of one element's chain of dependent products.  When the
+// is the latency of one element's chain of dependent products.  Each element
+// starts from one record (system, element, row position, block count and
+// columns) rather than a chain of index loads.  When the
 // blocks are small enough (prefetching form, PF), every thread issues the
 // loads of all its pivot and cross-block pieces and of the first columns of
 // the Jacobian row before anything else, so the element pays about one
@@ -86,8 +88,9 @@ __device__ __forceinline__ void prefetch_block(const GAS typename Vec16<TF>::st 
 }
 
 template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
-__device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int v_slot, int v_index,
-                                           int acc_slot, unsigned char *smem_raw)
+__device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, bool has, int tps,
+                                           int region, int v_slot, int v_index, int acc_slot,
+                                           unsigned char *smem_raw)
 {
     const int s = d.s, m = d.m, T = d.T;
     constexpr int VJ = Vec16<TJ>::V, VF = Vec16<TF>::V;
@@ -95,27 +98,20 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
     constexpr int QJ = 32 / VJ;       // prefetched loads per thread of the Jacobian row
     const int ldJ = ld_of<TJ>(d), ldF = ld_of<TF>(d);
     const int ldv = round_up(m, 8);
-    const int tpw = it.aux;
-    const int team = SW_THREADS / tpw;
+    const int team = SW_THREADS / tps;
     const int tm = threadIdx.x / team, tid = threadIdx.x - tm * team;
     const int RJ = ldJ / VJ, GJ = team / RJ;
     const int gJ = tid / RJ, sJ = tid - gJ * RJ;
     const int RF = ldF / VF, GF = team / RF;
     const int gF = tid / RF, sF = tid - gF * RF;
     const int maxg = d.maxrow * m;
-    const int region = sweep_region(S, m, d.maxrow, ldJ, VJ, ldF, VF, team);
     TC *base_lds = reinterpret_cast<TC *>(smem_raw) + (size_t)tm * region;
     TC *xg = base_lds;                       // gather, then partials
     TC *yv = base_lds + (region - 2 * S * ldv);   // [S][ldv]
     TC *uv = yv + S * ldv;                   // [S][ldv]
 
-    const bool has = tm < it.count;
     const long long n = (long long)T * m;
-    const GAS int *lvl = gp(FWD ? d.lvl_fwd : d.lvl_bwd);
-    const GAS int *row_ptr = gp(d.row_ptr);
-    const GAS int *col_idx = gp(d.col_idx);
-    const GAS int *diag_pos = gp(d.diag_pos);
-    const int i = has ? lvl[it.first + tm] : 0;
+    const int i = rec.i;
     GAS TC *yh = gp(reinterpret_cast<TC *>(d.vec[SL_YH]));
     const TC dt = (TC)d.dt;
     const auto Jb = jac_of<TJ>(d);
@@ -125,12 +121,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
     const int sm1 = s - 1;
     const bool fact = has && gF < GF;
 
-    int pa = 0, ncol = 0;
-    if (has) {
-        const int p0 = row_ptr[i], p1 = row_ptr[i + 1], pd = diag_pos[i];
-        pa = FWD ? p0 : pd + 1;
-        ncol = (FWD ? (pd - p0) : (p1 - pd - 1)) * m;
-    }
+    const int pa = rec.pa, ncol = rec.nb * m;
     const auto jrow = Jb + (size_t)pa * m * ldJ + sJ * VJ;
 
     // ---- prefetch: Jacobian row (first QJ column loads), pivots, cross blocks ----
@@ -168,7 +159,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
     if (has) {
         for (int q = tid; q < ncol; q += team) {
             const int b = q / m, c = q - b * m;
-            const long long j = col_idx[pa + b];
+            const long long j = (b < SW_NB) ? rec.col[b] : gp(d.col_idx)[pa + b];
 #pragma unroll
             for (int k = 0; k < S; ++k)
                 if (k < s) xg[k * maxg + q] = yh[k * n + j * m + c];
@@ -364,18 +355,25 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const Item it, int 
     }
 }
 
-// One level per launch: workgroup b handles items[b].
+// One level per launch: workgroup b handles records b*tps .. b*tps+tps-1.
 template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
 __global__ __launch_bounds__(SW_THREADS) void k_sweep(const SysDesc *__restrict__ sysv,
-                                                      const Item *__restrict__ items,
-                                                      int v_slot, int v_index, int acc_slot,
-                                                      int skip_done)
+                                                      const SwItem *__restrict__ recs, int nrec,
+                                                      int tps, int region, int v_slot, int v_index,
+                                                      int acc_slot, int skip_done)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const Item it = items[blockIdx.x];
-    if (skip_done && sysv[it.sys].st->done) return;
-    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PF>(sysv[it.sys], it, v_slot, v_index, acc_slot,
-                                                     smem_raw);
+    // every record of a workgroup belongs to one system (the host pads each
+    // system's records to whole workgroups), so the descriptor is uniform
+    const int sys = __builtin_amdgcn_readfirstlane(recs[blockIdx.x * tps].sys);
+    const SysDesc &d = sysv[sys];
+    if (skip_done && d.st->done) return;
+    const int team = SW_THREADS / tps;
+    const int idx = blockIdx.x * tps + threadIdx.x / team;
+    const SwItem rec = recs[min(idx, nrec - 1)];
+    const bool has = idx < nrec && rec.i >= 0;
+    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PF>(d, rec, has, tps, region, v_slot, v_index,
+                                                     acc_slot, smem_raw);
 }
 
 // Same register budget as the host's choice of form: variants beyond it are
@@ -386,14 +384,15 @@ constexpr bool pf_fits(int S, bool coupled, bool fp64)
 }
 
 template <int S, typename TJ, typename TF, typename TC, bool PF>
-static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items, int nitems,
-                           bool coupled, bool sharedJ, int v_slot, int v_index, int acc_slot,
-                           int skip_done, size_t shmem, hipStream_t st)
+static void launch_sweep_t(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
+                           int region, bool coupled, bool sharedJ, int v_slot, int v_index,
+                           int acc_slot, int skip_done, size_t shmem, hipStream_t st)
 {
-    dim3 grid(nitems), block(SW_THREADS);
+    dim3 grid((nrec + tps - 1) / tps), block(SW_THREADS);
 #define SW(C, SH, F)                                                                                   \
     hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F, PF && pf_fits(S, C, sizeof(TC) == 8)>), grid, \
-                       block, shmem, st, dsys, items, v_slot, v_index, acc_slot, skip_done)
+                       block, shmem, st, dsys, recs, nrec, tps, region, v_slot, v_index, acc_slot,   \
+                       skip_done)
     if (forward) {
         if (coupled) { if (sharedJ) SW(true, true, true); else SW(true, false, true); }
         else { if (sharedJ) SW(false, true, true); else SW(false, false, true); }
@@ -405,54 +404,43 @@ static void launch_sweep_t(bool forward, const SysDesc *dsys, const Item *items,
 }
 
 template <int S, bool PF>
-static void launch_sweep_p(bool forward, const SysDesc *dsys, const Item *items, int nitems,
-                           bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
+static void launch_sweep_p(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
+                           int region, bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
                            int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st)
 {
-    if (fp64) {
-        launch_sweep_t<S, double, double, double, PF>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                      v_slot, v_index, acc_slot, skip_done, shmem, st);
-    } else if (ftype == FT_F32) {
-        launch_sweep_t<S, float, float, float, PF>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                   v_slot, v_index, acc_slot, skip_done, shmem, st);
-    } else if (ftype == FT_BF16) {
-        launch_sweep_t<S, float, bf16s, float, PF>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                   v_slot, v_index, acc_slot, skip_done, shmem, st);
-    } else {
-        launch_sweep_t<S, float, f16s, float, PF>(forward, dsys, items, nitems, coupled, sharedJ,
-                                                  v_slot, v_index, acc_slot, skip_done, shmem, st);
-    }
+#define SWP(TJ, TF, TC)                                                                             \
+    launch_sweep_t<S, TJ, TF, TC, PF>(forward, dsys, recs, nrec, tps, region, coupled, sharedJ, v_slot, \
+                                      v_index, acc_slot, skip_done, shmem, st)
+    if (fp64) SWP(double, double, double);
+    else if (ftype == FT_F32) SWP(float, float, float);
+    else if (ftype == FT_BF16) SWP(float, bf16s, float);
+    else SWP(float, f16s, float);
+#undef SWP
 }
 
-template <int S>
-static void launch_sweep_s(bool forward, const SysDesc *dsys, const Item *items, int nitems,
-                           bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
-                           int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st,
-                           bool pf)
+void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
+                  int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
+                  int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st,
+                  bool prefetch)
 {
-    if (pf)
-        launch_sweep_p<S, true>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot,
-                                v_index, acc_slot, skip_done, shmem, st);
-    else
-        launch_sweep_p<S, false>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot,
-                                 v_index, acc_slot, skip_done, shmem, st);
-}
-
-void launch_sweep(bool forward, const SysDesc *dsys, const Item *items, int nitems, int s_max,
-                  bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot, int v_index,
-                  int acc_slot, int skip_done, size_t shmem, hipStream_t st, bool prefetch)
-{
-    if (nitems <= 0) return;
+    if (nrec <= 0) return;
+#define SWS(SS)                                                                                      \
+    do {                                                                                             \
+        if (prefetch)                                                                                \
+            launch_sweep_p<SS, true>(forward, dsys, recs, nrec, tps, region, fp64, ftype, coupled,   \
+                                     sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st);      \
+        else                                                                                         \
+            launch_sweep_p<SS, false>(forward, dsys, recs, nrec, tps, region, fp64, ftype, coupled,  \
+                                      sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st);     \
+    } while (0)
     switch (s_max) {
-#define SWS(SS) launch_sweep_s<SS>(forward, dsys, items, nitems, fp64, ftype, coupled, sharedJ, v_slot, \
-                                   v_index, acc_slot, skip_done, shmem, st, prefetch)
     case 1: SWS(1); break;
     case 2: SWS(2); break;
     case 3: SWS(3); break;
     case 4: SWS(4); break;
     default: SWS(5); break;
-#undef SWS
     }
+#undef SWS
 }
 
 }  // namespace irk
