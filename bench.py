@@ -72,6 +72,175 @@ def measured_traffic():
     return int(vals["traffic_bytes_per_launch"])
 
 
+def _log(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+def run_mixed(args):
+    """16^3 periodic hex mesh, m = 135, s = 3, dt = 0.5: plain FP64 GMRES
+    against the FP64 refinement loop with FP32 matvec and FP32 / BF16 /
+    FP16-scaled factors, all to a true relative residual of 1e-8.  One step
+    = factor + solve, operator resident."""
+    import torch
+    import dgsynth
+    import paper_1701_07181_amd as irk
+    steps = max(1, args.steps)
+    sy = dgsynth.config_system("cfg2")
+    rhs = torch.as_tensor(sy.rhs).cuda()
+    results = []
+    x_ref = None
+    for name, mv, fp in [("fp64", "fp64", "fp64"), ("fp32", "fp32", "fp32"),
+                         ("bf16", "fp32", "bf16"), ("fp16s", "fp32", "fp16s")]:
+        opts = irk.Options(pc="uncoupled_shifted", matvec_prec=mv, factor_prec=fp, rtol=1e-8,
+                           restart=30)
+        sol = irk.Solver(sy, opts)
+        for _ in range(max(1, args.warmup)):
+            sol.factor()
+            x, info = sol.solve(rhs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sol.factor()
+            x, info = sol.solve(rhs)
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / steps
+        if x_ref is None:
+            x_ref = x.clone()
+        err = float(torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref))
+        results.append({"variant": name, "solves_per_s": round(1.0 / dt_s, 3),
+                        "ms_per_solve": round(dt_s * 1e3, 2), "ms_factor": round(info["ms_factor"], 2),
+                        "iters": info["iters"], "outer_iters": info["outer_iters"],
+                        "rel_res_true": info["rel_res_true"], "rel_diff_vs_fp64": err,
+                        "converged": info["converged"]})
+        _log(f"mixed {name}: {results[-1]}")
+        sol.close()
+        del sol
+        torch.cuda.empty_cache()
+    return {"metric": "IRK solves/s at 1e-8 rel residual", "mode": "mixed", "unit": "solves/s",
+            "data": "synthetic",
+            "config": {"workload": "s=3 Radau IIA, periodic 16^3 hex mesh (T=4096), m=135, 7 blocks "
+                                   "per row, shifted uncoupled block ILU(0), GMRES(30), rtol 1e-8, dt=0.5",
+                       "steps": steps},
+            "results": results}
+
+
+def _build_systems(specs, torch):
+    systems = []
+    for q, sp in enumerate(specs):
+        sy = sp.build()
+        sy.J = torch.from_numpy(sy.J).cuda()
+        sy.M = torch.from_numpy(sy.M).cuda()
+        sy.rhs = torch.from_numpy(sy.rhs).cuda()
+        systems.append(sy)
+    torch.cuda.synchronize()
+    return systems
+
+
+def run_batched(args):
+    """256 independent systems of uneven size (2D periodic N in 4..32, p in
+    1..4, s in 2..4, dt log-uniform): FP32-inner / FP64-outer to 1e-8.  One
+    step = factor every system + one batched solve of all of them; compared
+    with the same solvers one by one and with plain FP64 one by one."""
+    import torch
+    import dgsynth
+    import paper_1701_07181_amd as irk
+    count = args.count or 256
+    specs = dgsynth.batch_specs(count)
+    t0 = time.time()
+    systems = _build_systems(specs, torch)
+    elems = sum(sy.T for sy in systems)
+    _log(f"built {count} systems ({elems} elements) in {time.time() - t0:.1f}s")
+    mixed = irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="fp32", rtol=1e-8,
+                        restart=30)
+    plain = irk.Options(pc="uncoupled_shifted", rtol=1e-8, restart=30)
+    res = {}
+    for label, opts in [("mixed", mixed), ("fp64", plain)]:
+        solvers = [irk.Solver(sy, opts) for sy in systems]
+        batch = irk.Batch(count, elems) if label == "mixed" else None
+        modes = ["batched", "one_by_one"] if batch else ["one_by_one"]
+        for mode in modes:
+            def step():
+                for s in solvers:
+                    s.factor()
+                if mode == "batched":
+                    xs, infos, st = irk.solve_batched(batch, solvers, [sy.rhs for sy in systems])
+                else:
+                    infos = [s.solve(sy.rhs)[1] for s, sy in zip(solvers, systems)]
+                return infos
+            step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(max(1, args.steps)):
+                infos = step()
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t1) / max(1, args.steps)
+            res[f"{label}_{mode}"] = {"solves_per_s": round(count / el, 2), "ms_per_step": round(el * 1e3, 2),
+                                      "converged": sum(bool(i["converged"]) for i in infos),
+                                      "mean_iters": round(sum(i["iters"] for i in infos) / count, 2),
+                                      "max_rel_res": max(i["rel_res_true"] for i in infos)}
+            _log(f"batched {label} {mode}: {res[f'{label}_{mode}']}")
+        for s in solvers:
+            s.close()
+        if batch:
+            batch.close()
+        torch.cuda.empty_cache()
+    return {"metric": "IRK solves/s at 1e-8 rel residual", "mode": "batched", "unit": "solves/s",
+            "data": "synthetic",
+            "config": {"workload": f"{count} systems: 2D periodic NxN, N in 4..32, DG p in 1..4 "
+                                   "(m = 4(p+1)^2), s in 2..4, dt log-uniform [0.01, 1], shifted "
+                                   "uncoupled block ILU(0), GMRES(30), rtol 1e-8",
+                       "elements": elems, "steps": max(1, args.steps)},
+            "results": res}
+
+
+def run_serve(args):
+    """Poisson arrivals of solve requests (75 % 2D up to 64x64 p 1..4, 25 % 3D
+    up to 16^3 p 2; s 2..4; 30 % re-use a resident operator), served by the
+    continuous-batching loop with FP32 inner / FP64 outer to 1e-8."""
+    import numpy as np
+    import torch
+    import dgsynth
+    import paper_1701_07181_amd as irk
+    from paper_1701_07181_amd.serve import Request, Server, latency_stats
+    count = args.count or 200
+    stream = dgsynth.serve_requests(count, N2max=48, N3max=12)
+    systems, reqs_base = {}, []
+    t0 = time.time()
+    for rid, (spec, reuse_of, rhs_seed) in enumerate(stream):
+        op = rid if reuse_of is None else reuse_of
+        if op not in systems:
+            sy = spec.build()
+            sy.J = torch.from_numpy(sy.J).cuda()
+            sy.M = torch.from_numpy(sy.M).cuda()
+            systems[op] = sy
+        sy = systems[op]
+        rhs = torch.from_numpy(dgsynth.fresh_rhs(rhs_seed, sy.s, sy.T, sy.m)).cuda()
+        reqs_base.append((rid, op, sy, rhs))
+    torch.cuda.synchronize()
+    _log(f"built {len(systems)} operators for {count} requests in {time.time() - t0:.1f}s")
+    opts = irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="fp32", rtol=1e-8,
+                       restart=30)
+    points = []
+    rng = np.random.default_rng(4242)
+    for qps in (50.0, 100.0, 200.0, 400.0):
+        arr = np.cumsum(rng.exponential(1.0 / qps, size=count))
+        reqs = [Request(rid, op, sy, rhs, float(a)) for (rid, op, sy, rhs), a in zip(reqs_base, arr)]
+        srv = Server(opts, capacity=64, max_elements=1 << 20, budget_bytes=120 << 30)
+        results = srv.run(reqs)
+        st = latency_stats(results)
+        srv.close()
+        st["offered_qps"] = qps
+        points.append(st)
+        _log(f"serve qps={qps}: {st}")
+        torch.cuda.empty_cache()
+    return {"metric": "IRK solves/s at 1e-8 rel residual; p99 latency", "mode": "serve",
+            "unit": "solves/s", "data": "synthetic",
+            "config": {"workload": f"{count} requests per arrival rate (Poisson), 75% 2D N<=48 p 1..4, "
+                                   "25% 3D N<=12 p=2, s 2..4, 30% operator re-use, FP32 inner / FP64 "
+                                   "outer, rtol 1e-8, capacity 64"},
+            "points": points}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +251,12 @@ def main():
     ap.add_argument("--N", type=int, default=64, help="mesh side (64 = the full workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around kernels")
+    ap.add_argument("--mode", default="headline", choices=["headline", "mixed", "batched", "serve"],
+                    help="headline: the FP64 64x64 workload (default); mixed: the 16^3 hex m=135 "
+                         "workload in FP64 and the three reduced-precision inner forms; batched: "
+                         "256 uneven systems solved together vs one by one; serve: a request "
+                         "stream at several arrival rates")
+    ap.add_argument("--count", type=int, default=0, help="systems / requests for batched and serve")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "known-size kernel that scales the HBM byte counters)")
@@ -106,6 +281,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
+        return
+    if args.mode != "headline":
+        out = {"mixed": run_mixed, "batched": run_batched, "serve": run_serve}[args.mode](args)
+        print(json.dumps(out), flush=True)
         return
     t0 = time.time()
     sy = dgsynth.config_system("cfg1", dt=args.dt, N=args.N)
