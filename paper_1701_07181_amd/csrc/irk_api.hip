@@ -1105,10 +1105,10 @@ irk_status irk_factor_ilu(irk_handle *h)
     for (size_t l = 0; l < h->fa.size(); ++l) {
         if (h->fa[l].n)
             launch_factor(0, h->dsys, h->ditems + h->fa[l].off, h->fa[l].n, h->coupled, h->sharedJ,
-                          h->shm_fac, h->stream);
+                          h->m <= 64, h->shm_fac, h->stream);
         if (h->coupled && h->fb[l].n)
             launch_factor(1, h->dsys, h->ditems + h->fb[l].off, h->fb[l].n, true, h->sharedJ,
-                          h->shm_fac, h->stream);
+                          h->m <= 64, h->shm_fac, h->stream);
     }
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
     prof_end(h, pf, PK_FACTOR);

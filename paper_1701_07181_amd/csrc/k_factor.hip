@@ -238,24 +238,29 @@ __device__ __forceinline__ int wg_invert(double *gptr, int m, int ld, double *ld
     return bad;
 }
 
-// Block product: the matrix-core path for m <= 64, the LDS-tiled one above.
+// Block product and inverse: the matrix-core path and the register
+// Gauss-Jordan for m <= 64 (SMALL), the LDS-tiled ones above otherwise.  The
+// kernels are compiled separately for the two classes so that each carries
+// only its own register demand.
+template <bool SMALL>
 __device__ __forceinline__ void blk_gemm(int m, int ld, double alpha, const double *A, const double *B,
                                          bool acc, double *C, double *lds)
 {
-    if (m <= 64) d64_gemm(m, ld, alpha, A, B, acc, C, lds);
+    if (SMALL) d64_gemm(m, ld, alpha, A, B, acc, C, lds);
     else wg_gemm(m, ld, alpha, A, B, acc, C, lds);
 }
 
+template <bool SMALL>
 __device__ __forceinline__ int wg_inverse(double *g, int m, int ld, double *lds)
 {
-    return (m <= 64) ? d64_invert(g, m, ld, lds) : wg_invert(g, m, ld, lds);
+    return SMALL ? d64_invert(g, m, ld, lds) : wg_invert(g, m, ld, lds);
 }
 
 __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
     if (threadIdx.x == 0) atomicCAS(&d.st->singular, 0, elem + 1);
 }
 
-template <bool COUPLED, bool SHJ>
+template <bool COUPLED, bool SHJ, bool SMALL>
 __global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict__ sysv,
                                                        const Item *__restrict__ items)
 {
@@ -290,15 +295,15 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict
     for (int p = p0; p < pd; ++p) {
         const long long j = col_idx[p];
         const double *Pinv_j = d.P64 + (j * s + k) * bs;
-        blk_gemm(m, ld, 1.0, Pinv_j, Jk + (long long)tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
-        blk_gemm(m, ld, -dt * dt, Jk + (long long)p * bs, X, true, Pk, lds);           // -= dt^2 J_ij X
+        blk_gemm<SMALL>(m, ld, 1.0, Pinv_j, Jk + (long long)tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
+        blk_gemm<SMALL>(m, ld, -dt * dt, Jk + (long long)p * bs, X, true, Pk, lds);           // -= dt^2 J_ij X
     }
     if (!COUPLED) {
-        if (wg_inverse(Pk, m, ld, lds)) flag_singular(d, i);
+        if (wg_inverse<SMALL>(Pk, m, ld, lds)) flag_singular(d, i);
     }
 }
 
-template <bool SHJ>
+template <bool SHJ, bool SMALL>
 __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict__ sysv,
                                                        const Item *__restrict__ items)
 {
@@ -319,12 +324,12 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict
     double *X = d.Fscr + ((long long)i * s + 1) * bs;
     const double *Mi = d.Mc + (long long)i * bs;
     for (int k = 0; k < s; ++k) {
-        if (wg_inverse(P(k), m, ld, lds)) flag_singular(d, i);
+        if (wg_inverse<SMALL>(P(k), m, ld, lds)) flag_singular(d, i);
         if (k == 0) {
             // every cross block is still A^{-1}_kl M_i: with X = M_i P_0^{-1} M_i,
             //   P_l  -= A^{-1}_l0 A^{-1}_0l X,   C_lq -= A^{-1}_l0 A^{-1}_0q X
-            blk_gemm(m, ld, 1.0, Mi, P(0), false, L, lds);
-            blk_gemm(m, ld, 1.0, L, Mi, false, X, lds);
+            blk_gemm<SMALL>(m, ld, 1.0, Mi, P(0), false, L, lds);
+            blk_gemm<SMALL>(m, ld, 1.0, L, Mi, false, X, lds);
             for (int l = 1; l < s; ++l)
                 for (int q = 1; q < s; ++q) {
                     double *D = (q == l) ? P(l) : C(l, q);
@@ -335,43 +340,57 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict
             continue;
         }
         for (int l = k + 1; l < s; ++l) {
-            blk_gemm(m, ld, 1.0, C(l, k), P(k), false, L, lds);          // L = C_lk P_k^{-1}
-            blk_gemm(m, ld, -1.0, L, C(k, l), true, P(l), lds);          // P_l -= L C_kl
+            blk_gemm<SMALL>(m, ld, 1.0, C(l, k), P(k), false, L, lds);          // L = C_lk P_k^{-1}
+            blk_gemm<SMALL>(m, ld, -1.0, L, C(k, l), true, P(l), lds);          // P_l -= L C_kl
             for (int q = k + 1; q < s; ++q) {
                 if (q == l) continue;
-                blk_gemm(m, ld, -1.0, L, C(k, q), true, C(l, q), lds);   // C_lq -= L C_kq
+                blk_gemm<SMALL>(m, ld, -1.0, L, C(k, q), true, C(l, q), lds);   // C_lq -= L C_kq
             }
         }
     }
 }
 
-void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
-                   bool sharedJ, size_t shmem, hipStream_t st)
+template <bool SMALL>
+static void launch_factor_t(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
+                            bool sharedJ, size_t shmem, hipStream_t st)
 {
     dim3 grid(nitems), block(NTHREADS);
+#define FA(C, SH) hipLaunchKernelGGL((k_factor_a<C, SH, SMALL>), grid, block, shmem, st, dsys, items)
+#define FB(SH) hipLaunchKernelGGL((k_factor_b<SH, SMALL>), grid, block, shmem, st, dsys, items)
     if (phase == 0) {
-        if (coupled) {
-            if (sharedJ) hipLaunchKernelGGL((k_factor_a<true, true>), grid, block, shmem, st, dsys, items);
-            else hipLaunchKernelGGL((k_factor_a<true, false>), grid, block, shmem, st, dsys, items);
-        } else {
-            if (sharedJ) hipLaunchKernelGGL((k_factor_a<false, true>), grid, block, shmem, st, dsys, items);
-            else hipLaunchKernelGGL((k_factor_a<false, false>), grid, block, shmem, st, dsys, items);
-        }
+        if (coupled) { if (sharedJ) FA(true, true); else FA(true, false); }
+        else { if (sharedJ) FA(false, true); else FA(false, false); }
     } else {
-        if (sharedJ) hipLaunchKernelGGL((k_factor_b<true>), grid, block, shmem, st, dsys, items);
-        else hipLaunchKernelGGL((k_factor_b<false>), grid, block, shmem, st, dsys, items);
+        if (sharedJ) FB(true); else FB(false);
     }
+#undef FA
+#undef FB
+}
+
+void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
+                   bool sharedJ, bool small, size_t shmem, hipStream_t st)
+{
+    if (small) launch_factor_t<true>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st);
+    else launch_factor_t<false>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st);
+}
+
+template <bool SMALL>
+static void set_lds_limit_t(size_t bytes)
+{
+    const int b = (int)bytes;
+    (void)hipFuncSetAttribute((const void *)k_factor_a<true, true, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void *)k_factor_a<true, false, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void *)k_factor_a<false, true, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void *)k_factor_a<false, false, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void *)k_factor_b<true, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    (void)hipFuncSetAttribute((const void *)k_factor_b<false, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
 }
 
 // Allow the factor kernels the LDS they need for m up to MMAX.
 void factor_set_lds_limit(size_t bytes)
 {
-    (void)hipFuncSetAttribute((const void *)k_factor_a<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_a<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_a<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_a<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_b<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_b<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    set_lds_limit_t<true>(bytes);
+    set_lds_limit_t<false>(bytes);
 }
 
 // ---------------------------------------------------------------------------

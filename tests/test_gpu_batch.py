@@ -98,3 +98,37 @@ def test_batch_rejects_mixed_kinds():
     out = batch.retire()
     assert len(out) == 1 and out[0][2]["converged"]
     batch.close()
+
+
+@pytest.mark.parametrize("pc,prec", [("coupled", "fp64"), ("uncoupled_shifted", "fp32")])
+def test_batch_mixed_launch_shapes(pc, prec, monkeypatch):
+    """Members with blocks of 16 to 100 rows and levels above and below the
+    size at which a sweep level switches from the prefetching to the
+    streaming form (lowered here so that small meshes cross it): launches
+    group members by elements per workgroup and pad each member to whole
+    workgroups; every member still equals its solo solve bitwise."""
+    irk = _irk()
+    monkeypatch.setenv("IRK_SWEEP_BIG", "12")
+    specs = dgsynth.batch_specs(count=8, seed=3300, Nmin=6, Nmax=12, pmax=4)
+    systems = [sp.build() for sp in specs]
+    assert len({sy.m for sy in systems}) >= 3
+    mixed = prec != "fp64"
+    opts = irk.Options(pc=pc, rtol=1e-8 if mixed else 1e-10,
+                       matvec_prec="fp32" if mixed else "fp64", factor_prec=prec)
+    solvers = []
+    for sy in systems:
+        so = irk.Solver(sy, opts)
+        so.factor()
+        solvers.append(so)
+    solo = [so.solve(sy.rhs) for so, sy in zip(solvers, systems)]
+    batch = irk.Batch(capacity=8, max_elements=sum(sy.T for sy in systems))
+    xs, infos, st = irk.solve_batched(batch, solvers, [sy.rhs for sy in systems])
+    assert st == irk.OK
+    for q, sy in enumerate(systems):
+        xsolo, isolo = solo[q]
+        assert infos[q]["converged"] and infos[q]["iters"] == isolo["iters"], (q, infos[q], isolo)
+        assert torch.equal(xs[q], xsolo), q
+        A, _, _ = oracle.radau_iia(sy.s)
+        r = sy.rhs - oracle.matvec(oracle.Problem(sy), oracle.inverse(A), xs[q].cpu().numpy())
+        assert np.linalg.norm(r) / np.linalg.norm(sy.rhs) <= (1e-8 if mixed else 1e-10) * 1.01
+    batch.close()
