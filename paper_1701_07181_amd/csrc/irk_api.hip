@@ -304,7 +304,8 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     }
     for (int sl = 0; sl < NSLOT; ++sl) {
         if (sl == SL_D) { P.o_vec[sl] = (size_t)-1; continue; }
-        const size_t n = (sl == SL_V) ? (size_t)(R + 1) * N : (size_t)N;
+        if (sl == SL_ZB && o->pc == IRK_PC_NONE) { P.o_vec[sl] = (size_t)-1; continue; }
+        const size_t n = (sl == SL_V) ? (size_t)(R + 1) * N : (sl == SL_ZB) ? (size_t)R * N : (size_t)N;
         P.o_vec[sl] = take(sizeof(double) * n);
     }
     P.o_H = take(sizeof(double) * (size_t)(R + 1) * R);
@@ -696,7 +697,8 @@ irk_status init_systems(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState
 
 // One GMRES cycle for every system of the work set (all unfinished):
 // up to `restart` Arnoldi steps (systems drop out when their estimate meets
-// the cycle tolerance), x += P^{-1} V y, FP64 true residual, next cycle start.
+// the cycle tolerance), x += Z y (z_j = P^{-1} v_j kept from the steps),
+// FP64 true residual, next cycle start.
 irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *hg)
 {
     WorkSet &W = *C.W;
@@ -706,6 +708,7 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
     for (int j = 0; j < W.restart; ++j) {
         if (W.has_pc) {
             enqueue_pc(C, fp64, SL_V, j, -1, 1);
+            launch_store_z(W.dsys, vec, W.vec.n, fp64, j, C.st);
         } else {
             launch_copy_to_yh(W.dsys, vec, W.vec.n, true, SL_V, j, 1, C.st);
         }
@@ -721,10 +724,10 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
             if (all_done) break;
         }
     }
-    // x += P^{-1} V y
-    launch_cycle_end(W.dsys, vec, W.vec.n, W.restart, C.st);
-    if (W.has_pc) enqueue_pc(C, fp64, SL_U, 0, SL_X, 0);
-    else launch_axpy(W.dsys, vec, W.vec.n, SL_X, SL_U, C.st);
+    // x += Z y with the stored z_j = P^{-1} v_j (equal to P^{-1} V y, without
+    // one more preconditioner application)
+    launch_cycle_end(W.dsys, vec, W.vec.n, W.restart, W.has_pc ? SL_ZB : SL_V, C.st);
+    launch_axpy(W.dsys, vec, W.vec.n, SL_X, SL_U, C.st);
     // FP64 true residual and the next cycle
     enqueue_matvec(C, true, SL_X, SL_R, SL_B, 1, 0);
     // the last step's flags (breakdown, non-finite) are read before the reset

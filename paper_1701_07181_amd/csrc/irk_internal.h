@@ -28,9 +28,10 @@ enum Slot : int {
     SL_X,       // solution / iterate                           (FP64)
     SL_B,       // right-hand side                              (FP64)
     SL_D,       // inner correction of the refinement loop      (FP64)
-    SL_U,       // combination V y at cycle end                 (FP64)
+    SL_U,       // combination Z y at cycle end                 (FP64)
     SL_EXT0,    // caller vectors for the kernel-level entry points
     SL_EXT1,
+    SL_ZB,      // preconditioned basis z_j = P^{-1} v_j, index j    (FP64)
     NSLOT
 };
 
@@ -169,8 +170,11 @@ void launch_quantize(const SysDesc *dsys, const SysDesc &hsys, int ftype, hipStr
 // one Arnoldi step j: CGS2 passes, Givens update, v_{j+1} = w / ||w||
 void launch_arnoldi(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int j,
                     hipStream_t st);
-// y = H^{-1} g over the cycle's steps, u = V y
-void launch_cycle_end(const SysDesc *dsys, const Item *vec, int nvec, int restart, hipStream_t st);
+// y = H^{-1} g over the cycle's steps, u = B y with B the basis in
+// basis_slot (SL_ZB: the preconditioned vectors, so x + u is the right-
+// preconditioned update; SL_V without a preconditioner)
+void launch_cycle_end(const SysDesc *dsys, const Item *vec, int nvec, int restart, int basis_slot,
+                      hipStream_t st);
 // ||slot||: which 0 -> st->bnorm; which 1 -> start of a cycle (beta, g, tolerance, flags)
 void launch_norm(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int slot,
                  int which, hipStream_t st);
@@ -179,6 +183,8 @@ void launch_start_cycle(const SysDesc *dsys, const Item *vec, int nvec, const It
                         int src_slot, hipStream_t st);
 void launch_axpy(const SysDesc *dsys, const Item *vec, int nvec, int dst_slot, int src_slot,
                  hipStream_t st);
+// SL_ZB[j] = SL_YH (the preconditioned vector just applied), as FP64
+void launch_store_z(const SysDesc *dsys, const Item *vec, int nvec, bool fp64, int j, hipStream_t st);
 // SL_YH = src_slot[src_index] in the compute type
 void launch_copy_to_yh(const SysDesc *dsys, const Item *vec, int nvec, bool fp64, int src_slot,
                        int src_index, int skip_done, hipStream_t st);

@@ -261,11 +261,9 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
 }
 
 template <bool COUPLED, bool SHJ, bool SMALL>
-__global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict__ sysv,
-                                                       const Item *__restrict__ items)
+__device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
+                                              const Item *__restrict__ items, double *lds)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *lds = reinterpret_cast<double *>(smem_raw);
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, ld = d.ld;
@@ -304,11 +302,9 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict
 }
 
 template <bool SHJ, bool SMALL>
-__global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict__ sysv,
-                                                       const Item *__restrict__ items)
+__device__ __forceinline__ void factor_b_body(const SysDesc *__restrict__ sysv,
+                                              const Item *__restrict__ items, double *lds)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    double *lds = reinterpret_cast<double *>(smem_raw);
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, ld = d.ld, sm1 = s - 1;
@@ -350,13 +346,53 @@ __global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict
     }
 }
 
+// Kernels: blocks of order <= 64 ask for four waves per SIMD (the products
+// run out of line, so the bodies fit 128 VGPRs); larger blocks keep the
+// default budget of the LDS-tiled routines.
+template <bool COUPLED, bool SHJ>
+__global__ __launch_bounds__(NTHREADS, 4) void k_factor_a64(const SysDesc *__restrict__ sysv,
+                                                          const Item *__restrict__ items)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    factor_a_body<COUPLED, SHJ, true>(sysv, items, reinterpret_cast<double *>(smem_raw));
+}
+template <bool COUPLED, bool SHJ>
+__global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict__ sysv,
+                                                       const Item *__restrict__ items)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    factor_a_body<COUPLED, SHJ, false>(sysv, items, reinterpret_cast<double *>(smem_raw));
+}
+template <bool SHJ>
+__global__ __launch_bounds__(NTHREADS, 4) void k_factor_b64(const SysDesc *__restrict__ sysv,
+                                                          const Item *__restrict__ items)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    factor_b_body<SHJ, true>(sysv, items, reinterpret_cast<double *>(smem_raw));
+}
+template <bool SHJ>
+__global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict__ sysv,
+                                                       const Item *__restrict__ items)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    factor_b_body<SHJ, false>(sysv, items, reinterpret_cast<double *>(smem_raw));
+}
+
 template <bool SMALL>
 static void launch_factor_t(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
                             bool sharedJ, size_t shmem, hipStream_t st)
 {
     dim3 grid(nitems), block(NTHREADS);
-#define FA(C, SH) hipLaunchKernelGGL((k_factor_a<C, SH, SMALL>), grid, block, shmem, st, dsys, items)
-#define FB(SH) hipLaunchKernelGGL((k_factor_b<SH, SMALL>), grid, block, shmem, st, dsys, items)
+#define FA(C, SH)                                                                                 \
+    do {                                                                                          \
+        if (SMALL) hipLaunchKernelGGL((k_factor_a64<C, SH>), grid, block, shmem, st, dsys, items); \
+        else hipLaunchKernelGGL((k_factor_a<C, SH>), grid, block, shmem, st, dsys, items);        \
+    } while (0)
+#define FB(SH)                                                                                    \
+    do {                                                                                          \
+        if (SMALL) hipLaunchKernelGGL((k_factor_b64<SH>), grid, block, shmem, st, dsys, items);    \
+        else hipLaunchKernelGGL((k_factor_b<SH>), grid, block, shmem, st, dsys, items);           \
+    } while (0)
     if (phase == 0) {
         if (coupled) { if (sharedJ) FA(true, true); else FA(true, false); }
         else { if (sharedJ) FA(false, true); else FA(false, false); }
@@ -374,23 +410,18 @@ void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems
     else launch_factor_t<false>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st);
 }
 
-template <bool SMALL>
-static void set_lds_limit_t(size_t bytes)
-{
-    const int b = (int)bytes;
-    (void)hipFuncSetAttribute((const void *)k_factor_a<true, true, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute((const void *)k_factor_a<true, false, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute((const void *)k_factor_a<false, true, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute((const void *)k_factor_a<false, false, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute((const void *)k_factor_b<true, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute((const void *)k_factor_b<false, SMALL>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-}
-
 // Allow the factor kernels the LDS they need for m up to MMAX.
 void factor_set_lds_limit(size_t bytes)
 {
-    set_lds_limit_t<true>(bytes);
-    set_lds_limit_t<false>(bytes);
+    const int b = (int)bytes;
+    const void *k[] = {
+        (const void *)k_factor_a<true, true>, (const void *)k_factor_a<true, false>,
+        (const void *)k_factor_a<false, true>, (const void *)k_factor_a<false, false>,
+        (const void *)k_factor_a64<true, true>, (const void *)k_factor_a64<true, false>,
+        (const void *)k_factor_a64<false, true>, (const void *)k_factor_a64<false, false>,
+        (const void *)k_factor_b<true>, (const void *)k_factor_b<false>,
+        (const void *)k_factor_b64<true>, (const void *)k_factor_b64<false>};
+    for (const void *f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
 }
 
 // ---------------------------------------------------------------------------

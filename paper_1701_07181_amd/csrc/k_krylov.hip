@@ -249,10 +249,10 @@ __global__ __launch_bounds__(NTHREADS) void k_norm_finish(const SysDesc *__restr
 }
 
 // y = H^{-1} g over the nv = st->j + 1 steps of the cycle (every workgroup
-// solves the small triangular system), u = V y
+// solves the small triangular system), u = B y for the basis B in basis_slot
 template <int NVMAX>
 __global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restrict__ sysv,
-                                                        const Item *__restrict__ items)
+                                                        const Item *__restrict__ items, int basis_slot)
 {
     __shared__ double ys[NVMAX];
     const Item it = items[blockIdx.x];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restric
             for (int i = 0; i < nv; ++i) d.y[i] = ys[i];
     }
     __syncthreads();
-    const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[SL_V]));
+    const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[basis_slot]));
     GAS double *u = gp(reinterpret_cast<double *>(d.vec[SL_U]));
     for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
          e += (long long)it.count * NTHREADS) {
@@ -312,6 +312,22 @@ __global__ __launch_bounds__(NTHREADS) void k_copy_yh(const SysDesc *__restrict_
     for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
          e += (long long)it.count * NTHREADS)
         dst[e] = (TD)src[e];
+}
+
+// SL_ZB[j] = (double) SL_YH (skipped for systems whose cycle has ended)
+template <typename TS>
+__global__ __launch_bounds__(NTHREADS) void k_store_z(const SysDesc *__restrict__ sysv,
+                                                      const Item *__restrict__ items, int j)
+{
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    if (d.st->done) return;
+    const long long N = d.N;
+    const GAS TS *src = gp(reinterpret_cast<const TS *>(d.vec[SL_YH]));
+    GAS double *dst = gp(reinterpret_cast<double *>(d.vec[SL_ZB])) + (long long)j * N;
+    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
+         e += (long long)it.count * NTHREADS)
+        dst[e] = (double)src[e];
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_fill_zero_slot(const SysDesc *__restrict__ sysv,
@@ -380,13 +396,14 @@ void launch_arnoldi(const SysDesc *dsys, const Item *vec, int nvec, const Item *
                        (int)SL_W, 1);
 }
 
-void launch_cycle_end(const SysDesc *dsys, const Item *vec, int nvec, int restart, hipStream_t st)
+void launch_cycle_end(const SysDesc *dsys, const Item *vec, int nvec, int restart, int basis_slot,
+                      hipStream_t st)
 {
     dim3 g(nvec), b(NTHREADS);
-    if (restart <= 8) hipLaunchKernelGGL((k_cycle_end<8>), g, b, 0, st, dsys, vec);
-    else if (restart <= 16) hipLaunchKernelGGL((k_cycle_end<16>), g, b, 0, st, dsys, vec);
-    else if (restart <= 32) hipLaunchKernelGGL((k_cycle_end<32>), g, b, 0, st, dsys, vec);
-    else hipLaunchKernelGGL((k_cycle_end<64>), g, b, 0, st, dsys, vec);
+    if (restart <= 8) hipLaunchKernelGGL((k_cycle_end<8>), g, b, 0, st, dsys, vec, basis_slot);
+    else if (restart <= 16) hipLaunchKernelGGL((k_cycle_end<16>), g, b, 0, st, dsys, vec, basis_slot);
+    else if (restart <= 32) hipLaunchKernelGGL((k_cycle_end<32>), g, b, 0, st, dsys, vec, basis_slot);
+    else hipLaunchKernelGGL((k_cycle_end<64>), g, b, 0, st, dsys, vec, basis_slot);
 }
 
 void launch_norm(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin, int slot,
@@ -418,6 +435,12 @@ void launch_copy_to_yh(const SysDesc *dsys, const Item *vec, int nvec, bool fp64
     else
         hipLaunchKernelGGL(k_copy_yh<float>, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, src_slot,
                            src_index, skip_done);
+}
+
+void launch_store_z(const SysDesc *dsys, const Item *vec, int nvec, bool fp64, int j, hipStream_t st)
+{
+    if (fp64) hipLaunchKernelGGL(k_store_z<double>, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, j);
+    else hipLaunchKernelGGL(k_store_z<float>, dim3(nvec), dim3(NTHREADS), 0, st, dsys, vec, j);
 }
 
 void launch_fill_zero_slot(const SysDesc *dsys, const Item *vec, int nvec, int slot, hipStream_t st)

@@ -37,11 +37,27 @@
 namespace irk {
 
 // Reduce team partials red[g][S][ldr] over g for stage k, row r.
+// Four running sums over g = 0, 4, 8, ... (+1, +2, +3) keep four LDS loads in
+// flight; they are combined as (a0 + a1) + (a2 + a3), a fixed order.
+template <typename TC>
+__device__ __forceinline__ TC sum_strided(const TC *p, int G, int stride) {
+    TC a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int g = 0;
+    for (; g + 4 <= G; g += 4) {
+        a0 += p[g * stride];
+        a1 += p[(g + 1) * stride];
+        a2 += p[(g + 2) * stride];
+        a3 += p[(g + 3) * stride];
+    }
+    if (g < G) a0 += p[g * stride];
+    if (g + 1 < G) a1 += p[(g + 1) * stride];
+    if (g + 2 < G) a2 += p[(g + 2) * stride];
+    return (a0 + a1) + (a2 + a3);
+}
+
 template <typename TC, int S>
 __device__ __forceinline__ TC sum_groups(const TC *red, int G, int k, int ldr, int r) {
-    TC a = 0;
-    for (int g = 0; g < G; ++g) a += red[(g * S + k) * ldr + r];
-    return a;
+    return sum_strided(red + k * ldr + r, G, S * ldr);
 }
 
 // acc[v] += column c of a block (rows slot*V .. slot*V+V-1) times x, for the
@@ -309,8 +325,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
             if (act) {
                 const TC sc = block_scale<TF, TC>(d.P16e, (long long)i * s + k);
                 for (int r = tid; r < m; r += team) {
-                    TC o = 0;
-                    for (int g = 0; g < GF; ++g) o += red[g * ldF + r];
+                    TC o = sum_strided(red + r, GF, ldF);
                     o *= sc;
                     const long long gi = k * n + (long long)i * m + r;
                     if (!FWD) o += yv[k * ldv + r];
