@@ -1,19 +1,20 @@
-// dense64.h -- dense FP64 block kernels for blocks of order m <= 64, run by
-// one 256-thread workgroup (four waves):
+// dense64.h -- dense FP64 block kernels (product on the matrix cores,
+// Gauss-Jordan inverse in registers).  Blocks of order m <= 64 are run by one
+// 256-thread workgroup (four waves):
 //
 //   * d64_gemm: C = alpha A B (+ C) for column-major blocks on the FP64
 //     matrix cores (v_mfma_f64_16x16x4f64).  Each wave owns a 32 x 32
-//     quadrant of the 64 x 64 output (2 x 2 tiles of 16 x 16); the operands
-//     pass through LDS in K panels of 32, so a K step costs every wave two A
-//     and two B fragment loads for four matrix instructions.
+//     quadrant of the 64 x 64 output (2 x 2 tiles of 16 x 16) and loads its
+//     operands from global memory directly (no LDS, no barrier inside).
 //   * d64_invert: in-place Gauss-Jordan inversion with partial pivoting.
 //     Lane r of wave w keeps row r, columns 16w .. 16w+15 in registers.  The
-//     wave that owns the pivot column compares every unused row against the
-//     first unused one with a single wave vote and searches the column only
-//     when some row is larger, so the chosen pivot is the largest entry
-//     (first of equals) as in ordinary partial pivoting.  Rows are never
+//     wave that owns the pivot column finds the largest candidate with a
+//     DPP maximum of a 32-bit key (pivot_key) and one ballot.  Rows are never
 //     moved; the row and column permutations are undone when the inverse is
 //     written back.
+//
+// Blocks of order 64 < m <= 160 use the same two methods, sized for
+// 512-thread workgroups (dm_gemm, dm_invert).
 #pragma once
 #include "irk_device.h"
 
@@ -21,7 +22,7 @@ namespace irk {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int D64_LDS_DOUBLES = 4352;       // the larger of the inversion (4291) and product (4160) needs
+constexpr int D64_LDS_DOUBLES = 4291;       // the inversion's (the product uses none)
 
 // Fragment layouts of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l
 // supplies A(l % 16, l / 16) and B(l / 16, l % 16); element r of the result
@@ -29,119 +30,125 @@ constexpr int D64_LDS_DOUBLES = 4352;       // the larger of the inversion (4291
 __device__ __forceinline__ int d64_frag_row(int lane, int r) { return 4 * r + (lane >> 4); }
 __device__ __forceinline__ int d64_frag_col(int lane) { return lane & 15; }
 
+// index of the calling wave in its workgroup, as a scalar (uniform) value
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// K panels of 32: A(:, k0:k0+32) -> As[kk * 64 + i] and B(k0:k0+32, :) ->
-// Bs[j * 33 + kk] (odd stride: conflict-free fragment reads), zero outside
-// m.  Each thread moves four 16-byte pieces of each operand per panel, all
-// loads issued before the first LDS write.
-constexpr int D64_KP = 32;
-constexpr int D64_LDB = 33;
 
-__device__ __forceinline__ void d64_stage_panel(double *As, double *Bs, const GAS double *A,
-                                                const GAS double *B, int m, int ld, int k0)
+// C = alpha A B (+ C when add) for column-major m x m blocks (m <= 64,
+// leading dimension ld) on the FP64 matrix cores, without LDS: wave w owns
+// the 32 x 32 quadrant (w & 1, w >> 1) of C (up to 2 x 2 tiles of 16 x 16,
+// tiles wholly outside m skipped) and loads its matrix-core operands
+// straight from global memory.  K is taken in blocks of 8; inside block t
+// lane (r, kq) of step u supplies k = 8 t + 2 kq + u, so its two B values of
+// a block are one 16-byte load and its A values are 16 consecutive doubles
+// of a column per lane group.  Two blocks are in flight while one is
+// multiplied.  With add the accumulators start from alpha * C, which
+// requires alpha = 1 or -1 (then C + alpha A B is alpha * (alpha C + A B),
+// exactly).  C must not overlap A or B.  Ends with a workgroup barrier, so
+// the result can be read by every wave of the workgroup afterwards.
+struct D64Ops {
+    double a[2][2];     // A(i, k) of tiles x = 0, 1 for the two steps of a block
+    dbl2 b[2];          // B(k, j) of tiles y = 0, 1 for the two steps
+};
+
+// Loads of block t; every address is clamped into the block, so the loads
+// are unconditional (K padding is zeroed when the values are used).
+__device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, const GAS double *B, int m, int ld,
+                                             int i0, int j0, int kq, int t)
 {
-    dbl2 ra[4], rb[4];
+    const int kb = 8 * t + 2 * kq;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + q * NTHREADS;        // 0 .. 1023
-        const int kk = e >> 5, i = (e & 31) * 2;         // A: column k0+kk, rows i, i+1
-        ra[q] = *reinterpret_cast<const GAS dbl2 *>(A + (size_t)min(k0 + kk, m - 1) * ld + min(i, ld - 2));
-        const int j = e >> 4, kb = (e & 15) * 2;         // B: column j, rows k0+kb, +1
-        rb[q] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j, m - 1) * ld + min(k0 + kb, ld - 2));
-    }
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + q * NTHREADS;
-        const int kk = e >> 5, i = (e & 31) * 2;
-        dbl2 x = ra[q];
-        if (k0 + kk >= m || i >= m) x.x = 0.0;
-        if (k0 + kk >= m || i + 1 >= m) x.y = 0.0;
-        *reinterpret_cast<dbl2 *>(As + kk * 64 + i) = x;
-        const int j = e >> 4, kb = (e & 15) * 2;
-        Bs[j * D64_LDB + kb] = (j < m && k0 + kb < m) ? rb[q].x : 0.0;
-        Bs[j * D64_LDB + kb + 1] = (j < m && k0 + kb + 1 < m) ? rb[q].y : 0.0;
+        for (int u = 0; u < 2; ++u)
+            o.a[x][u] = A[(size_t)min(kb + u, m - 1) * ld + min(i0 + 16 * x, ld - 1)];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+        o.b[y] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j0 + 16 * y, m - 1) * ld + min(kb, ld - 2));
+}
+
+template <bool FULL>
+__device__ __forceinline__ void d64_mma_ops(const D64Ops &o, int m, int kq, int t, int nx, int ny,
+                                            dbl4 (&acc)[2][2])
+{
+    const int kb = 8 * t + 2 * kq;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const bool kin = kb + u < m;
+        double av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) av[x] = kin ? o.a[x][u] : 0.0;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bv[y] = kin ? (u ? o.b[y].y : o.b[y].x) : 0.0;
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                if (!FULL && (x >= nx || y >= ny)) continue;
+                acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+            }
     }
 }
 
-// acc += this wave's quadrant of one K panel (nkc steps of 4).
-__device__ __forceinline__ void d64_mma_panel(const double *As, const double *Bs, int nkc, dbl4 (&acc)[2][2])
+template <bool FULL>
+__device__ __forceinline__ void d64_gemm_tiles(int m, int ld, double alpha, const GAS double *A,
+                                               const GAS double *B, bool add, GAS double *C, int nx, int ny)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
     const int qi = w & 1, qj = w >> 1;
     const int r = lane & 15, kq = lane >> 4;
-    const double *ap = As + kq * 64 + 32 * qi + r;
-    const double *bp = Bs + (32 * qj + r) * D64_LDB + kq;
-#pragma unroll 2
-    for (int kc = 0; kc < nkc; ++kc) {
-        const double a0 = ap[kc * 4 * 64], a1 = ap[kc * 4 * 64 + 16];
-        const double b0 = bp[kc * 4], b1 = bp[kc * 4 + 16 * D64_LDB];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-    }
-}
-
-__device__ __forceinline__ void d64_zero(dbl4 (&acc)[2][2])
-{
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
-}
-
-// C = alpha acc (+ C when add) for rows and columns below m.  The old
-// values are all loaded before the first store.
-__device__ __forceinline__ void d64_store(double *gC, int m, int ld, double alpha, bool add,
-                                          const dbl4 (&acc)[2][2])
-{
-    GAS double *C = gp(gC);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int qi = w & 1, qj = w >> 1;
-    double old[2][2][4];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = 32 * qj + 16 * y + d64_frag_col(lane);
-                const int i = 32 * qi + 16 * x + d64_frag_row(lane, r);
-                old[x][y][r] = 0.0;
-                if (add && i < m && j < m) old[x][y][r] = C[(size_t)j * ld + i];
-            }
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = 32 * qj + 16 * y + d64_frag_col(lane);
-                const int i = 32 * qi + 16 * x + d64_frag_row(lane, r);
-                if (i < m && j < m) C[(size_t)j * ld + i] = fma(alpha, acc[x][y][r], old[x][y][r]);
-            }
-}
-
-// C = alpha A B (+ C when add); blocks m x m column-major with leading
-// dimension ld; C must not overlap A or B.  The operands pass through LDS in
-// K panels of 32 (33 KB).  Not inlined: one body serves every call site of a
-// kernel, which keeps the kernels' register demand (and so their occupancy)
-// at the level of the product itself.
-__device__ __noinline__ void d64_gemm(int m, int ld, double alpha, const double *gA, const double *gB,
-                                      bool add, double *C, double *lds)
-{
-    const GAS double *A = gp(gA);
-    const GAS double *B = gp(gB);
-    double *As = lds, *Bs = lds + 64 * D64_KP;
+    const int i0 = 32 * qi + r, j0 = 32 * qj + r;
     dbl4 acc[2][2];
-    d64_zero(acc);
-    for (int k0 = 0; k0 < m; k0 += D64_KP) {
-        d64_stage_panel(As, Bs, A, B, m, ld, k0);
-        __syncthreads();
-        d64_mma_panel(As, Bs, (min(m - k0, D64_KP) + 3) >> 2, acc);
-        __syncthreads();
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 32 * qi + 16 * x + d64_frag_row(lane, q);
+                const int j = 32 * qj + 16 * y + d64_frag_col(lane);
+                const double old = C[(size_t)min(j, m - 1) * ld + min(i, m - 1)];
+                acc[x][y][q] = (add && i < m && j < m) ? alpha * old : 0.0;
+            }
+    // FULL (all 2 x 2 tiles, eight K blocks): straight-line code, so the
+    // waits before each block's products leave the two later blocks' loads
+    // in flight; otherwise blocks past the last one are skipped
+    const int nb = FULL ? 8 : (m + 7) >> 3;
+    D64Ops o[3];
+    d64_load_ops(o[0], A, B, m, ld, i0, j0, kq, 0);
+    if (FULL || nb > 1) d64_load_ops(o[1], A, B, m, ld, i0, j0, kq, 1);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        if (!FULL && t >= nb) continue;
+        if (FULL ? (t + 2 < 8) : (t + 2 < nb)) d64_load_ops(o[(t + 2) % 3], A, B, m, ld, i0, j0, kq, t + 2);
+        d64_mma_ops<FULL>(o[t % 3], m, kq, t, nx, ny, acc);
     }
-    d64_store(C, m, ld, alpha, add, acc);
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            if (!FULL && (x >= nx || y >= ny)) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 32 * qi + 16 * x + d64_frag_row(lane, q);
+                const int j = 32 * qj + 16 * y + d64_frag_col(lane);
+                if (i < m && j < m) C[(size_t)j * ld + i] = alpha * acc[x][y][q];
+            }
+        }
+}
+
+__device__ __forceinline__ void d64_gemm(int m, int ld, double alpha, const double *gA, const double *gB,
+                                         bool add, double *gC)
+{
+    // opaque copies of the sizes: keeps the per-lane operand offsets inside
+    // each call instead of letting them be hoisted (and held in registers)
+    // across a caller's loop of products
+    asm volatile("" : "+s"(m), "+s"(ld));
+    const int w = wave_id();
+    const int nx = min(2, max(0, (m - 32 * (w & 1) + 15) >> 4));      // tiles holding rows below m
+    const int ny = min(2, max(0, (m - 32 * (w >> 1) + 15) >> 4));
+    if (m > 56) d64_gemm_tiles<true>(m, ld, alpha, gp(gA), gp(gB), add, gp(gC), 2, 2);
+    else if (nx > 0 && ny > 0) d64_gemm_tiles<false>(m, ld, alpha, gp(gA), gp(gB), add, gp(gC), nx, ny);
     __syncthreads();
 }
 
@@ -153,23 +160,79 @@ __device__ __forceinline__ double d64_readlane(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// In-place inverse of the m x m block at gptr.  The memory image is handled
-// as the row-major matrix Q = P^T (row stride ld); writing Q^{-1} back the
-// same way leaves P^{-1} in column-major order.  Returns nonzero (in every
-// thread) when a pivot is zero or a pivot column holds a non-finite value.
+// Maximum of x over the 64 lanes of a wave (every lane active), as a scalar:
+// DPP exchanges inside each row of 16 lanes (quad swaps, half-row and row
+// mirrors), then the four row results.
+__device__ __forceinline__ int wave_max_i32(int x)
+{
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false));    // quad_perm 1,0,3,2
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false));    // quad_perm 2,3,0,1
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false));   // row_half_mirror
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false));   // row_mirror
+    const int r0 = __builtin_amdgcn_readlane(x, 0), r1 = __builtin_amdgcn_readlane(x, 16);
+    const int r2 = __builtin_amdgcn_readlane(x, 32), r3 = __builtin_amdgcn_readlane(x, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
+// Pivot key of a candidate entry: the high word of |v| (sign cleared), which
+// orders non-negative doubles like their values up to the top 20 mantissa
+// bits; -1 for rows already used.  The pivot is the first unused row whose
+// key equals the column maximum, so its magnitude is within a factor
+// 1 - 2^-20 of the largest one (partial pivoting).
+__device__ __forceinline__ int pivot_key(double v, bool unused_row)
+{
+    return unused_row ? (__double2hiint(v) & 0x7fffffff) : -1;
+}
+
+// 1 / x from the hardware reciprocal and one Newton step (three dependent
+// operations instead of a full division; a few ulp at most for normal x).
+__device__ __forceinline__ double fast_recip(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Pivot choice for the column v (one value per lane = row) among the rows
+// marked in unused, by the owner wave (every lane active): publishes the
+// column, the pivot row (with 0x100 set when the pivot is zero or the column
+// holds a non-finite value) and 1 / pivot.
+__device__ __forceinline__ void d64_publish(double v, unsigned long long unused, int lane, double *col, int *pw,
+                                            double *pinv)
+{
+    const bool mine = (unused >> lane) & 1ull;
+    const int key = pivot_key(v, mine);
+    const int K = wave_max_i32(key);
+    const bool nonfin = __any(mine && !isfinite(v));
+    const int p = __builtin_ctzll(__ballot(key == K));
+    const double piv = d64_readlane(v, p);
+    col[lane] = v;
+    if (lane == 0) {
+        *pw = p | ((nonfin || K <= 0 || !isfinite(piv)) ? 0x100 : 0);
+        *pinv = fast_recip(piv);
+    }
+}
+
+// In-place inverse of the column-major m x m block P at gptr.  Returns
+// nonzero (in every thread) when a pivot is zero or a pivot column holds a
+// non-finite value.
+//
+// Lane r of wave w keeps row r of P, columns 16w .. 16w+15, in registers
+// (consecutive lanes read consecutive doubles of a column: coalesced).
 //
 // Pivot rows are not scaled when they are used: a row that served as pivot
 // with value piv is stored as piv times its Gauss-Jordan value (the update
 // of every other row is the same either way), and the scale is removed when
-// the result is written back.  Step c: the wave owning column c picks the
-// pivot row p and publishes the column, p and 1/piv through LDS; after one
-// barrier every wave updates its 16 columns from row p (read with
-// v_readlane) and the column multipliers.
-// LDS: 2 * 64 + 2 + 64 * 64 doubles + 132 ints.
+// the result is written back.  Step c, after one barrier: every wave reads
+// the published column c, pivot row p and 1/piv, takes row p of its columns
+// with v_readlane and updates them.  The owner of column c+1 updates that
+// column first and publishes its pivot choice (look-ahead), so the search
+// overlaps the other updates and each step costs one barrier.
+// LDS: 2 * 64 + 2 + 64 * 64 doubles + 130 ints.
 __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *lds)
 {
     GAS double *g = gp(gptr);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    asm volatile("" : "+s"(m), "+s"(ld));      // nothing of a call hoisted into a caller's loop
+    const int lane = threadIdx.x & 63, w = wave_id();
     double *colbuf = lds;                                          // [2][64] pivot columns
     double *pinvbuf = lds + 128;                                   // [2] 1 / pivot
     double *stage = lds + 130;                                     // [64][64] permuted result
@@ -177,17 +240,15 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
     int *step_of_row = pbuf + 2;                                   // [64]
     int *row_of_step = pbuf + 66;                                  // [64]
     double a[16];
-    {
-        const GAS double *src = g + (size_t)lane * ld + 16 * w;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int c = 16 * w + j;
-            a[j] = (lane < m && c < m) ? src[j] : (lane == c ? 1.0 : 0.0);
-        }
+    for (int j = 0; j < 16; ++j) {
+        const int c = 16 * w + j;
+        a[j] = (lane < m && c < m) ? g[(size_t)c * ld + lane] : (lane == c ? 1.0 : 0.0);
     }
     unsigned long long unused = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
     double myscale = 1.0;           // pivot value of this lane's row once it has been used
     int bad = 0;
+    if (w == 0) d64_publish(a[0], unused, lane, colbuf, pbuf, pinvbuf);
     for (int wc = 0; wc < 4; ++wc) {
         if (16 * wc >= m) break;
 #pragma unroll
@@ -195,34 +256,6 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
             const int c = 16 * wc + cc;
             if (c >= m) continue;           // uniform: every thread skips the same steps
             const int par = c & 1;
-            if (w == wc) {
-                const double v = a[cc];
-                const int n = __builtin_ctzll(unused);
-                const double vn = d64_readlane(v, n);
-                const bool mine = (unused >> lane) & 1ull;
-                const bool big = __any(mine && fabs(v) > fabs(vn));
-                const bool nonfin = __any(mine && !isfinite(v));
-                int p = n;
-                double piv = vn;
-                if (big) {
-                    double best = mine ? fabs(v) : -1.0;
-                    int bi = mine ? lane : 64;
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const double ob = __shfl_xor(best, o);
-                        const int oi = __shfl_xor(bi, o);
-                        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                    }
-                    p = __builtin_amdgcn_readfirstlane(bi);
-                    if (p < 0 || p >= 64 || !((unused >> p) & 1ull)) p = n;
-                    piv = d64_readlane(v, p);
-                }
-                colbuf[par * 64 + lane] = v;
-                if (lane == 0) {
-                    pbuf[par] = p | ((nonfin || !(fabs(piv) > 0.0) || !isfinite(piv)) ? 0x100 : 0);
-                    pinvbuf[par] = 1.0 / piv;
-                }
-            }
             __syncthreads();
             const int pw = __builtin_amdgcn_readfirstlane(pbuf[par]);
             const double pinv = pinvbuf[par];
@@ -232,51 +265,74 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
             const bool isp = (lane == p);
             const double gm = isp ? 0.0 : f * pinv;
             if (isp) myscale = f;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) a[j] = fma(-gm, d64_readlane(a[j], p), a[j]);
-            if (w == wc) a[cc] = isp ? 1.0 : -gm;
             unused &= ~(1ull << p);
+            // row p of this wave's columns
+            double prow[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) prow[j] = d64_readlane(a[j], p);
+            // column c + 1 (index cn of wave wn): updated and searched first
+            const int cn = (cc + 1) & 15;        // a constant once the loop is unrolled
+            const int wn = (cc == 15) ? wc + 1 : wc;
+            const bool ahead = (c + 1 < m) && (w == wn);
+            if (ahead) {
+                a[cn] = fma(-gm, prow[cn], a[cn]);
+                d64_publish(a[cn], unused, lane, colbuf + (par ^ 1) * 64, pbuf + (par ^ 1), pinvbuf + (par ^ 1));
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                if (j == cn && ahead) continue;
+                a[j] = fma(-gm, prow[j], a[j]);
+            }
+            if (w == wc) a[cc] = isp ? 1.0 : -gm;
             if (threadIdx.x == 0) { step_of_row[p] = c; row_of_step[c] = p; }
         }
     }
     __syncthreads();
-    // element (r, c) of the result is Q^{-1}(step(r), row(c)) times the scale of row r
+    // the value kept for (row r, column c) is P^{-1}(step(r), row(c)) times
+    // the pivot of row r; stage[col * 64 + row] is written one column per
+    // instruction (conflict-free), then copied out column by column
     if (lane < m) {
         const int row = step_of_row[lane];
         const double sc = 1.0 / myscale;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int c = 16 * w + j;
-            if (c < m) stage[row * 64 + row_of_step[c]] = a[j] * sc;
+            if (c < m) stage[row_of_step[c] * 64 + row] = a[j] * sc;
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < m * 64; e += NTHREADS) {
-        const int r = e >> 6, c = e & 63;
-        if (c < m) g[(size_t)r * ld + c] = stage[e];
+        const int c = e >> 6, r = e & 63;
+        if (r < m) g[(size_t)c * ld + r] = stage[e];
     }
     __syncthreads();
     return bad;
 }
 
 // ---------------------------------------------------------------------------
-// C = alpha A B (+ C when add) for column-major blocks of order 64 < m <= 160
-// on the FP64 matrix cores.  The 16 x 16 output tiles (NT = ceil(m/16) per
-// side) are split into four quadrants, one per wave (at most 5 x 5 tiles, 25
-// accumulators of four doubles).  K runs in panels of 16: A(:, panel) ->
-// Am[kk][i] (row stride 160) and B(panel, :) -> Bm[j][kk] (stride 17, odd:
-// conflict-free fragment reads); the next panel's loads are issued before the
-// current panel is multiplied.  LDS: 16 * 160 + 160 * 17 doubles.
+// Blocks of order 64 < m <= 160 are processed by 512-thread workgroups
+// (eight waves, two per SIMD).
 // ---------------------------------------------------------------------------
+constexpr int DM_TEAM = 512;
+
+// C = alpha A B (+ C when add) for column-major blocks on the FP64 matrix
+// cores.  The NT x NT grid of 16 x 16 output tiles (NT = ceil(m / 16) <= 10)
+// is split in two tile-row halves and four tile-column quarters, one part
+// per wave (at most 5 x 3 tiles, 15 accumulators of four doubles).  K runs
+// in panels of 16: A(:, panel) -> Am[kk * 160 + i] and B(panel, :) ->
+// Bm[j * 17 + kk] (odd stride: conflict-free fragment reads); the next
+// panel's loads are issued before the current panel is multiplied.
 constexpr int DM_AP = 160, DM_BP = 17, DM_KP = 16;
+constexpr int DM_PIECES = DM_KP * DM_AP / 2;           // 16-byte pieces of either panel (1280)
+constexpr int DM_Q = (DM_PIECES + DM_TEAM - 1) / DM_TEAM;
 constexpr int DM_LDS_DOUBLES = DM_KP * DM_AP + DM_AP * DM_BP;
 
 __device__ __forceinline__ void dm_load_panel(const GAS double *A, const GAS double *B, int m, int ld,
-                                              int k0, dbl2 (&ra)[5], dbl2 (&rb)[5])
+                                              int k0, dbl2 (&ra)[DM_Q], dbl2 (&rb)[DM_Q])
 {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const int e = threadIdx.x + q * NTHREADS;        // 0 .. 1279
+    for (int q = 0; q < DM_Q; ++q) {
+        const int e = min((int)threadIdx.x + q * DM_TEAM, DM_PIECES - 1);
         const int kk = e / 80, i = (e - kk * 80) * 2;     // A: column k0+kk, rows i, i+1
         ra[q] = *reinterpret_cast<const GAS dbl2 *>(A + (size_t)min(k0 + kk, m - 1) * ld + min(i, ld - 2));
         const int j = e >> 3, kb = (e & 7) * 2;           // B: column j, rows k0+kb, +1
@@ -284,12 +340,13 @@ __device__ __forceinline__ void dm_load_panel(const GAS double *A, const GAS dou
     }
 }
 
-__device__ __forceinline__ void dm_put_panel(double *Am, double *Bm, int m, int k0, const dbl2 (&ra)[5],
-                                             const dbl2 (&rb)[5])
+__device__ __forceinline__ void dm_put_panel(double *Am, double *Bm, int m, int k0, const dbl2 (&ra)[DM_Q],
+                                             const dbl2 (&rb)[DM_Q])
 {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const int e = threadIdx.x + q * NTHREADS;
+    for (int q = 0; q < DM_Q; ++q) {
+        const int e = (int)threadIdx.x + q * DM_TEAM;
+        if (e >= DM_PIECES) continue;
         const int kk = e / 80, i = (e - kk * 80) * 2;
         Am[kk * DM_AP + i] = (k0 + kk < m && i < m) ? ra[q].x : 0.0;
         Am[kk * DM_AP + i + 1] = (k0 + kk < m && i + 1 < m) ? ra[q].y : 0.0;
@@ -300,40 +357,43 @@ __device__ __forceinline__ void dm_put_panel(double *Am, double *Bm, int m, int 
 }
 
 __device__ __forceinline__ void dm_gemm(int m, int ld, double alpha, const double *gA, const double *gB,
-                                     bool add, double *gC, double *lds)
+                                        bool add, double *gC, double *lds)
 {
     const GAS double *A = gp(gA);
     const GAS double *B = gp(gB);
     GAS double *C = gp(gC);
     double *Am = lds, *Bm = lds + DM_KP * DM_AP;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
     const int r = lane & 15, kq = lane >> 4;
-    const int NT = (m + 15) >> 4, H = (NT + 1) >> 1;
-    const int ti0 = (w & 1) * H, tj0 = (w >> 1) * H;
-    const int TI = min(H, NT - ti0), TJ = min(H, NT - tj0);
-    dbl4 acc[5][5];
+    const int NT = (m + 15) >> 4;
+    const int rh = w & 1, cq = w >> 1;
+    const int ti0 = rh * NT / 2, TI = (rh + 1) * NT / 2 - ti0;      // <= 5
+    const int tj0 = cq * NT / 4, TJ = (cq + 1) * NT / 4 - tj0;      // <= 3
+    dbl4 acc[5][3];
 #pragma unroll
     for (int x = 0; x < 5; ++x)
 #pragma unroll
-        for (int y = 0; y < 5; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
-    dbl2 ra[5], rb[5];
+        for (int y = 0; y < 3; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+    dbl2 ra[DM_Q], rb[DM_Q];
     dm_load_panel(A, B, m, ld, 0, ra, rb);
     for (int k0 = 0; k0 < m; k0 += DM_KP) {
         __syncthreads();                                  // previous panel fully read
         dm_put_panel(Am, Bm, m, k0, ra, rb);
         if (k0 + DM_KP < m) dm_load_panel(A, B, m, ld, k0 + DM_KP, ra, rb);
         __syncthreads();
+        const int nkc = (min(m - k0, DM_KP) + 3) >> 2;
 #pragma unroll
         for (int kc = 0; kc < DM_KP / 4; ++kc) {
-            double a[5], b[5];
+            if (kc >= nkc) continue;
+            double a[5], b[3];
 #pragma unroll
             for (int x = 0; x < 5; ++x) a[x] = Am[(4 * kc + kq) * DM_AP + 16 * (ti0 + min(x, TI - 1)) + r];
 #pragma unroll
-            for (int y = 0; y < 5; ++y) b[y] = Bm[(16 * (tj0 + min(y, TJ - 1)) + r) * DM_BP + 4 * kc + kq];
+            for (int y = 0; y < 3; ++y) b[y] = Bm[(16 * (tj0 + min(y, TJ - 1)) + r) * DM_BP + 4 * kc + kq];
 #pragma unroll
             for (int x = 0; x < 5; ++x)
 #pragma unroll
-                for (int y = 0; y < 5; ++y)
+                for (int y = 0; y < 3; ++y)
                     if (x < TI && y < TJ)
                         acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
@@ -342,7 +402,7 @@ __device__ __forceinline__ void dm_gemm(int m, int ld, double alpha, const doubl
 #pragma unroll
     for (int x = 0; x < 5; ++x)
 #pragma unroll
-        for (int y = 0; y < 5; ++y) {
+        for (int y = 0; y < 3; ++y) {
             if (x >= TI || y >= TJ) continue;
             const int j = 16 * (tj0 + y) + d64_frag_col(lane);
             double o[4];
@@ -360,98 +420,79 @@ __device__ __forceinline__ void dm_gemm(int m, int ld, double alpha, const doubl
     __syncthreads();
 }
 
-// ---------------------------------------------------------------------------
-// In-place inverse for 64 < m <= 160 (same contract as d64_invert): lane l of
-// wave w keeps rows l, l + 64, l + 128 and columns 40w .. 40w + 39 in
-// registers (120 values).  Step c: the owner wave of column c picks the
-// pivot (wave vote against the first unused row, full search only when a
-// larger entry exists), publishes the column, p and 1/piv through LDS; after
-// one barrier every wave takes the pivot row's values for its own columns
-// from the lane that holds them (through a wave-private LDS row, no barrier)
-// and updates its columns.  Pivot rows keep a deferred scale.  The result is
-// written straight to global memory with the row and column permutations
-// undone.  LDS: 2 * 160 + 2 + 4 * 40 doubles and 2 + 2 * 160 ints.
-// ---------------------------------------------------------------------------
-constexpr int DMI_LDS_DOUBLES = 2 * 160 + 2 + 4 * 40 + 162;
+// In-place inverse for 64 < m <= 160 (same contract as d64_invert).  Lane l
+// of wave w keeps rows l + 64 g (g < RG, RG = 2 for m <= 128, else 3) and
+// columns 20w .. 20w + 19 in registers.  Step c: the owner wave of column c
+// picks the pivot row p (pivot_key maximum) and publishes the column with its entry
+// p set to zero, p, the pivot and its reciprocal through LDS; after one
+// barrier every wave takes row p's values of its own columns from the lane
+// that holds them (through wave-private LDS rows) and updates its columns
+// with multipliers column(r) / pivot (zero for row p itself, which keeps a
+// deferred scale).  The result is written straight to global memory with the
+// row and column permutations undone (one column per store instruction).
+constexpr int DMI_CW = 20;
+constexpr int DMI_LDS_DOUBLES = 2 * DM_AP + 2 + DM_AP + (DM_TEAM / 64) * 3 * DMI_CW + (2 + 2 * DM_AP) / 2;
 
-__device__ __forceinline__ double dm_pick3(const double (&v)[3], int g)
+// (x0, x1, x2)[g] for a uniform g, from scalars: arrays selected this way can
+// be turned into indexed (scratch) loads by the compiler
+template <typename T>
+__device__ __forceinline__ T dm_sel(int g, T x0, T x1, T x2)
 {
-    return g == 0 ? v[0] : (g == 1 ? v[1] : v[2]);
+    return g == 0 ? x0 : (g == 1 ? x1 : x2);
 }
 
-__device__ __forceinline__ int dm_invert(double *gptr, int m, int ld, double *lds)
+template <int RG>
+__device__ __forceinline__ int dm_invert_rg(double *gptr, int m, int ld, double *lds)
 {
-    GAS double *gm_ = gp(gptr);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double *colbuf = lds;                                   // [2][160]
-    double *pinvbuf = lds + 320;                            // [2]
-    double *rowbuf = lds + 322 + 40 * w;                    // [40] this wave's pivot-row values
-    int *pbuf = reinterpret_cast<int *>(lds + 322 + 160);   // [2]
-    int *step_of_row = pbuf + 2;                            // [160]
-    int *row_of_step = pbuf + 162;                          // [160]
-    double a[3][40];
+    GAS double *G = gp(gptr);
+    const int lane = threadIdx.x & 63, w = wave_id();
+    double *colbuf = lds;                                           // [2][160] pivot columns
+    double *pinvbuf = lds + 2 * DM_AP;                              // [2] 1 / pivot
+    double *pivval = lds + 2 * DM_AP + 2;                           // [160] pivot of step c
+    double *rowbuf = lds + 3 * DM_AP + 2 + 3 * DMI_CW * w;          // [RG][20] this wave's rows of lane pl
+    int *pbuf = reinterpret_cast<int *>(lds + 3 * DM_AP + 2 + (DM_TEAM / 64) * 3 * DMI_CW);   // [2]
+    int *step_of_row = pbuf + 2;                                    // [160]
+    int *row_of_step = pbuf + 2 + DM_AP;                            // [160]
+    double a[RG][DMI_CW];
 #pragma unroll
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < RG; ++g) {
         const int row = lane + 64 * g;
 #pragma unroll
-        for (int j = 0; j < 40; ++j) {
-            const int c = 40 * w + j;
-            a[g][j] = (row < m && c < m) ? gm_[(size_t)row * ld + c] : (row == c ? 1.0 : 0.0);
+        for (int j = 0; j < DMI_CW; ++j) {
+            const int c = DMI_CW * w + j;
+            a[g][j] = (row < m && c < m) ? G[(size_t)c * ld + row] : (row == c ? 1.0 : 0.0);
         }
     }
-    unsigned long long un[3];
-#pragma unroll
-    for (int g = 0; g < 3; ++g) {
+    // unused rows of the three row groups (groups >= RG stay empty)
+    auto group_mask = [m](int g) {
         const int lo = 64 * g;
-        un[g] = (m <= lo) ? 0ull : (m - lo >= 64 ? ~0ull : ((1ull << (m - lo)) - 1ull));
-    }
-    double myscale[3] = {1.0, 1.0, 1.0};
+        return (m <= lo) ? 0ull : (m - lo >= 64 ? ~0ull : ((1ull << (m - lo)) - 1ull));
+    };
+    unsigned long long un0 = group_mask(0), un1 = group_mask(1), un2 = (RG > 2) ? group_mask(2) : 0ull;
     int bad = 0;
-    for (int wc = 0; wc < 4; ++wc) {
-        if (40 * wc >= m) break;
+    for (int wc = 0; wc < DM_TEAM / 64; ++wc) {
+        if (DMI_CW * wc >= m) break;
 #pragma unroll
-        for (int cc = 0; cc < 40; ++cc) {
-            const int c = 40 * wc + cc;
-            if (c >= m) continue;
+        for (int cc = 0; cc < DMI_CW; ++cc) {
+            const int c = DMI_CW * wc + cc;
+            if (c >= m) continue;                     // uniform
             const int par = c & 1;
             if (w == wc) {
-                const double v[3] = {a[0][cc], a[1][cc], a[2][cc]};
-                bool mine[3];
-#pragma unroll
-                for (int g = 0; g < 3; ++g) mine[g] = (un[g] >> lane) & 1ull;
-                const int ng = un[0] ? 0 : (un[1] ? 1 : 2);
-                const int n = 64 * ng + __builtin_ctzll(un[ng]);
-                const double vn = d64_readlane(dm_pick3(v, ng), n & 63);
-                bool big = false, nonfin = false;
-#pragma unroll
-                for (int g = 0; g < 3; ++g) {
-                    big |= mine[g] && fabs(v[g]) > fabs(vn);
-                    nonfin |= mine[g] && !isfinite(v[g]);
-                }
-                const bool anybig = __any(big), anynf = __any(nonfin);
-                int p = n;
-                if (anybig) {
-                    double best = -1.0;
-                    int bi = 1 << 20;
-#pragma unroll
-                    for (int g = 0; g < 3; ++g)
-                        if (mine[g] && fabs(v[g]) > best) { best = fabs(v[g]); bi = lane + 64 * g; }
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) {
-                        const double ob = __shfl_xor(best, o);
-                        const int oi = __shfl_xor(bi, o);
-                        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                    }
-                    p = __builtin_amdgcn_readfirstlane(bi);
-                    if (p < 0 || p >= m || !((un[p >> 6] >> (p & 63)) & 1ull)) p = n;
-                }
-                const double piv = d64_readlane(dm_pick3(v, p >> 6), p & 63);
-#pragma unroll
-                for (int g = 0; g < 3; ++g)
-                    if (lane + 64 * g < 160) colbuf[par * 160 + lane + 64 * g] = v[g];
+                const double v0 = a[0][cc], v1 = a[1][cc], v2 = (RG > 2) ? a[RG - 1][cc] : 0.0;
+                const bool m0 = (un0 >> lane) & 1ull, m1 = (un1 >> lane) & 1ull, m2 = (un2 >> lane) & 1ull;
+                const int k0 = pivot_key(v0, m0), k1 = pivot_key(v1, m1), k2 = pivot_key(v2, m2);
+                const int K = wave_max_i32(max(k0, max(k1, k2)));
+                const bool anynf = __any((m0 && !isfinite(v0)) || (m1 && !isfinite(v1)) || (m2 && !isfinite(v2)));
+                const unsigned long long b0 = __ballot(k0 == K), b1 = __ballot(k1 == K), b2 = __ballot(k2 == K);
+                const int p = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : 128 + __builtin_ctzll(b2));
+                const double piv = d64_readlane(dm_sel(p >> 6, v0, v1, v2), p & 63);
+                colbuf[par * DM_AP + lane] = (lane == p) ? 0.0 : v0;
+                colbuf[par * DM_AP + lane + 64] = (lane + 64 == p) ? 0.0 : v1;
+                if (RG > 2 && lane + 128 < DM_AP) colbuf[par * DM_AP + lane + 128] = (lane + 128 == p) ? 0.0 : v2;
                 if (lane == 0) {
-                    pbuf[par] = p | ((anynf || !(fabs(piv) > 0.0) || !isfinite(piv)) ? 0x1000 : 0);
+                    pbuf[par] = p | ((anynf || K <= 0 || !isfinite(piv)) ? 0x1000 : 0);
                     pinvbuf[par] = 1.0 / piv;
+                    pivval[c] = piv;
                 }
             }
             __syncthreads();
@@ -460,55 +501,66 @@ __device__ __forceinline__ int dm_invert(double *gptr, int m, int ld, double *ld
             if (pw & 0x1000) bad = 1;
             const double pinv = pinvbuf[par];
             const int pg = p >> 6, pl = p & 63;
-            // the pivot row's values of this wave's columns, from lane pl
+            // the pivot row's values of this wave's columns: lane pl copies
+            // all its rows, every lane reads those of group pg
             if (lane == pl) {
 #pragma unroll
-                for (int j = 0; j < 40; ++j) rowbuf[j] = pg == 0 ? a[0][j] : (pg == 1 ? a[1][j] : a[2][j]);
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int j = 0; j < DMI_CW / 2; ++j)
+                        reinterpret_cast<dbl2 *>(rowbuf + DMI_CW * g)[j] = dbl2{a[g][2 * j], a[g][2 * j + 1]};
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            double gmul[3];
+            double gmul[RG];
 #pragma unroll
-            for (int g = 0; g < 3; ++g) {
+            for (int g = 0; g < RG; ++g) {
                 const int row = lane + 64 * g;
-                const double f = (row < 160) ? colbuf[par * 160 + row] : 0.0;
-                const bool isp = (row == p);
-                gmul[g] = isp ? 0.0 : f * pinv;
-                if (isp) myscale[g] = f;
+                gmul[g] = (row < DM_AP) ? colbuf[par * DM_AP + row] * pinv : 0.0;
             }
+            const dbl2 *rb = reinterpret_cast<const dbl2 *>(rowbuf + DMI_CW * pg);
 #pragma unroll
-            for (int j = 0; j < 40; ++j) {
-                const double pr = rowbuf[j];
+            for (int j = 0; j < DMI_CW / 2; ++j) {
+                const dbl2 pr = rb[j];
 #pragma unroll
-                for (int g = 0; g < 3; ++g) a[g][j] = fma(-gmul[g], pr, a[g][j]);
+                for (int g = 0; g < RG; ++g) {
+                    a[g][2 * j] = fma(-gmul[g], pr.x, a[g][2 * j]);
+                    a[g][2 * j + 1] = fma(-gmul[g], pr.y, a[g][2 * j + 1]);
+                }
             }
             if (w == wc) {
 #pragma unroll
-                for (int g = 0; g < 3; ++g) a[g][cc] = (lane + 64 * g == p) ? 1.0 : -gmul[g];
+                for (int g = 0; g < RG; ++g) a[g][cc] = (lane + 64 * g == p) ? 1.0 : -gmul[g];
             }
-            un[pg] &= ~(1ull << pl);
+            if (pg == 0) un0 &= ~(1ull << pl);
+            else if (pg == 1) un1 &= ~(1ull << pl);
+            else un2 &= ~(1ull << pl);
             if (threadIdx.x == 0) { step_of_row[p] = c; row_of_step[c] = p; }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();   // rowbuf is rewritten next step
         }
     }
     __syncthreads();
-    // element (r, c) of the result is Q^{-1}(step(r), row(c)) times the scale of row r
+    // the value kept for (row r, column c) is P^{-1}(step(r), row(c)) times
+    // the pivot of row r
 #pragma unroll
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < RG; ++g) {
         const int row = lane + 64 * g;
         if (row >= m) continue;
         const int st = step_of_row[row];
-        const double sc = 1.0 / myscale[g];
+        const double sc = 1.0 / pivval[st];
 #pragma unroll
-        for (int j = 0; j < 40; ++j) {
-            const int c = 40 * w + j;
-            if (c < m) gm_[(size_t)st * ld + row_of_step[c]] = a[g][j] * sc;
+        for (int j = 0; j < DMI_CW; ++j) {
+            const int c = DMI_CW * w + j;
+            if (c < m) G[(size_t)row_of_step[c] * ld + st] = a[g][j] * sc;
         }
     }
     __syncthreads();
     return bad;
+}
+
+__device__ __forceinline__ int dm_invert(double *gptr, int m, int ld, double *lds)
+{
+    return (m <= 128) ? dm_invert_rg<2>(gptr, m, ld, lds) : dm_invert_rg<3>(gptr, m, ld, lds);
 }
 
 }  // namespace irk

@@ -974,14 +974,9 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         W.shm_sw32 = sizeof(float) * std::max(h->sw32.tps_pf * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_pf),
                                               h->sw32.tps_st * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_st));
     }
-    {
-        const size_t gj = sizeof(double) * (size_t)m * (m + 1) + sizeof(double) * m + sizeof(int) * (m + 4);
-        // m <= 64: matrix-core products and register Gauss-Jordan (dense64.h);
-        // larger blocks: LDS-tiled products and LDS Gauss-Jordan
-        const size_t gm = (m <= 64) ? sizeof(double) * (size_t)D64_LDS_DOUBLES
-                                    : sizeof(double) * 2 * 64 * 64;
-        h->shm_fac = (m <= 64) ? gm : std::max(gj, gm);
-    }
+    // factorization: matrix-core products and register Gauss-Jordan, four
+    // waves for m <= 64, eight above
+    h->shm_fac = sizeof(double) * (size_t)((m <= 64) ? D64_LDS_DOUBLES : std::max(DM_LDS_DOUBLES, DMI_LDS_DOUBLES));
     const size_t lds_max = 160 * 1024;
     if (h->shm_fac > lds_max || W.shm_mv64 > lds_max || W.shm_sw64 > lds_max ||
         (h->mixed && (W.shm_sw32 > lds_max || W.shm_mv32 > lds_max))) {
@@ -1108,10 +1103,10 @@ irk_status irk_factor_ilu(irk_handle *h)
     for (size_t l = 0; l < h->fa.size(); ++l) {
         if (h->fa[l].n)
             launch_factor(0, h->dsys, h->ditems + h->fa[l].off, h->fa[l].n, h->coupled, h->sharedJ,
-                          h->m <= 64, h->shm_fac, h->stream);
+                          h->m, h->shm_fac, h->stream);
         if (h->coupled && h->fb[l].n)
             launch_factor(1, h->dsys, h->ditems + h->fb[l].off, h->fb[l].n, true, h->sharedJ,
-                          h->m <= 64, h->shm_fac, h->stream);
+                          h->m, h->shm_fac, h->stream);
     }
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
     prof_end(h, pf, PK_FACTOR);

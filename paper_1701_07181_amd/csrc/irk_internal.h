@@ -156,9 +156,10 @@ void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nre
 // Factorization of one level.  phase 0: tasks (stage k = aux, element) build
 // P_{k,i} (and invert it when !coupled; set up cross blocks of column k when
 // coupled).  phase 1 (coupled): tasks = elements, sequential stage rounds.
-//   small: m <= 64 (matrix-core products, register Gauss-Jordan).
+// The kernels are chosen by the block order m (all systems of one launch
+// share it): four-wave workgroups for m <= 64, eight-wave ones above.
 void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems,
-                   bool coupled, bool sharedJ, bool small, size_t shmem, hipStream_t st);
+                   bool coupled, bool sharedJ, int m, size_t shmem, hipStream_t st);
 
 // Quantize nblk column-major blocks (leading dimensions ld in, ldq out).
 void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int m, int ld,

@@ -27,243 +27,38 @@
 
 namespace irk {
 
-// ---------------------------------------------------------------------------
-// C = (acc ? C : 0) + alpha * A * B for m x m column-major blocks (leading
-// dimension ld), computed by the whole workgroup with a 4 x 4 register tile
-// per thread (16 x 16 threads cover a 64 x 64 output tile).
-//   m <= 64: both operands are staged in LDS at once (one round of loads in
-//            flight, no panel barriers);
-//   m >  64: 64 x 64 output tiles, K panels of 16, the next panel prefetched
-//            into registers while the current one is multiplied.
-// LDS: 2 * 64 * 64 doubles.
-// ---------------------------------------------------------------------------
-constexpr int GT = 64, GK = 16;
-
-__device__ __forceinline__ void tile_fma(const double *As, const double *Bs, int kn, int tx, int ty,
-                                         double (&c)[4][4])
-{
-#pragma unroll 4
-    for (int kk = 0; kk < kn; ++kk) {
-        const double2 a01 = *reinterpret_cast<const double2 *>(&As[kk * GT + tx * 4]);
-        const double2 a23 = *reinterpret_cast<const double2 *>(&As[kk * GT + tx * 4 + 2]);
-        const double2 b01 = *reinterpret_cast<const double2 *>(&Bs[kk * GT + ty * 4]);
-        const double2 b23 = *reinterpret_cast<const double2 *>(&Bs[kk * GT + ty * 4 + 2]);
-        const double av[4] = {a01.x, a01.y, a23.x, a23.y};
-        const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) c[a][b] += av[a] * bv[b];
-    }
-}
-
-__device__ __forceinline__ void tile_store(int m, int ld, double alpha, bool acc, GAS double *C, int i0,
-                                           int j0, int tx, int ty, const double (&c)[4][4])
-{
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int gj = j0 + ty * 4 + b;
-        if (gj >= m) continue;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int gi = i0 + tx * 4 + a;
-            if (gi >= m) continue;
-            GAS double *cp = C + (size_t)gj * ld + gi;
-            *cp = (acc ? *cp : 0.0) + alpha * c[a][b];
-        }
-    }
-}
-
-__device__ __forceinline__ void wg_gemm(int m, int ld, double alpha, const double *__restrict__ Ap,
-                        const double *__restrict__ Bp, bool acc, double *Cp, double *lds)
-{
-    const GAS double *A = gp(Ap);
-    const GAS double *B = gp(Bp);
-    GAS double *C = gp(Cp);
-    double *As = lds;               // [k][64]
-    double *Bs = lds + GT * GT;     // [k][64]
-    const int t = threadIdx.x;
-    const int tx = t & 15, ty = t >> 4;
-    if (m <= GT) {
-        // whole operands: As[k][i] = A(i,k), Bs[k][j] = B(k,j)
-        for (int e = t; e < GT * GT; e += NTHREADS) {
-            const int i = e & 63, k = e >> 6;
-            As[k * GT + i] = (i < m && k < m) ? A[(size_t)k * ld + i] : 0.0;
-            const int kb = e & 63, j = e >> 6;
-            Bs[kb * GT + j] = (kb < m && j < m) ? B[(size_t)j * ld + kb] : 0.0;
-        }
-        __syncthreads();
-        double c[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
-        tile_fma(As, Bs, m, tx, ty, c);
-        tile_store(m, ld, alpha, acc, C, 0, 0, tx, ty, c);
-        __syncthreads();
-        return;
-    }
-    for (int i0 = 0; i0 < m; i0 += GT) {
-        for (int j0 = 0; j0 < m; j0 += GT) {
-            double c[4][4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
-            double ra[4], rb[4];
-            auto load_panel = [&](int k0) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int e = t + q * NTHREADS;         // 0..1023
-                    const int ii = e & 63, kk = e >> 6;
-                    const int gi = i0 + ii, gk = k0 + kk;
-                    ra[q] = (gi < m && gk < m) ? A[(size_t)gk * ld + gi] : 0.0;
-                    const int kb = e & 15, jj = e >> 4;
-                    const int gkb = k0 + kb, gj = j0 + jj;
-                    rb[q] = (gkb < m && gj < m) ? B[(size_t)gj * ld + gkb] : 0.0;
-                }
-            };
-            load_panel(0);
-            for (int k0 = 0; k0 < m; k0 += GK) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int e = t + q * NTHREADS;
-                    As[(e >> 6) * GT + (e & 63)] = ra[q];
-                    Bs[(e & 15) * GT + (e >> 4)] = rb[q];
-                }
-                __syncthreads();
-                if (k0 + GK < m) load_panel(k0 + GK);
-                tile_fma(As, Bs, GK, tx, ty, c);
-                __syncthreads();
-            }
-            tile_store(m, ld, alpha, acc, C, i0, j0, tx, ty, c);
-        }
-    }
-    __syncthreads();
-}
-
-// ---------------------------------------------------------------------------
-// In-place inverse of an m x m block by Gauss-Jordan elimination with
-// partial pivoting, in LDS.  The block's memory image is handled as the
-// row-major matrix Q = P^T (row stride ld); inverting Q and writing it back
-// the same way leaves P^{-1} in column-major order.  Returns nonzero (in
-// every thread) if a pivot column is zero or not finite.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int wg_invert(double *gptr, int m, int ld, double *lds)
-{
-    GAS double *g = gp(gptr);
-    const int lda = m + 1;
-    double *a = lds;                              // [m][lda]
-    double *colc = a + m * lda;                   // [m]
-    int *perm = reinterpret_cast<int *>(colc + m);   // [m]
-    int *sh = perm + m;                           // [2]: pivot row, bad flag
-    const int t = threadIdx.x;
-    // 2D mapping: thread owns column tc (+64, +128) and rows tr, tr+4, ...
-    const int tc = t & 63, tr = t >> 6;
-    for (int c0 = tc; c0 < m; c0 += 64)
-        for (int r = tr; r < m; r += NTHREADS / 64) a[r * lda + c0] = g[(size_t)r * ld + c0];
-    if (t == 0) sh[1] = 0;
-    __syncthreads();
-    for (int c = 0; c < m; ++c) {
-        if (t < 64) {
-            double best = -1.0;
-            int bi = c;
-            for (int r = c + t; r < m; r += 64) {
-                const double v = fabs(a[r * lda + c]);
-                if (v > best) { best = v; bi = r; }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ob = __shfl_xor(best, o, 64);
-                const int oi = __shfl_xor(bi, o, 64);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if (t == 0) {
-                sh[0] = bi;
-                perm[c] = bi;
-                if (!(best > 0.0) || !isfinite(best)) sh[1] = 1;
-            }
-        }
-        __syncthreads();
-        const int p = sh[0];
-        if (p != c) {
-            for (int j = t; j < m; j += NTHREADS) {
-                const double tmp = a[c * lda + j];
-                a[c * lda + j] = a[p * lda + j];
-                a[p * lda + j] = tmp;
-            }
-            __syncthreads();
-        }
-        const double pinv = 1.0 / a[c * lda + c];
-        // pivot row scaled; every thread keeps the entries of its columns
-        // (read before the barrier: row c is rewritten after it)
-        double prow[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int j = tc + 64 * q;
-            prow[q] = (j < m) ? ((j == c) ? pinv : a[c * lda + j] * pinv) : 0.0;
-        }
-        for (int r = t; r < m; r += NTHREADS) colc[r] = a[r * lda + c];
-        __syncthreads();
-        for (int r = tr; r < m; r += NTHREADS / 64) {
-            const double f = colc[r];
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int j = tc + 64 * q;
-                if (j >= m) continue;
-                double v;
-                if (r == c) v = prow[q];
-                else if (j == c) v = -f * pinv;
-                else v = a[r * lda + j] - f * prow[q];
-                a[r * lda + j] = v;
-            }
-        }
-        __syncthreads();
-    }
-    for (int c = m - 1; c >= 0; --c) {
-        const int p = perm[c];
-        if (p != c) {
-            for (int r = t; r < m; r += NTHREADS) {
-                const double tmp = a[r * lda + c];
-                a[r * lda + c] = a[r * lda + p];
-                a[r * lda + p] = tmp;
-            }
-            __syncthreads();
-        }
-    }
-    for (int c0 = tc; c0 < m; c0 += 64)
-        for (int r = tr; r < m; r += NTHREADS / 64) g[(size_t)r * ld + c0] = a[r * lda + c0];
-    const int bad = sh[1];
-    __syncthreads();
-    return bad;
-}
-
-// Block product and inverse: the matrix-core path and the register
-// Gauss-Jordan for m <= 64 (SMALL), the LDS-tiled ones above otherwise.  The
-// kernels are compiled separately for the two classes so that each carries
-// only its own register demand.
-template <bool SMALL>
+// Block-size classes: 0 -- m <= 64, four-wave routines (the bodies fit 128
+// VGPRs: four waves per SIMD);
+// 2 / 3 -- 64 < m <= 128 / 128 < m <= 160, eight-wave routines holding two /
+// three row groups per lane in the inverse.  Each body has one call site of
+// the product and one of the inverse, so each kernel carries one copy.  The
+// product accumulates (acc) only with alpha = 1 or -1.
+template <int CLS>
 __device__ __forceinline__ void blk_gemm(int m, int ld, double alpha, const double *A, const double *B,
                                          bool acc, double *C, double *lds)
 {
-    if (SMALL) d64_gemm(m, ld, alpha, A, B, acc, C, lds);
-    else wg_gemm(m, ld, alpha, A, B, acc, C, lds);
+    if (CLS == 0) d64_gemm(m, ld, alpha, A, B, acc, C);
+    else dm_gemm(m, ld, alpha, A, B, acc, C, lds);
 }
 
-template <bool SMALL>
-__device__ __forceinline__ int wg_inverse(double *g, int m, int ld, double *lds)
+template <int CLS>
+__device__ __forceinline__ int blk_inverse(double *g, int m, int ld, double *lds)
 {
-    return SMALL ? d64_invert(g, m, ld, lds) : wg_invert(g, m, ld, lds);
+    if (CLS == 0) return d64_invert(g, m, ld, lds);
+    return dm_invert_rg<(CLS == 0 ? 2 : CLS)>(g, m, ld, lds);
 }
+
+template <int CLS> constexpr int team_of() { return CLS == 0 ? NTHREADS : DM_TEAM; }
 
 __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
     if (threadIdx.x == 0) atomicCAS(&d.st->singular, 0, elem + 1);
 }
 
-template <bool COUPLED, bool SHJ, bool SMALL>
+template <bool COUPLED, bool SHJ, int CLS>
 __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
                                               const Item *__restrict__ items, double *lds)
 {
+    constexpr int TEAM = team_of<CLS>();
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, ld = d.ld;
@@ -276,7 +71,7 @@ __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
                   *tpos = gp(d.tpos);
     const double *Jd = Jk + (long long)diag_pos[i] * bs;
     const double dk = d.dcoef[k], dt = d.dt;
-    for (long long e = threadIdx.x; e < bs; e += NTHREADS) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
+    for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
     if (COUPLED) {
         // column k of the cross blocks: C_{lk,i} = A^{-1}_lk M_i (l != k)
         for (int l = 0; l < s; ++l) {
@@ -284,27 +79,31 @@ __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
             const int idx = l < k ? l : l - 1;
             double *Cl = d.C64 + (((long long)i * s + k) * (s - 1) + idx) * bs;
             const double al = d.Ainv[l * SMAX + k];
-            for (long long e = threadIdx.x; e < bs; e += NTHREADS) gp(Cl)[e] = al * gp(Mi)[e];
+            for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Cl)[e] = al * gp(Mi)[e];
         }
     }
     __syncthreads();
     double *X = d.Fscr + ((long long)i * s + k) * bs;
     const int p0 = row_ptr[i], pd = diag_pos[i];
-    for (int p = p0; p < pd; ++p) {
+    // per lower neighbour j: X = -dt^2 P_j^{-1} J_ji, then P_k += J_ij X
+    for (int t = 2 * p0; t < 2 * pd; ++t) {
+        const int p = t >> 1;
+        const bool second = t & 1;
         const long long j = col_idx[p];
-        const double *Pinv_j = d.P64 + (j * s + k) * bs;
-        blk_gemm<SMALL>(m, ld, 1.0, Pinv_j, Jk + (long long)tpos[p] * bs, false, X, lds);   // P_j^{-1} J_ji
-        blk_gemm<SMALL>(m, ld, -dt * dt, Jk + (long long)p * bs, X, true, Pk, lds);           // -= dt^2 J_ij X
+        const double *A = second ? Jk + (long long)p * bs : d.P64 + (j * s + k) * bs;
+        const double *B = second ? X : Jk + (long long)tpos[p] * bs;
+        blk_gemm<CLS>(m, ld, second ? 1.0 : -dt * dt, A, B, second, second ? Pk : X, lds);
     }
     if (!COUPLED) {
-        if (wg_inverse<SMALL>(Pk, m, ld, lds)) flag_singular(d, i);
+        if (blk_inverse<CLS>(Pk, m, ld, lds)) flag_singular(d, i);
     }
 }
 
-template <bool SHJ, bool SMALL>
+template <bool SHJ, int CLS>
 __device__ __forceinline__ void factor_b_body(const SysDesc *__restrict__ sysv,
                                               const Item *__restrict__ items, double *lds)
 {
+    constexpr int TEAM = team_of<CLS>();
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, ld = d.ld, sm1 = s - 1;
@@ -320,108 +119,105 @@ __device__ __forceinline__ void factor_b_body(const SysDesc *__restrict__ sysv,
     double *X = d.Fscr + ((long long)i * s + 1) * bs;
     const double *Mi = d.Mc + (long long)i * bs;
     for (int k = 0; k < s; ++k) {
-        if (wg_inverse<SMALL>(P(k), m, ld, lds)) flag_singular(d, i);
+        if (blk_inverse<CLS>(P(k), m, ld, lds)) flag_singular(d, i);
+        // k = 0: every cross block is still A^{-1}_kl M_i; with
+        //   L = M_i P_0^{-1},  X = L M_i:
+        //   P_l -= A^{-1}_l0 A^{-1}_0l X,   C_lq -= A^{-1}_l0 A^{-1}_0q X.
+        // k > 0, for every later stage l (q runs over k, k+1, .., s-1):
+        //   q = k:  L = C_lk P_k^{-1};  q = l:  P_l -= L C_kl;  else  C_lq -= L C_kq
+        const int w = s - k;
+        const int nops = (k == 0) ? 2 : (s - 1 - k) * w;
+        for (int t = 0; t < nops; ++t) {
+            const double *A, *B;
+            double *D;
+            double al;
+            bool add;
+            if (k == 0) {
+                A = t ? L : Mi;
+                B = t ? Mi : P(0);
+                D = t ? X : L;
+                al = 1.0;
+                add = false;
+            } else {
+                const int l = k + 1 + t / w, q = k + t % w;
+                if (q == k) { A = C(l, k); B = P(k); D = L; al = 1.0; add = false; }
+                else { A = L; B = C(k, q); D = (q == l) ? P(l) : C(l, q); al = -1.0; add = true; }
+            }
+            blk_gemm<CLS>(m, ld, al, A, B, add, D, lds);
+        }
         if (k == 0) {
-            // every cross block is still A^{-1}_kl M_i: with X = M_i P_0^{-1} M_i,
-            //   P_l  -= A^{-1}_l0 A^{-1}_0l X,   C_lq -= A^{-1}_l0 A^{-1}_0q X
-            blk_gemm<SMALL>(m, ld, 1.0, Mi, P(0), false, L, lds);
-            blk_gemm<SMALL>(m, ld, 1.0, L, Mi, false, X, lds);
             for (int l = 1; l < s; ++l)
                 for (int q = 1; q < s; ++q) {
                     double *D = (q == l) ? P(l) : C(l, q);
                     const double f = d.Ainv[l * SMAX + 0] * d.Ainv[0 * SMAX + q];
-                    for (long long e = threadIdx.x; e < bs; e += NTHREADS) gp(D)[e] -= f * gp(X)[e];
+                    for (long long e = threadIdx.x; e < bs; e += TEAM) gp(D)[e] -= f * gp(X)[e];
                 }
             __syncthreads();
-            continue;
-        }
-        for (int l = k + 1; l < s; ++l) {
-            blk_gemm<SMALL>(m, ld, 1.0, C(l, k), P(k), false, L, lds);          // L = C_lk P_k^{-1}
-            blk_gemm<SMALL>(m, ld, -1.0, L, C(k, l), true, P(l), lds);          // P_l -= L C_kl
-            for (int q = k + 1; q < s; ++q) {
-                if (q == l) continue;
-                blk_gemm<SMALL>(m, ld, -1.0, L, C(k, q), true, C(l, q), lds);   // C_lq -= L C_kq
-            }
         }
     }
 }
 
-// Kernels: blocks of order <= 64 ask for four waves per SIMD (the products
-// run out of line, so the bodies fit 128 VGPRs); larger blocks keep the
-// default budget of the LDS-tiled routines.
-template <bool COUPLED, bool SHJ>
-__global__ __launch_bounds__(NTHREADS, 4) void k_factor_a64(const SysDesc *__restrict__ sysv,
-                                                          const Item *__restrict__ items)
+template <bool COUPLED, bool SHJ, int CLS>
+__global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_a(const SysDesc *__restrict__ sysv,
+                                                                          const Item *__restrict__ items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_a_body<COUPLED, SHJ, true>(sysv, items, reinterpret_cast<double *>(smem_raw));
+    factor_a_body<COUPLED, SHJ, CLS>(sysv, items, reinterpret_cast<double *>(smem_raw));
 }
-template <bool COUPLED, bool SHJ>
-__global__ __launch_bounds__(NTHREADS) void k_factor_a(const SysDesc *__restrict__ sysv,
-                                                       const Item *__restrict__ items)
+template <bool SHJ, int CLS>
+__global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_b(const SysDesc *__restrict__ sysv,
+                                                                          const Item *__restrict__ items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_a_body<COUPLED, SHJ, false>(sysv, items, reinterpret_cast<double *>(smem_raw));
-}
-template <bool SHJ>
-__global__ __launch_bounds__(NTHREADS, 4) void k_factor_b64(const SysDesc *__restrict__ sysv,
-                                                          const Item *__restrict__ items)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_b_body<SHJ, true>(sysv, items, reinterpret_cast<double *>(smem_raw));
-}
-template <bool SHJ>
-__global__ __launch_bounds__(NTHREADS) void k_factor_b(const SysDesc *__restrict__ sysv,
-                                                       const Item *__restrict__ items)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_b_body<SHJ, false>(sysv, items, reinterpret_cast<double *>(smem_raw));
+    factor_b_body<SHJ, CLS>(sysv, items, reinterpret_cast<double *>(smem_raw));
 }
 
-template <bool SMALL>
+template <int CLS>
 static void launch_factor_t(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
                             bool sharedJ, size_t shmem, hipStream_t st)
 {
-    dim3 grid(nitems), block(NTHREADS);
-#define FA(C, SH)                                                                                 \
-    do {                                                                                          \
-        if (SMALL) hipLaunchKernelGGL((k_factor_a64<C, SH>), grid, block, shmem, st, dsys, items); \
-        else hipLaunchKernelGGL((k_factor_a<C, SH>), grid, block, shmem, st, dsys, items);        \
-    } while (0)
-#define FB(SH)                                                                                    \
-    do {                                                                                          \
-        if (SMALL) hipLaunchKernelGGL((k_factor_b64<SH>), grid, block, shmem, st, dsys, items);    \
-        else hipLaunchKernelGGL((k_factor_b<SH>), grid, block, shmem, st, dsys, items);           \
-    } while (0)
+    dim3 grid(nitems), block(team_of<CLS>());
     if (phase == 0) {
-        if (coupled) { if (sharedJ) FA(true, true); else FA(true, false); }
-        else { if (sharedJ) FA(false, true); else FA(false, false); }
+        if (coupled) {
+            if (sharedJ) hipLaunchKernelGGL((k_factor_a<true, true, CLS>), grid, block, shmem, st, dsys, items);
+            else hipLaunchKernelGGL((k_factor_a<true, false, CLS>), grid, block, shmem, st, dsys, items);
+        } else {
+            if (sharedJ) hipLaunchKernelGGL((k_factor_a<false, true, CLS>), grid, block, shmem, st, dsys, items);
+            else hipLaunchKernelGGL((k_factor_a<false, false, CLS>), grid, block, shmem, st, dsys, items);
+        }
     } else {
-        if (sharedJ) FB(true); else FB(false);
+        if (sharedJ) hipLaunchKernelGGL((k_factor_b<true, CLS>), grid, block, shmem, st, dsys, items);
+        else hipLaunchKernelGGL((k_factor_b<false, CLS>), grid, block, shmem, st, dsys, items);
     }
-#undef FA
-#undef FB
 }
 
+int factor_class(int m) { return m <= 64 ? 0 : (m <= 128 ? 2 : 3); }
+
 void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
-                   bool sharedJ, bool small, size_t shmem, hipStream_t st)
+                   bool sharedJ, int m, size_t shmem, hipStream_t st)
 {
-    if (small) launch_factor_t<true>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st);
-    else launch_factor_t<false>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st);
+    switch (factor_class(m)) {
+    case 0: launch_factor_t<0>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st); break;
+    case 2: launch_factor_t<2>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st); break;
+    default: launch_factor_t<3>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st); break;
+    }
+}
+
+template <int CLS>
+static void set_lds_limit_t(int b)
+{
+    const void *k[] = {(const void *)k_factor_a<true, true, CLS>, (const void *)k_factor_a<true, false, CLS>,
+                       (const void *)k_factor_a<false, true, CLS>, (const void *)k_factor_a<false, false, CLS>,
+                       (const void *)k_factor_b<true, CLS>, (const void *)k_factor_b<false, CLS>};
+    for (const void *f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
 }
 
 // Allow the factor kernels the LDS they need for m up to MMAX.
 void factor_set_lds_limit(size_t bytes)
 {
-    const int b = (int)bytes;
-    const void *k[] = {
-        (const void *)k_factor_a<true, true>, (const void *)k_factor_a<true, false>,
-        (const void *)k_factor_a<false, true>, (const void *)k_factor_a<false, false>,
-        (const void *)k_factor_a64<true, true>, (const void *)k_factor_a64<true, false>,
-        (const void *)k_factor_a64<false, true>, (const void *)k_factor_a64<false, false>,
-        (const void *)k_factor_b<true>, (const void *)k_factor_b<false>,
-        (const void *)k_factor_b64<true>, (const void *)k_factor_b64<false>};
-    for (const void *f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    set_lds_limit_t<0>((int)bytes);
+    set_lds_limit_t<2>((int)bytes);
+    set_lds_limit_t<3>((int)bytes);
 }
 
 // ---------------------------------------------------------------------------
