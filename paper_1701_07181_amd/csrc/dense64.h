@@ -422,16 +422,18 @@ __device__ __forceinline__ void dm_gemm(int m, int ld, double alpha, const doubl
 
 // In-place inverse for 64 < m <= 160 (same contract as d64_invert).  Lane l
 // of wave w keeps rows l + 64 g (g < RG, RG = 2 for m <= 128, else 3) and
-// columns 20w .. 20w + 19 in registers.  Step c: the owner wave of column c
-// picks the pivot row p (pivot_key maximum) and publishes the column with its entry
-// p set to zero, p, the pivot and its reciprocal through LDS; after one
-// barrier every wave takes row p's values of its own columns from the lane
-// that holds them (through wave-private LDS rows) and updates its columns
+// columns 20w .. 20w + 19 in registers.  The owner wave of column c picks
+// the pivot row p (pivot_key maximum) and publishes the column with its entry
+// p set to zero, p, the pivot and its reciprocal through LDS.  Step c, after
+// one barrier: every wave reads row p's values of its own columns from the
+// lane that holds them (v_readlane) and updates its columns
 // with multipliers column(r) / pivot (zero for row p itself, which keeps a
-// deferred scale).  The result is written straight to global memory with the
-// row and column permutations undone (one column per store instruction).
+// deferred scale); the owner of column c + 1 updates that column first and
+// publishes its pivot choice (look-ahead).  The result is written straight to
+// global memory with the row and column permutations undone (one column per
+// store instruction).
 constexpr int DMI_CW = 20;
-constexpr int DMI_LDS_DOUBLES = 2 * DM_AP + 2 + DM_AP + (DM_TEAM / 64) * 3 * DMI_CW + (2 + 2 * DM_AP) / 2;
+constexpr int DMI_LDS_DOUBLES = 2 * DM_AP + 2 + DM_AP + (2 + 2 * DM_AP) / 2;
 
 // (x0, x1, x2)[g] for a uniform g, from scalars: arrays selected this way can
 // be turned into indexed (scratch) loads by the compiler
@@ -441,16 +443,43 @@ __device__ __forceinline__ T dm_sel(int g, T x0, T x1, T x2)
     return g == 0 ? x0 : (g == 1 ? x1 : x2);
 }
 
+// Pivot choice for the column (v0, v1, v2) of row groups 0..2 among the rows
+// marked in un0..un2, by the owner wave (every lane active): publishes the
+// column with its pivot entry set to zero, the pivot row (0x1000 set when
+// the pivot is zero or the column holds a non-finite value), the pivot and
+// its reciprocal.
+template <int RG>
+__device__ __forceinline__ void dm_publish(double v0, double v1, double v2, unsigned long long un0,
+                                           unsigned long long un1, unsigned long long un2, int lane,
+                                           double *col, int *pw, double *pinv, double *pivc)
+{
+    const bool m0 = (un0 >> lane) & 1ull, m1 = (un1 >> lane) & 1ull, m2 = (un2 >> lane) & 1ull;
+    const int k0 = pivot_key(v0, m0), k1 = pivot_key(v1, m1), k2 = pivot_key(v2, m2);
+    const int K = wave_max_i32(max(k0, max(k1, k2)));
+    const bool anynf = __any((m0 && !isfinite(v0)) || (m1 && !isfinite(v1)) || (m2 && !isfinite(v2)));
+    const unsigned long long b0 = __ballot(k0 == K), b1 = __ballot(k1 == K), b2 = __ballot(k2 == K);
+    const int p = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : 128 + __builtin_ctzll(b2));
+    const double piv = d64_readlane(dm_sel(p >> 6, v0, v1, v2), p & 63);
+    col[lane] = (lane == p) ? 0.0 : v0;
+    col[lane + 64] = (lane + 64 == p) ? 0.0 : v1;
+    if (RG > 2 && lane + 128 < DM_AP) col[lane + 128] = (lane + 128 == p) ? 0.0 : v2;
+    if (lane == 0) {
+        *pw = p | ((anynf || K <= 0 || !isfinite(piv)) ? 0x1000 : 0);
+        *pinv = fast_recip(piv);
+        *pivc = piv;
+    }
+}
+
 template <int RG>
 __device__ __forceinline__ int dm_invert_rg(double *gptr, int m, int ld, double *lds)
 {
     GAS double *G = gp(gptr);
+    asm volatile("" : "+s"(m), "+s"(ld));      // nothing of a call hoisted into a caller's loop
     const int lane = threadIdx.x & 63, w = wave_id();
     double *colbuf = lds;                                           // [2][160] pivot columns
     double *pinvbuf = lds + 2 * DM_AP;                              // [2] 1 / pivot
     double *pivval = lds + 2 * DM_AP + 2;                           // [160] pivot of step c
-    double *rowbuf = lds + 3 * DM_AP + 2 + 3 * DMI_CW * w;          // [RG][20] this wave's rows of lane pl
-    int *pbuf = reinterpret_cast<int *>(lds + 3 * DM_AP + 2 + (DM_TEAM / 64) * 3 * DMI_CW);   // [2]
+    int *pbuf = reinterpret_cast<int *>(lds + 3 * DM_AP + 2);      // [2]
     int *step_of_row = pbuf + 2;                                    // [160]
     int *row_of_step = pbuf + 2 + DM_AP;                            // [160]
     double a[RG][DMI_CW];
@@ -470,6 +499,8 @@ __device__ __forceinline__ int dm_invert_rg(double *gptr, int m, int ld, double 
     };
     unsigned long long un0 = group_mask(0), un1 = group_mask(1), un2 = (RG > 2) ? group_mask(2) : 0ull;
     int bad = 0;
+    if (w == 0)
+        dm_publish<RG>(a[0][0], a[1][0], a[RG - 1][0], un0, un1, un2, lane, colbuf, pbuf, pinvbuf, pivval);
     for (int wc = 0; wc < DM_TEAM / 64; ++wc) {
         if (DMI_CW * wc >= m) break;
 #pragma unroll
@@ -477,65 +508,53 @@ __device__ __forceinline__ int dm_invert_rg(double *gptr, int m, int ld, double 
             const int c = DMI_CW * wc + cc;
             if (c >= m) continue;                     // uniform
             const int par = c & 1;
-            if (w == wc) {
-                const double v0 = a[0][cc], v1 = a[1][cc], v2 = (RG > 2) ? a[RG - 1][cc] : 0.0;
-                const bool m0 = (un0 >> lane) & 1ull, m1 = (un1 >> lane) & 1ull, m2 = (un2 >> lane) & 1ull;
-                const int k0 = pivot_key(v0, m0), k1 = pivot_key(v1, m1), k2 = pivot_key(v2, m2);
-                const int K = wave_max_i32(max(k0, max(k1, k2)));
-                const bool anynf = __any((m0 && !isfinite(v0)) || (m1 && !isfinite(v1)) || (m2 && !isfinite(v2)));
-                const unsigned long long b0 = __ballot(k0 == K), b1 = __ballot(k1 == K), b2 = __ballot(k2 == K);
-                const int p = b0 ? __builtin_ctzll(b0) : (b1 ? 64 + __builtin_ctzll(b1) : 128 + __builtin_ctzll(b2));
-                const double piv = d64_readlane(dm_sel(p >> 6, v0, v1, v2), p & 63);
-                colbuf[par * DM_AP + lane] = (lane == p) ? 0.0 : v0;
-                colbuf[par * DM_AP + lane + 64] = (lane + 64 == p) ? 0.0 : v1;
-                if (RG > 2 && lane + 128 < DM_AP) colbuf[par * DM_AP + lane + 128] = (lane + 128 == p) ? 0.0 : v2;
-                if (lane == 0) {
-                    pbuf[par] = p | ((anynf || K <= 0 || !isfinite(piv)) ? 0x1000 : 0);
-                    pinvbuf[par] = 1.0 / piv;
-                    pivval[c] = piv;
-                }
-            }
             __syncthreads();
             const int pw = __builtin_amdgcn_readfirstlane(pbuf[par]);
             const int p = pw & 0xfff;
             if (pw & 0x1000) bad = 1;
             const double pinv = pinvbuf[par];
             const int pg = p >> 6, pl = p & 63;
-            // the pivot row's values of this wave's columns: lane pl copies
-            // all its rows, every lane reads those of group pg
-            if (lane == pl) {
+            // the pivot row's values of this wave's columns, read from lane pl
+            double prow[DMI_CW];
+            if (pg == 0) {
 #pragma unroll
-                for (int g = 0; g < RG; ++g)
+                for (int j = 0; j < DMI_CW; ++j) prow[j] = d64_readlane(a[0][j], pl);
+            } else if (RG == 2 || pg == 1) {
 #pragma unroll
-                    for (int j = 0; j < DMI_CW / 2; ++j)
-                        reinterpret_cast<dbl2 *>(rowbuf + DMI_CW * g)[j] = dbl2{a[g][2 * j], a[g][2 * j + 1]};
+                for (int j = 0; j < DMI_CW; ++j) prow[j] = d64_readlane(a[1][j], pl);
+            } else {
+#pragma unroll
+                for (int j = 0; j < DMI_CW; ++j) prow[j] = d64_readlane(a[RG - 1][j], pl);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             double gmul[RG];
 #pragma unroll
             for (int g = 0; g < RG; ++g) {
                 const int row = lane + 64 * g;
                 gmul[g] = (row < DM_AP) ? colbuf[par * DM_AP + row] * pinv : 0.0;
             }
-            const dbl2 *rb = reinterpret_cast<const dbl2 *>(rowbuf + DMI_CW * pg);
+            if (pg == 0) un0 &= ~(1ull << pl);
+            else if (pg == 1) un1 &= ~(1ull << pl);
+            else un2 &= ~(1ull << pl);
+            // column c + 1 (index cn of wave wn): updated and published first
+            const int cn = (cc + 1) % DMI_CW;         // a constant once the loop is unrolled
+            const int wn = (cc == DMI_CW - 1) ? wc + 1 : wc;
+            const bool ahead = (c + 1 < m) && (w == wn);
+            if (ahead) {
 #pragma unroll
-            for (int j = 0; j < DMI_CW / 2; ++j) {
-                const dbl2 pr = rb[j];
+                for (int g = 0; g < RG; ++g) a[g][cn] = fma(-gmul[g], prow[cn], a[g][cn]);
+                dm_publish<RG>(a[0][cn], a[1][cn], a[RG - 1][cn], un0, un1, un2, lane, colbuf + (par ^ 1) * DM_AP,
+                               pbuf + (par ^ 1), pinvbuf + (par ^ 1), pivval + c + 1);
+            }
 #pragma unroll
-                for (int g = 0; g < RG; ++g) {
-                    a[g][2 * j] = fma(-gmul[g], pr.x, a[g][2 * j]);
-                    a[g][2 * j + 1] = fma(-gmul[g], pr.y, a[g][2 * j + 1]);
-                }
+            for (int j = 0; j < DMI_CW; ++j) {
+                if (j == cn && ahead) continue;
+#pragma unroll
+                for (int g = 0; g < RG; ++g) a[g][j] = fma(-gmul[g], prow[j], a[g][j]);
             }
             if (w == wc) {
 #pragma unroll
                 for (int g = 0; g < RG; ++g) a[g][cc] = (lane + 64 * g == p) ? 1.0 : -gmul[g];
             }
-            if (pg == 0) un0 &= ~(1ull << pl);
-            else if (pg == 1) un1 &= ~(1ull << pl);
-            else un2 &= ~(1ull << pl);
             if (threadIdx.x == 0) { step_of_row[p] = c; row_of_step[c] = p; }
         }
     }
