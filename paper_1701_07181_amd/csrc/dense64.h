@@ -52,9 +52,14 @@ struct D64Ops {
 };
 
 // Loads of block t; every address is clamped into the block, so the loads
-// are unconditional (K padding is zeroed when the values are used).
-__device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, const GAS double *B, int m, int ld,
-                                             int i0, int j0, int kq, int t)
+// are unconditional (K padding is zeroed when the values are used).  B comes
+// from global memory (leading dimension ld) or, with BLDS, from LDS
+// (leading dimension D64_LDX).
+constexpr int D64_LDX = 66;
+
+template <bool BLDS>
+__device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, const GAS double *B, const double *Bs,
+                                             int m, int ld, int i0, int j0, int kq, int t)
 {
     const int kb = 8 * t + 2 * kq;
 #pragma unroll
@@ -63,8 +68,10 @@ __device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, con
         for (int u = 0; u < 2; ++u)
             o.a[x][u] = A[(size_t)min(kb + u, m - 1) * ld + min(i0 + 16 * x, ld - 1)];
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-        o.b[y] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j0 + 16 * y, m - 1) * ld + min(kb, ld - 2));
+    for (int y = 0; y < 2; ++y) {
+        if (BLDS) o.b[y] = *reinterpret_cast<const dbl2 *>(Bs + (j0 + 16 * y) * D64_LDX + min(kb, 62));
+        else o.b[y] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j0 + 16 * y, m - 1) * ld + min(kb, ld - 2));
+    }
 }
 
 template <bool FULL>
@@ -90,14 +97,41 @@ __device__ __forceinline__ void d64_mma_ops(const D64Ops &o, int m, int kq, int 
     }
 }
 
+// acc += A B over K = m for this wave's tiles (quadrant (w & 1, w >> 1)).
+// FULL (m > 56: all 2 x 2 tiles, eight K blocks): straight-line code, so the
+// waits before each block's products leave the two later blocks' loads in
+// flight; otherwise blocks past the last one are skipped.
+// DEPTH operand buffers: DEPTH - 1 blocks in flight while one is multiplied.
+template <bool FULL, bool BLDS, int DEPTH = 3>
+__device__ __forceinline__ void d64_accum(dbl4 (&acc)[2][2], int m, int ld, const GAS double *A,
+                                          const GAS double *B, const double *Bs, int nx, int ny)
+{
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int r = lane & 15, kq = lane >> 4;
+    const int i0 = 32 * (w & 1) + r, j0 = 32 * (w >> 1) + r;
+    const int nb = FULL ? 8 : (m + 7) >> 3;
+    D64Ops o[DEPTH];
+#pragma unroll
+    for (int t = 0; t < DEPTH - 1; ++t)
+        if (FULL || t < nb) d64_load_ops<BLDS>(o[t], A, B, Bs, m, ld, i0, j0, kq, t);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        if (!FULL && t >= nb) continue;
+        const int tn = t + DEPTH - 1;
+        if (FULL ? (tn < 8) : (tn < nb)) d64_load_ops<BLDS>(o[tn % DEPTH], A, B, Bs, m, ld, i0, j0, kq, tn);
+        d64_mma_ops<FULL>(o[t % DEPTH], m, kq, t, nx, ny, acc);
+    }
+}
+
+// Row and column of element q of tile (x, y) of this wave's quadrant.
+__device__ __forceinline__ int d64_tile_row(int lane, int w, int x, int q) { return 32 * (w & 1) + 16 * x + d64_frag_row(lane, q); }
+__device__ __forceinline__ int d64_tile_col(int lane, int w, int y) { return 32 * (w >> 1) + 16 * y + d64_frag_col(lane); }
+
 template <bool FULL>
 __device__ __forceinline__ void d64_gemm_tiles(int m, int ld, double alpha, const GAS double *A,
                                                const GAS double *B, bool add, GAS double *C, int nx, int ny)
 {
     const int lane = threadIdx.x & 63, w = wave_id();
-    const int qi = w & 1, qj = w >> 1;
-    const int r = lane & 15, kq = lane >> 4;
-    const int i0 = 32 * qi + r, j0 = 32 * qj + r;
     dbl4 acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -105,24 +139,11 @@ __device__ __forceinline__ void d64_gemm_tiles(int m, int ld, double alpha, cons
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = 32 * qi + 16 * x + d64_frag_row(lane, q);
-                const int j = 32 * qj + 16 * y + d64_frag_col(lane);
+                const int i = d64_tile_row(lane, w, x, q), j = d64_tile_col(lane, w, y);
                 const double old = C[(size_t)min(j, m - 1) * ld + min(i, m - 1)];
                 acc[x][y][q] = (add && i < m && j < m) ? alpha * old : 0.0;
             }
-    // FULL (all 2 x 2 tiles, eight K blocks): straight-line code, so the
-    // waits before each block's products leave the two later blocks' loads
-    // in flight; otherwise blocks past the last one are skipped
-    const int nb = FULL ? 8 : (m + 7) >> 3;
-    D64Ops o[3];
-    d64_load_ops(o[0], A, B, m, ld, i0, j0, kq, 0);
-    if (FULL || nb > 1) d64_load_ops(o[1], A, B, m, ld, i0, j0, kq, 1);
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        if (!FULL && t >= nb) continue;
-        if (FULL ? (t + 2 < 8) : (t + 2 < nb)) d64_load_ops(o[(t + 2) % 3], A, B, m, ld, i0, j0, kq, t + 2);
-        d64_mma_ops<FULL>(o[t % 3], m, kq, t, nx, ny, acc);
-    }
+    d64_accum<FULL, false>(acc, m, ld, A, B, nullptr, nx, ny);
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -130,12 +151,14 @@ __device__ __forceinline__ void d64_gemm_tiles(int m, int ld, double alpha, cons
             if (!FULL && (x >= nx || y >= ny)) continue;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = 32 * qi + 16 * x + d64_frag_row(lane, q);
-                const int j = 32 * qj + 16 * y + d64_frag_col(lane);
+                const int i = d64_tile_row(lane, w, x, q), j = d64_tile_col(lane, w, y);
                 if (i < m && j < m) C[(size_t)j * ld + i] = alpha * acc[x][y][q];
             }
         }
 }
+
+// Tiles (of 16 x 16) of wave w's quadrant that hold rows / columns below m.
+__device__ __forceinline__ int d64_ntiles(int m, int q) { return min(2, max(0, (m - 32 * q + 15) >> 4)); }
 
 __device__ __forceinline__ void d64_gemm(int m, int ld, double alpha, const double *gA, const double *gB,
                                          bool add, double *gC)
@@ -145,8 +168,7 @@ __device__ __forceinline__ void d64_gemm(int m, int ld, double alpha, const doub
     // across a caller's loop of products
     asm volatile("" : "+s"(m), "+s"(ld));
     const int w = wave_id();
-    const int nx = min(2, max(0, (m - 32 * (w & 1) + 15) >> 4));      // tiles holding rows below m
-    const int ny = min(2, max(0, (m - 32 * (w >> 1) + 15) >> 4));
+    const int nx = d64_ntiles(m, w & 1), ny = d64_ntiles(m, w >> 1);
     if (m > 56) d64_gemm_tiles<true>(m, ld, alpha, gp(gA), gp(gB), add, gp(gC), 2, 2);
     else if (nx > 0 && ny > 0) d64_gemm_tiles<false>(m, ld, alpha, gp(gA), gp(gB), add, gp(gC), nx, ny);
     __syncthreads();

@@ -54,6 +54,78 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
     if (threadIdx.x == 0) atomicCAS(&d.st->singular, 0, elem + 1);
 }
 
+// Phase 0 for m <= 64 with the products fused: the accumulators of P_{k,i}
+// stay in registers from d_k M_i - dt J_ii through every lower neighbour j,
+// and X = -dt^2 P_j^{-1} J_ji passes through LDS (64 x 66 doubles) into
+// P_{k,i} += J_ij X; P_{k,i} is written once.
+template <bool FULL>
+__device__ __forceinline__ void factor_a_small_products(const SysDesc &d, int i, int k, const double *Jk,
+                                                        double *Pk, double *Xs)
+{
+    const int s = d.s, lane = threadIdx.x & 63, w = wave_id();
+    int m = d.m, ld = d.ld;
+    const long long bs = (long long)m * ld;
+    const GAS int *diag_pos = gp(d.diag_pos), *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx),
+                  *tpos = gp(d.tpos);
+    const double dk = d.dcoef[k], dt = d.dt;
+    const int nx = FULL ? 2 : d64_ntiles(m, w & 1), ny = FULL ? 2 : d64_ntiles(m, w >> 1);
+    const bool act = nx > 0 && ny > 0;
+    const GAS double *Mi = gp(d.Mc + (long long)i * bs);
+    const GAS double *Jd = gp(Jk + (long long)diag_pos[i] * bs);
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
+                const size_t e = (size_t)min(c, m - 1) * ld + min(r, m - 1);
+                acc[x][y][q] = dk * Mi[e] - dt * Jd[e];
+            }
+    const int p0 = row_ptr[i], pd = diag_pos[i];
+    for (int p = p0; p < pd; ++p) {
+        asm volatile("" : "+s"(m), "+s"(ld));   // per-lane offsets recomputed inside the loop
+        const long long j = col_idx[p];
+        dbl4 ax[2][2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) ax[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+        if (act)
+            d64_accum<FULL, false, 2>(ax, m, ld, gp(d.P64 + (j * s + k) * bs), gp(Jk + (long long)tpos[p] * bs),
+                                      nullptr, nx, ny);
+        __syncthreads();                          // the previous neighbour's X is consumed
+        if (act) {
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    if (!FULL && (x >= nx || y >= ny)) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        Xs[d64_tile_col(lane, w, y) * D64_LDX + d64_tile_row(lane, w, x, q)] = -dt * dt * ax[x][y][q];
+                }
+        }
+        __syncthreads();
+        if (act) d64_accum<FULL, true, 2>(acc, m, ld, gp(Jk + (long long)p * bs), nullptr, Xs, nx, ny);
+    }
+    if (act) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                if (!FULL && (x >= nx || y >= ny)) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
+                    if (r < m && c < m) gp(Pk)[(size_t)c * ld + r] = acc[x][y][q];
+                }
+            }
+    }
+    __syncthreads();
+}
+
 template <bool COUPLED, bool SHJ, int CLS>
 __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
                                               const Item *__restrict__ items, double *lds)
@@ -71,7 +143,8 @@ __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
                   *tpos = gp(d.tpos);
     const double *Jd = Jk + (long long)diag_pos[i] * bs;
     const double dk = d.dcoef[k], dt = d.dt;
-    for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
+    if (CLS != 0)
+        for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
     if (COUPLED) {
         // column k of the cross blocks: C_{lk,i} = A^{-1}_lk M_i (l != k)
         for (int l = 0; l < s; ++l) {
@@ -81,6 +154,14 @@ __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
             const double al = d.Ainv[l * SMAX + k];
             for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Cl)[e] = al * gp(Mi)[e];
         }
+    }
+    if (CLS == 0) {
+        if (m > 56) factor_a_small_products<true>(d, i, k, Jk, Pk, lds);
+        else factor_a_small_products<false>(d, i, k, Jk, Pk, lds);
+        if (!COUPLED) {
+            if (blk_inverse<CLS>(Pk, m, ld, lds)) flag_singular(d, i);
+        }
+        return;
     }
     __syncthreads();
     double *X = d.Fscr + ((long long)i * s + k) * bs;
