@@ -82,13 +82,22 @@ __device__ __forceinline__ void col_product(const GAS typename Vec16<TF>::st *bl
         }
         c0 = g + G * NQ;
     }
-#pragma unroll 4
-    for (int c = c0; c < m; c += G) {
-        TC a[V];
-        Vec16<TF>::load(blk + (size_t)c * ld, a);
-        const TC xv = x[c];
+    // chunks of U columns: the loads of a chunk are unconditional (clamped
+    // addresses), so they are all in flight before the first product
+    constexpr int U = (V <= 4) ? 8 : 4;
+    for (int cb = c0; cb < m; cb += U * G) {
+        TC a[U][V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] += a[v] * xv;
+        for (int u = 0; u < U; ++u) Vec16<TF>::load(blk + (size_t)min(cb + u * G, m - 1) * ld, a[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = cb + u * G;
+            if (c < m) {
+                const TC xv = x[c];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] += a[u][v] * xv;
+            }
+        }
     }
 }
 
@@ -172,24 +181,31 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     }
 
     // ---- gather the neighbours' vectors and this element's input ----
+    // (every load of a pass is unconditional, with clamped indices, so a
+    // pass costs one memory latency)
     if (has) {
-        for (int q = tid; q < ncol; q += team) {
-            const int b = q / m, c = q - b * m;
-            const long long j = (b < SW_NB) ? rec.col[b] : gp(d.col_idx)[pa + b];
+        const int nown = s * m;
+        const GAS double *vin = gp(reinterpret_cast<const double *>(d.vec[v_slot])) + (long long)v_index * d.N;
+        for (int q = tid; q < max(ncol, nown); q += team) {
+            // this element's input, stage k, row r
+            const int qo = min(q, nown - 1), ko = qo / m, ro = qo - ko * m;
+            const long long go = ko * n + (long long)i * m + ro;
+            const TC own = FWD ? (TC)vin[go] : yh[go];
+            // the neighbours' vectors: block b, row c, every stage
+            const int qn = min(q, max(ncol - 1, 0)), b = qn / m, c = qn - b * m;
+            int jb = rec.col[0];
 #pragma unroll
-            for (int k = 0; k < S; ++k)
-                if (k < s) xg[k * maxg + q] = yh[k * n + j * m + c];
-        }
-        if (FWD) {
-            const GAS double *v = gp(reinterpret_cast<const double *>(d.vec[v_slot])) + (long long)v_index * d.N;
-            for (int q = tid; q < s * m; q += team) {
-                const int k = q / m, r = q - k * m;
-                yv[k * ldv + r] = (TC)v[k * n + (long long)i * m + r];
-            }
-        } else {
-            for (int q = tid; q < s * m; q += team) {
-                const int k = q / m, r = q - k * m;
-                yv[k * ldv + r] = yh[k * n + (long long)i * m + r];
+            for (int t = 1; t < SW_NB; ++t) jb = (b == t) ? rec.col[t] : jb;
+            long long j = (ncol == 0) ? i : jb;
+            if (b >= SW_NB) j = gp(d.col_idx)[pa + b];     // rows of more than SW_NB blocks only
+            TC nv[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) nv[k] = yh[min(k, s - 1) * n + j * m + c];
+            if (q < nown) yv[ko * ldv + ro] = own;
+            if (q < ncol) {
+#pragma unroll
+                for (int k = 0; k < S; ++k)
+                    if (k < s) xg[k * maxg + q] = nv[k];
             }
         }
     }
@@ -221,16 +237,22 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
                     }
                     c0 = gJ + GJ * QJ;
                 }
-#pragma unroll 4
-                for (int cg = c0; cg < ncol; cg += GJ) {
-                    TC a[VJ];
-                    Vec16<TJ>::load(jrow + (size_t)cg * ldJ, a);
+                constexpr int UJ = (VJ <= 4) ? 8 : 4;   // columns per chunk, loads all in flight
+                for (int cb = c0; cb < ncol; cb += UJ * GJ) {
+                    TC a[UJ][VJ];
 #pragma unroll
-                    for (int k = 0; k < S; ++k) {
-                        if (k >= s) continue;
-                        const TC xv = xg[k * maxg + cg];
+                    for (int u = 0; u < UJ; ++u) Vec16<TJ>::load(jrow + (size_t)min(cb + u * GJ, ncol - 1) * ldJ, a[u]);
 #pragma unroll
-                        for (int v = 0; v < VJ; ++v) aj[k][v] += a[v] * xv;
+                    for (int u = 0; u < UJ; ++u) {
+                        const int cg = cb + u * GJ;
+                        if (cg >= ncol) continue;
+#pragma unroll
+                        for (int k = 0; k < S; ++k) {
+                            if (k >= s) continue;
+                            const TC xv = xg[k * maxg + cg];
+#pragma unroll
+                            for (int v = 0; v < VJ; ++v) aj[k][v] += a[u][v] * xv;
+                        }
                     }
                 }
             } else {
@@ -238,13 +260,19 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
                 for (int k = 0; k < S; ++k) {
                     if (k >= s) continue;
                     const auto base = Jb + ((size_t)k * d.nnzb + pa) * m * ldJ + sJ * VJ;
-#pragma unroll 4
-                    for (int cg = gJ; cg < ncol; cg += GJ) {
-                        TC a[VJ];
-                        Vec16<TJ>::load(base + (size_t)cg * ldJ, a);
-                        const TC xv = xg[k * maxg + cg];
+                    constexpr int UJ = (VJ <= 4) ? 8 : 4;
+                    for (int cb = gJ; cb < ncol; cb += UJ * GJ) {
+                        TC a[UJ][VJ];
 #pragma unroll
-                        for (int v = 0; v < VJ; ++v) aj[k][v] += a[v] * xv;
+                        for (int u = 0; u < UJ; ++u) Vec16<TJ>::load(base + (size_t)min(cb + u * GJ, ncol - 1) * ldJ, a[u]);
+#pragma unroll
+                        for (int u = 0; u < UJ; ++u) {
+                            const int cg = cb + u * GJ;
+                            if (cg >= ncol) continue;
+                            const TC xv = xg[k * maxg + cg];
+#pragma unroll
+                            for (int v = 0; v < VJ; ++v) aj[k][v] += a[u][v] * xv;
+                        }
                     }
                 }
             }
