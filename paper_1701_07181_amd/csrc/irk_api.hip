@@ -247,7 +247,7 @@ SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupl
     sh.pf = sh.tps_pf > 0 && sweep_prefetch_fits(s, coupled, VJ, VF);
     const int R = std::max(RF, RJ);
     while (sh.tps_st < 8 && SW_THREADS / (sh.tps_st * 2) >= R * 8) sh.tps_st *= 2;
-    sh.big_min = 384;
+    sh.big_min = 256;
     if (const char *e = std::getenv("IRK_SWEEP_BIG")) sh.big_min = std::max(1, std::atoi(e));
     if (!sh.pf) { sh.tps_pf = sh.tps_st; sh.big_min = 1; }
     return sh;
@@ -273,7 +273,7 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     const int ft = factor_type(o);
     const long long N = (long long)s * T * m;
     const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * s * (s - 1) : 0;
-    P.nitems_max = T * (16 + 2 * s) + 2 * RED_BLOCKS + 64;
+    P.nitems_max = T * (24 + 10 * s) + 2 * RED_BLOCKS + 64;   // sweep records and padded factor tasks
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
     P.o_dsys = take(sizeof(SysDesc));
@@ -942,9 +942,20 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     h->fitems.clear();
     if (o->pc != IRK_PC_NONE) {
         for (size_t l = 0; l + 1 < h->sc.off_fwd.size(); ++l) {
+            // phase 0: workgroup w takes stage k = (w / 8) % s of element
+            // 8 (w / (8 s)) + w % 8, so the s tasks of an element run on one
+            // XCD (workgroups go to the XCDs round-robin) and share its L2
+            // for the blocks common to all stages; first = -1 pads the last
+            // group of eight
             Launch A{(int)(W.items.size() + h->fitems.size()), 0};
-            for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a)
-                for (int k = 0; k < s; ++k) { h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, k}); A.n++; }
+            const int a0 = h->sc.off_fwd[l], ne = h->sc.off_fwd[l + 1] - a0;
+            for (int g = 0; g < (ne + 7) / 8; ++g)
+                for (int k = 0; k < s; ++k)
+                    for (int r = 0; r < 8; ++r) {
+                        const int e = 8 * g + r;
+                        h->fitems.push_back(Item{0, e < ne ? h->sc.lvl_fwd[a0 + e] : -1, 1, k});
+                        A.n++;
+                    }
             h->fa.push_back(A);
             Launch B{(int)(W.items.size() + h->fitems.size()), 0};
             if (h->coupled)

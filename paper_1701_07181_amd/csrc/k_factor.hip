@@ -132,6 +132,7 @@ __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
 {
     constexpr int TEAM = team_of<CLS>();
     const Item it = items[blockIdx.x];
+    if (it.first < 0) return;                     // padding task (whole workgroup)
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, ld = d.ld;
     const int i = it.first, k = it.aux;
