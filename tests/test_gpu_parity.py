@@ -102,6 +102,14 @@ FAC_CASES = [
     ("uncoupled", (2, 2, 4, 7, 2)),
     ("coupled", (3, 3, 4, 135, 1)),
     ("uncoupled_shifted", (3, 2, 6, 64, 1)),
+    # the block-size classes of the factorization kernels and their edges:
+    # m <= 64 partial tiles / all tiles with a ragged K block, 64 < m <= 128
+    # (two row groups per lane), 128 < m <= 160 (three)
+    ("coupled", (3, 2, 4, 33, 1)),
+    ("coupled", (2, 2, 4, 60, 1)),
+    ("uncoupled_shifted", (2, 2, 4, 100, 1)),
+    ("coupled", (2, 2, 4, 129, 1)),
+    ("uncoupled", (2, 2, 4, 160, 1)),
 ]
 
 
@@ -130,6 +138,31 @@ def test_factor_parity(pc, case):
                     ref = G if l > k else G @ F.block(l * T + i, l * T + i)
                     worst = max(worst, np.abs(Cg[k, l, i] - ref).max() / max(np.abs(ref).max(), 1e-300))
         assert worst < 1e-11
+    sol.close()
+
+
+@pytest.mark.parametrize("m", [16, 64, 100, 135])
+def test_factor_pivot_ties(m):
+    """Pivot blocks whose columns hold equal magnitudes everywhere (random
+    +-1 mass blocks, zero Jacobian, so P_{k,i} = A^{-1}_kk M_i): every pivot
+    choice is a tie, decided by the first candidate row.  The inverses must
+    still match the oracle's."""
+    irk = _irk()
+    _say("factor ties", m)
+    sy = _system(2, 2, 4, m, 1, seed=41)
+    rng = np.random.default_rng(43 + m)
+    sy.J[:] = 0.0
+    for i in range(sy.T):
+        while True:             # a well-conditioned sign matrix (redrawn otherwise)
+            sy.M[i] = rng.choice([-1.0, 1.0], size=(m, m))
+            if np.linalg.cond(sy.M[i]) < 1e4:
+                break
+    sol = irk.Solver(sy, irk.Options(pc="uncoupled"))
+    sol.factor()
+    Pg = sol.export_factors(cross=False)
+    Po, _ = _oracle_pivots(sy, "uncoupled")
+    # condition numbers up to 1e4: the two FP64 inverses agree to ~cond * eps
+    assert _rel(Pg.cpu().numpy(), Po) < 1e-10
     sol.close()
 
 
