@@ -112,6 +112,25 @@ __device__ __forceinline__ void prefetch_block(const GAS typename Vec16<TF>::st 
     }
 }
 
+// The record's first SW_NB (= 8) columns as separate register values: a
+// select over them picks block b's column.  (Selects over loads of an array
+// are folded into one indexed load, which places the array in private
+// memory; scalars produced by an empty asm statement stay in registers.)
+struct RecCols {
+    int c0, c1, c2, c3, c4, c5, c6, c7;
+    __device__ __forceinline__ explicit RecCols(const SwItem &rec)
+        : c0(rec.col[0]), c1(rec.col[1]), c2(rec.col[2]), c3(rec.col[3]),
+          c4(rec.col[4]), c5(rec.col[5]), c6(rec.col[6]), c7(rec.col[7])
+    {
+        asm volatile("" : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(c4), "+v"(c5), "+v"(c6), "+v"(c7));
+    }
+    __device__ __forceinline__ int operator()(int b) const
+    {
+        return b == 0 ? c0 : b == 1 ? c1 : b == 2 ? c2 : b == 3 ? c3 : b == 4 ? c4 : b == 5 ? c5 : b == 6 ? c6 : c7;
+    }
+};
+static_assert(SW_NB == 8, "RecCols holds eight columns");
+
 template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
 __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, bool has, int tps,
                                            int region, int v_slot, int v_index, int acc_slot,
@@ -149,63 +168,85 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     const int pa = rec.pa, ncol = rec.nb * m;
     const auto jrow = Jb + (size_t)pa * m * ldJ + sJ * VJ;
 
+    // Every load below (first gather pass, prefetch) is unconditional, with
+    // indices clamped into the arrays (padding teams read element 0), so all
+    // of them are in flight together and the first pass's stores wait only
+    // for its own loads.
+    // ---- gather, first pass (loads): this element's input and the
+    //      neighbours' vectors ----
+    const int nown = s * m;
+    const long long ic = max(i, 0);
+    const RecCols cols(rec);
+    const GAS double *vin = gp(reinterpret_cast<const double *>(d.vec[v_slot])) + (long long)v_index * d.N;
+    // entry q: this element's input (q < s m) and, for q < ncol, block b row
+    // c of the neighbours' vectors (every stage); blocks b >= SW_NB (rows of
+    // more than SW_NB blocks) are redone below with the index array
+    TC own0, nv0[S];
+    {
+        const int q = tid;
+        const int qo = min(q, nown - 1), ko = qo / m, ro = qo - ko * m;
+        const long long go = ko * n + ic * m + ro;
+        own0 = FWD ? (TC)vin[go] : yh[go];
+        const int qn = min(q, max(ncol - 1, 0)), b = qn / m, c = qn - b * m;
+        const long long j = (ncol == 0) ? ic : cols(b);
+#pragma unroll
+        for (int k = 0; k < S; ++k) nv0[k] = yh[min(k, s - 1) * n + j * m + c];
+    }
+    __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the prefetch
+
     // ---- prefetch: Jacobian row (first QJ column loads), pivots, cross blocks ----
     TC rJ[QJ][VJ];
     TC rP[S][NQ][VF];
     TC rC[S][S][NQ][VF];   // [k][l]: block C_{lk} used by round k
     if (PF) {
-        if (SHJ && has && gJ < GJ && ncol > 0) {
+        if (SHJ) {
+            const auto jrow_c = Jb + (size_t)min(pa, d.nnzb - 1) * m * ldJ + sJ * VJ;
 #pragma unroll
             for (int q = 0; q < QJ; ++q) {
                 const int cg = gJ + GJ * q;
-                Vec16<TJ>::load(jrow + (size_t)min(cg, ncol - 1) * ldJ, rJ[q]);
+                Vec16<TJ>::load(jrow_c + (size_t)min(cg, max(ncol - 1, 0)) * ldJ, rJ[q]);
             }
         }
-        if (fact) {
 #pragma unroll
-            for (int k = 0; k < S; ++k) {
-                if (k >= s) continue;
-                prefetch_block<TF, TC, NQ>(Pb + ((long long)i * s + k) * bsF + sF * VF, ldF, m, gF, GF,
-                                           rP[k]);
-                if (COUPLED) {
+        for (int k = 0; k < S; ++k) {
+            const int kc = min(k, s - 1);
+            prefetch_block<TF, TC, NQ>(Pb + (ic * s + kc) * bsF + sF * VF, ldF, m, gF, GF, rP[k]);
+            if (COUPLED) {
 #pragma unroll
-                    for (int l = 0; l < S; ++l) {
-                        if (l >= s || l == k || (FWD ? (l < k) : (l > k))) continue;
-                        const int idx = l < k ? l : l - 1;
-                        prefetch_block<TF, TC, NQ>(Cb + (((long long)i * s + k) * sm1 + idx) * bsF + sF * VF,
-                                                   ldF, m, gF, GF, rC[k][l]);
-                    }
+                for (int l = 0; l < S; ++l) {
+                    if (l == k || (FWD ? (l < k) : (l > k))) continue;
+                    const int lc = min(l, s - 1);
+                    const int idx = max(0, min(lc < kc ? lc : lc - 1, sm1 - 1));
+                    prefetch_block<TF, TC, NQ>(Cb + ((ic * s + kc) * sm1 + idx) * bsF + sF * VF,
+                                               ldF, m, gF, GF, rC[k][l]);
                 }
             }
         }
     }
 
-    // ---- gather the neighbours' vectors and this element's input ----
-    // (every load of a pass is unconditional, with clamped indices, so a
-    // pass costs one memory latency)
+    // ---- gather: first pass stores, entries beyond it (more than a team's
+    //      worth, or blocks past SW_NB) ----
     if (has) {
-        const int nown = s * m;
-        const GAS double *vin = gp(reinterpret_cast<const double *>(d.vec[v_slot])) + (long long)v_index * d.N;
+        if (tid < nown) yv[(tid / m) * ldv + tid % m] = own0;
+        if (tid < ncol) {
+#pragma unroll
+            for (int k = 0; k < S; ++k)
+                if (k < s) xg[k * maxg + tid] = nv0[k];
+        }
         for (int q = tid; q < max(ncol, nown); q += team) {
-            // this element's input, stage k, row r
-            const int qo = min(q, nown - 1), ko = qo / m, ro = qo - ko * m;
-            const long long go = ko * n + (long long)i * m + ro;
-            const TC own = FWD ? (TC)vin[go] : yh[go];
-            // the neighbours' vectors: block b, row c, every stage
-            const int qn = min(q, max(ncol - 1, 0)), b = qn / m, c = qn - b * m;
-            int jb = rec.col[0];
-#pragma unroll
-            for (int t = 1; t < SW_NB; ++t) jb = (b == t) ? rec.col[t] : jb;
-            long long j = (ncol == 0) ? i : jb;
-            if (b >= SW_NB) j = gp(d.col_idx)[pa + b];     // rows of more than SW_NB blocks only
-            TC nv[S];
-#pragma unroll
-            for (int k = 0; k < S; ++k) nv[k] = yh[min(k, s - 1) * n + j * m + c];
-            if (q < nown) yv[ko * ldv + ro] = own;
+            const bool far = q < ncol && q / m >= SW_NB;
+            if (q == tid && !far) continue;           // done by the first pass
+            if (q < nown && q != tid) {
+                const int ko = q / m, ro = q - ko * m;
+                const long long go = ko * n + (long long)i * m + ro;
+                yv[ko * ldv + ro] = FWD ? (TC)vin[go] : yh[go];
+            }
             if (q < ncol) {
+                const int b = q / m, c = q - b * m;
+                const long long j = (b < SW_NB) ? cols(b) : gp(d.col_idx)[pa + b];
 #pragma unroll
                 for (int k = 0; k < S; ++k)
-                    if (k < s) xg[k * maxg + q] = nv[k];
+                    if (k < s) xg[k * maxg + q] = yh[k * n + j * m + c];
             }
         }
     }
