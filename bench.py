@@ -228,6 +228,7 @@ def run_serve(args):
         srv = Server(opts, capacity=64, max_elements=1 << 20, budget_bytes=120 << 30)
         results = srv.run(reqs)
         st = latency_stats(results)
+        st["stalls"], st["evictions"] = srv.stalls, srv.evictions
         srv.close()
         st["offered_qps"] = qps
         points.append(st)

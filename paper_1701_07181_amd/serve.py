@@ -71,7 +71,8 @@ class Server:
         self.ready: collections.deque = collections.deque()
         self.active: Dict[int, tuple] = {}                  # rid -> (request, reused)
         self.results: List[Result] = []
-        self.stalls = 0
+        self.stalls = 0                                     # waits for memory or a free slot
+        self.evictions = 0                                  # resident factorizations dropped
         self.t0 = time.perf_counter()
         self.error: Optional[BaseException] = None
         self.worker = threading.Thread(target=self._prep_loop, daemon=True)
@@ -92,6 +93,7 @@ class Server:
                     return False
                 self.resident.pop(victim).close()
                 used -= self.bytes_of.pop(victim)
+                self.evictions += 1
             self.reserved += need
             return True
 
