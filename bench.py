@@ -94,6 +94,8 @@ def run_mixed(args):
         opts = irk.Options(pc="uncoupled_shifted", matvec_prec=mv, factor_prec=fp, rtol=1e-8,
                            restart=30)
         sol = irk.Solver(sy, opts)
+        sol.factor()
+        sol.autotune()
         for _ in range(max(1, args.warmup)):
             sol.factor()
             x, info = sol.solve(rhs)
@@ -156,6 +158,13 @@ def run_batched(args):
     res = {}
     for label, opts in [("mixed", mixed), ("fp64", plain)]:
         solvers = [irk.Solver(sy, opts) for sy in systems]
+        # launch shapes per problem class: timed on the first system of each
+        # class, then taken from the process-wide table
+        tuned = 0
+        for so in solvers:
+            so.factor()
+            tuned += 1 - so.autotune()["from_cache"]
+        _log(f"batched {label}: {tuned} problem classes timed by the autotuner")
         batch = irk.Batch(count, elems) if label == "mixed" else None
         modes = ["batched", "one_by_one"] if batch else ["one_by_one"]
         for mode in modes:
@@ -294,6 +303,10 @@ def main():
     opts = irk.Options(pc=args.pc, rtol=1e-10, restart=30)
     solver = irk.Solver(sy, opts)
     Jd, Md = solver.J, solver.M
+    # launch shapes timed once on this system (setup, like the level schedule)
+    solver.factor()
+    tune = solver.autotune()
+    print(f"# autotune: {tune}", file=sys.stderr, flush=True)
     rhs = torch.as_tensor(sy.rhs).cuda()
     stream = solver.stream
 
@@ -385,6 +398,7 @@ def main():
                    "dt": args.dt, "rtol": 1e-10, "restart": 30},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "autotune": {k: tune[k] for k in ("matvec_teams", "sweep_big_min", "sweep_teams")},
         "iters": {"min": min(iters), "max": max(iters)},
         "equiv_mults": iters[0] * sy.s,
         "rel_res_true_max": res,

@@ -65,6 +65,11 @@ class _Prof(C.Structure):
                 ("dropped", C.c_int)]
 
 
+class _Tune(C.Structure):
+    _fields_ = [("matvec_teams", C.c_int), ("sweep_big_min", C.c_int), ("sweep_teams", C.c_int),
+                ("from_cache", C.c_int), ("matvec_us", C.c_float), ("sweep_us", C.c_float)]
+
+
 _vp = C.c_void_p
 _L.irk_status_str.restype = C.c_char_p
 _L.irk_status_str.argtypes = [C.c_int]
@@ -91,6 +96,7 @@ _L.irk_radau_iia.argtypes = [C.c_int, _vp, _vp, _vp]
 _L.irk_profile_enable.argtypes = [_vp, C.c_int]
 _L.irk_quantize_blocks.argtypes = [_vp, C.c_longlong, C.c_int, C.c_int, _vp, _vp, _vp]
 _L.irk_profile_read.argtypes = [_vp, C.POINTER(_Prof)]
+_L.irk_autotune.argtypes = [_vp, C.c_int, C.POINTER(_Tune)]
 
 EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_update_values",
             "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
@@ -98,7 +104,7 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_destroy", "irk_status_str", "irk_radau_iia", "irk_profile_enable",
             "irk_profile_read", "irk_quantize_blocks", "irk_batch_workspace_size",
             "irk_batch_create", "irk_batch_admit", "irk_batch_advance", "irk_batch_retire",
-            "irk_batch_pending", "irk_batch_destroy"]
+            "irk_batch_pending", "irk_batch_destroy", "irk_autotune"]
 
 
 def _check(st: int, where: str):
@@ -285,6 +291,14 @@ class Solver:
         _check(_L.irk_apply_preconditioner(self._h, vv.data_ptr(), z.data_ptr()),
                "irk_apply_preconditioner")
         return z
+
+    def autotune(self, retime: bool = False) -> dict:
+        """Pick the matvec and sweep launch shapes by timing them on this
+        system (irk_autotune); needs a factored solver.  Later solvers of the
+        same problem class reuse the choice without timing."""
+        t = _Tune()
+        _check(_L.irk_autotune(self._h, 1 if retime else 0, C.byref(t)), "irk_autotune")
+        return {f: getattr(t, f) for f, _ in _Tune._fields_}
 
     def profile(self, on: bool = True):
         """Turn HIP-event kernel timing on or off (clears recorded intervals)."""

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -856,6 +858,102 @@ irk_status irk_radau_iia(int s, double *A, double *b, double *c)
     return IRK_OK;
 }
 
+// Work items of a handle (matvec rows, reduction chunks, sweep records per
+// level, factor tasks) and the LDS sizes of its launches, from the launch
+// shapes in the handle (tpw64/32, sw64/32) and the host copy of the
+// pattern.  Used by irk_setup and again by irk_autotune for each candidate.
+static irk_status build_items(irk_handle *h)
+{
+    const Plan &P = h->plan;
+    const irk_options *o = &h->opt;
+    const int s = h->s, T = h->T, m = h->m;
+    const int32_t *rp = h->ints.data(), *ci = h->ints.data() + T + 1;
+    // ---- work items ----
+    WorkSet &W = h->W;
+    W.items.clear();
+    W.fwd64.clear(); W.bwd64.clear(); W.fwd32.clear(); W.bwd32.clear();
+    auto row_items = [&](int tpw, Launch &L) {
+        L.off = (int)W.items.size();
+        L.n = 0;
+        for (int a = 0; a < T; a += tpw) { W.items.push_back(Item{0, a, std::min(tpw, T - a), tpw}); L.n++; }
+    };
+    row_items(h->tpw64, W.mv64);
+    if (h->mixed) row_items(h->tpw32, W.mv32);
+    h->nblk = reduction_chunks((long long)s * T * m);
+    W.vec.off = (int)W.items.size();
+    for (int c = 0; c < h->nblk; ++c) W.items.push_back(Item{0, c, h->nblk, 0});
+    W.vec.n = h->nblk;
+    W.fin.off = (int)W.items.size();
+    W.items.push_back(Item{0, 0, h->nblk, 0});
+    W.fin.n = 1;
+    if (o->pc != IRK_PC_NONE) {
+        const int mr = h->sc.maxrow;
+        const SweepShape &a = h->sw64, &b = h->sw32;
+        const int pa = sw_region(s, m, mr, P, true, h->ftype, a.tps_pf);
+        const int sa = sw_region(s, m, mr, P, true, h->ftype, a.tps_st);
+        add_level_records(W.items, h->sc, rp, ci, true, a, pa, sa, W.fwd64);
+        add_level_records(W.items, h->sc, rp, ci, false, a, pa, sa, W.bwd64);
+        if (h->mixed) {
+            const int pb = sw_region(s, m, mr, P, false, h->ftype, b.tps_pf);
+            const int sb = sw_region(s, m, mr, P, false, h->ftype, b.tps_st);
+            add_level_records(W.items, h->sc, rp, ci, true, b, pb, sb, W.fwd32);
+            add_level_records(W.items, h->sc, rp, ci, false, b, pb, sb, W.bwd32);
+        }
+    }
+    // factor tasks per forward level (stored after the work set's items)
+    h->fa.clear(); h->fb.clear();
+    h->fitems.clear();
+    if (o->pc != IRK_PC_NONE) {
+        for (size_t l = 0; l + 1 < h->sc.off_fwd.size(); ++l) {
+            // phase 0: workgroup w takes stage k = (w / 8) % s of element
+            // 8 (w / (8 s)) + w % 8, so the s tasks of an element run on one
+            // XCD (workgroups go to the XCDs round-robin) and share its L2
+            // for the blocks common to all stages; first = -1 pads the last
+            // group of eight
+            Launch A{(int)(W.items.size() + h->fitems.size()), 0};
+            const int a0 = h->sc.off_fwd[l], ne = h->sc.off_fwd[l + 1] - a0;
+            for (int g = 0; g < (ne + 7) / 8; ++g)
+                for (int k = 0; k < s; ++k)
+                    for (int r = 0; r < 8; ++r) {
+                        const int e = 8 * g + r;
+                        h->fitems.push_back(Item{0, e < ne ? h->sc.lvl_fwd[a0 + e] : -1, 1, k});
+                        A.n++;
+                    }
+            h->fa.push_back(A);
+            Launch B{(int)(W.items.size() + h->fitems.size()), 0};
+            if (h->coupled)
+                for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
+                    h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, 0});
+                    B.n++;
+                }
+            h->fb.push_back(B);
+        }
+    }
+    if ((int)(W.items.size() + h->fitems.size()) > P.nitems_max) return IRK_ERR_ARG;
+    W.smax = s;
+    W.restart = o->restart;
+    W.nsys = 1;
+    W.mixed = h->mixed; W.coupled = h->coupled; W.sharedJ = h->sharedJ;
+    W.has_pc = o->pc != IRK_PC_NONE; W.ftype = h->ftype;
+
+    // ---- LDS sizes ----
+    const int maxrow = h->sc.maxrow;
+    W.shm_mv64 = lds_matvec(s, m, maxrow, P.ld, 2, h->tpw64, sizeof(double));
+    W.shm_mv32 = lds_matvec(s, m, maxrow, P.ld32, 4, h->tpw32, sizeof(float));
+    W.shm_sw64 = sizeof(double) * std::max(h->sw64.tps_pf * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_pf),
+                                           h->sw64.tps_st * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_st));
+    W.shm_sw32 = sizeof(float) * std::max(h->sw32.tps_pf * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_pf),
+                                          h->sw32.tps_st * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_st));
+    // factorization: matrix-core products and register Gauss-Jordan, four
+    // waves for m <= 64, eight above
+    h->shm_fac = sizeof(double) * (size_t)((m <= 64) ? D64_LDS_DOUBLES : std::max(DM_LDS_DOUBLES, DMI_LDS_DOUBLES));
+    const size_t lds_max = 160 * 1024;
+    if (h->shm_fac > lds_max || W.shm_mv64 > lds_max || W.shm_sw64 > lds_max ||
+        (h->mixed && (W.shm_sw32 > lds_max || W.shm_mv32 > lds_max)))
+        return IRK_ERR_ARG;
+    return IRK_OK;
+}
+
 irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace, size_t ws_bytes,
                      hipStream_t stream, irk_handle **out)
 {
@@ -898,102 +996,21 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     h->sharedJ = (p->nJ == 1);
     h->ftype = factor_type(o);
 
-    // ---- work items ----
-    WorkSet &W = h->W;
-    W.items.clear();
     h->tpw64 = pick_tpw(P.ld, 2);
     h->tpw32 = pick_tpw(P.ld32, 4);
-    auto row_items = [&](int tpw, Launch &L) {
-        L.off = (int)W.items.size();
-        L.n = 0;
-        for (int a = 0; a < T; a += tpw) { W.items.push_back(Item{0, a, std::min(tpw, T - a), tpw}); L.n++; }
-    };
-    row_items(h->tpw64, W.mv64);
-    if (h->mixed) row_items(h->tpw32, W.mv32);
-    h->nblk = reduction_chunks((long long)s * T * m);
-    W.vec.off = (int)W.items.size();
-    for (int c = 0; c < h->nblk; ++c) W.items.push_back(Item{0, c, h->nblk, 0});
-    W.vec.n = h->nblk;
-    W.fin.off = (int)W.items.size();
-    W.items.push_back(Item{0, 0, h->nblk, 0});
-    W.fin.n = 1;
     {
         const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
         const int VF = (h->ftype == FT_F32) ? 4 : 8;
         h->sw64 = pick_sweep(m, P.ld, 2, P.ld, 2, s, h->coupled);
         h->sw32 = pick_sweep(m, P.ld32, 4, ldF, VF, s, h->coupled);
     }
-    if (o->pc != IRK_PC_NONE) {
-        const int mr = h->sc.maxrow;
-        const SweepShape &a = h->sw64, &b = h->sw32;
-        const int pa = sw_region(s, m, mr, P, true, h->ftype, a.tps_pf);
-        const int sa = sw_region(s, m, mr, P, true, h->ftype, a.tps_st);
-        add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, true, a, pa, sa, W.fwd64);
-        add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, false, a, pa, sa, W.bwd64);
-        if (h->mixed) {
-            const int pb = sw_region(s, m, mr, P, false, h->ftype, b.tps_pf);
-            const int sb = sw_region(s, m, mr, P, false, h->ftype, b.tps_st);
-            add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, true, b, pb, sb, W.fwd32);
-            add_level_records(W.items, h->sc, p->row_ptr, p->col_idx, false, b, pb, sb, W.bwd32);
-        }
-    }
-    // factor tasks per forward level (stored after the work set's items)
-    h->fa.clear(); h->fb.clear();
-    h->fitems.clear();
-    if (o->pc != IRK_PC_NONE) {
-        for (size_t l = 0; l + 1 < h->sc.off_fwd.size(); ++l) {
-            // phase 0: workgroup w takes stage k = (w / 8) % s of element
-            // 8 (w / (8 s)) + w % 8, so the s tasks of an element run on one
-            // XCD (workgroups go to the XCDs round-robin) and share its L2
-            // for the blocks common to all stages; first = -1 pads the last
-            // group of eight
-            Launch A{(int)(W.items.size() + h->fitems.size()), 0};
-            const int a0 = h->sc.off_fwd[l], ne = h->sc.off_fwd[l + 1] - a0;
-            for (int g = 0; g < (ne + 7) / 8; ++g)
-                for (int k = 0; k < s; ++k)
-                    for (int r = 0; r < 8; ++r) {
-                        const int e = 8 * g + r;
-                        h->fitems.push_back(Item{0, e < ne ? h->sc.lvl_fwd[a0 + e] : -1, 1, k});
-                        A.n++;
-                    }
-            h->fa.push_back(A);
-            Launch B{(int)(W.items.size() + h->fitems.size()), 0};
-            if (h->coupled)
-                for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
-                    h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, 0});
-                    B.n++;
-                }
-            h->fb.push_back(B);
-        }
-    }
-    if ((int)(W.items.size() + h->fitems.size()) > P.nitems_max) { delete h; return IRK_ERR_ARG; }
-    W.smax = s;
-    W.restart = o->restart;
-    W.nsys = 1;
-    W.mixed = h->mixed; W.coupled = h->coupled; W.sharedJ = h->sharedJ;
-    W.has_pc = o->pc != IRK_PC_NONE; W.ftype = h->ftype;
-
-    // ---- LDS sizes ----
+    h->ints.assign((size_t)(T + 1) + 2 * (size_t)p->nnzb + 3 * (size_t)T, 0);
+    std::memcpy(h->ints.data(), p->row_ptr, sizeof(int) * (T + 1));
+    std::memcpy(h->ints.data() + T + 1, p->col_idx, sizeof(int) * p->nnzb);
+    st = build_items(h);
+    if (st != IRK_OK) { delete h; return st; }
+    WorkSet &W = h->W;
     const int maxrow = h->sc.maxrow;
-    W.shm_mv64 = lds_matvec(s, m, maxrow, P.ld, 2, h->tpw64, sizeof(double));
-    W.shm_mv32 = lds_matvec(s, m, maxrow, P.ld32, 4, h->tpw32, sizeof(float));
-    W.shm_sw64 = sizeof(double) * std::max(h->sw64.tps_pf * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_pf),
-                                           h->sw64.tps_st * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_st));
-    {
-        const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
-        const int VF = (h->ftype == FT_F32) ? 4 : 8;
-        W.shm_sw32 = sizeof(float) * std::max(h->sw32.tps_pf * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_pf),
-                                              h->sw32.tps_st * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_st));
-    }
-    // factorization: matrix-core products and register Gauss-Jordan, four
-    // waves for m <= 64, eight above
-    h->shm_fac = sizeof(double) * (size_t)((m <= 64) ? D64_LDS_DOUBLES : std::max(DM_LDS_DOUBLES, DMI_LDS_DOUBLES));
-    const size_t lds_max = 160 * 1024;
-    if (h->shm_fac > lds_max || W.shm_mv64 > lds_max || W.shm_sw64 > lds_max ||
-        (h->mixed && (W.shm_sw32 > lds_max || W.shm_mv32 > lds_max))) {
-        delete h;
-        return IRK_ERR_ARG;
-    }
     factor_set_lds_limit(h->shm_fac);
     // ---- device pointers ----
     char *ws = h->ws;
@@ -1051,9 +1068,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     W.ditems = h->ditems;
 
     // ---- uploads ----
-    h->ints.assign((size_t)(T + 1) + 2 * (size_t)p->nnzb + 3 * (size_t)T, 0);
-    std::memcpy(h->ints.data(), p->row_ptr, sizeof(int) * (T + 1));
-    std::memcpy(h->ints.data() + T + 1, p->col_idx, sizeof(int) * p->nnzb);
+    // (row_ptr and col_idx are already in h->ints)
     std::memcpy(h->ints.data() + T + 1 + p->nnzb, h->sc.tpos.data(), sizeof(int) * p->nnzb);
     std::memcpy(h->ints.data() + T + 1 + 2 * p->nnzb, h->sc.diag.data(), sizeof(int) * T);
     std::memcpy(h->ints.data() + T + 1 + 2 * p->nnzb + T, h->sc.lvl_fwd.data(), sizeof(int) * T);
@@ -1509,3 +1524,138 @@ irk_status irk_batch_destroy(irk_batch *b)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuning of the launch shapes
+// ---------------------------------------------------------------------------
+namespace {
+
+// Items to the device (work set + factor tasks); synchronous, so the host
+// vector may go out of scope.
+irk_status upload_items(irk_handle *h)
+{
+    std::vector<Item> all(h->W.items);
+    all.insert(all.end(), h->fitems.begin(), h->fitems.end());
+    HIPCHK(hipMemcpyAsync(h->ditems, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+struct TuneVal {
+    int tpw64, tpw32;
+    SweepShape sw64, sw32;
+    float matvec_us, sweep_us;
+};
+
+std::mutex g_tune_mu;
+std::map<std::vector<long long>, TuneVal> g_tune;   // process-wide: one timing per problem class
+
+std::vector<long long> tune_key(const irk_handle *h)
+{
+    int lg = 0;
+    while ((1LL << lg) < h->T) ++lg;
+    return {h->m, h->s, h->coupled, h->mixed, h->ftype, h->sharedJ, h->sc.maxrow, (long long)h->opt.pc, lg};
+}
+
+// Average time of reps calls of f on the handle's stream (after one warm-up).
+template <typename F>
+float time_us(irk_handle *h, F f, int reps)
+{
+    f();
+    hipEventRecord(h->ev0, h->stream);
+    for (int r = 0; r < reps; ++r) f();
+    hipEventRecord(h->ev1, h->stream);
+    hipEventSynchronize(h->ev1);
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    return ms * 1e3f / reps;
+}
+
+}  // namespace
+
+extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *info)
+{
+    if (!h) return IRK_ERR_ARG;
+    if (h->opt.pc != IRK_PC_NONE && !h->factored) return IRK_ERR_STATE;
+    const std::vector<long long> key = tune_key(h);
+    TuneVal best{h->tpw64, h->tpw32, h->sw64, h->sw32, 0.0f, 0.0f};
+    bool cached = false;
+    if (!retime) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) { best = it->second; cached = true; }
+    }
+    if (!cached) {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        Ctx C{&h->W, h->stream, nullptr};
+        const bool fp64 = !h->mixed;        // the precision of the inner iteration
+        const Plan &P = h->plan;
+        // matvec: block rows per workgroup
+        {
+            const int ld = fp64 ? P.ld : P.ld32, V = fp64 ? 2 : 4;
+            int &tpw = fp64 ? h->tpw64 : h->tpw32;
+            float tbest = 0.0f;
+            int cbest = tpw;
+            for (int cand = 1; cand <= 8; cand *= 2) {
+                if (NTHREADS / cand < ld / V) break;
+                tpw = cand;
+                if (build_items(h) != IRK_OK) continue;
+                irk_status st = upload_items(h);
+                if (st != IRK_OK) return st;
+                const float t = time_us(h, [&] { enqueue_matvec(C, fp64, SL_YH, SL_W, -1, 0, 0); }, 3);
+                if (tbest == 0.0f || t < tbest) { tbest = t; cbest = cand; }
+            }
+            tpw = cbest;
+            best.matvec_us = tbest;
+            best.tpw64 = h->tpw64;
+            best.tpw32 = h->tpw32;
+        }
+        // sweeps: streaming-form threshold and elements per streaming workgroup
+        if (h->opt.pc != IRK_PC_NONE) {
+            SweepShape &sh = fp64 ? h->sw64 : h->sw32;
+            const SweepShape base = sh;
+            const int ldF = fp64 ? P.ld : ((h->ftype == FT_F32) ? P.ld32 : P.ld16);
+            const int VF = fp64 ? 2 : ((h->ftype == FT_F32) ? 4 : 8);
+            const int R = std::max(ldF / VF, fp64 ? P.ld / 2 : P.ld32 / 4);
+            const int bigs[] = {1, 64, 128, 256, 512, 1 << 30};
+            float tbest = 0.0f;
+            SweepShape cbest = base;
+            for (int tps : {base.tps_st / 2, base.tps_st, base.tps_st * 2}) {
+                if (tps < 1 || tps > 16 || SW_THREADS / tps < 4 * R) continue;
+                for (int bm : bigs) {
+                    if (!base.pf && bm != 1) continue;
+                    sh = base;
+                    sh.tps_st = tps;
+                    sh.big_min = bm;
+                    if (build_items(h) != IRK_OK) continue;
+                    irk_status st = upload_items(h);
+                    if (st != IRK_OK) return st;
+                    const float t = time_us(h, [&] { enqueue_pc(C, fp64, SL_EXT0, 0, -1, 0); }, 3);
+                    if (tbest == 0.0f || t < tbest) { tbest = t; cbest = sh; }
+                }
+            }
+            sh = cbest;
+            best.sweep_us = tbest;
+            best.sw64 = h->sw64;
+            best.sw32 = h->sw32;
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+    }
+    h->tpw64 = best.tpw64; h->tpw32 = best.tpw32;
+    h->sw64 = best.sw64; h->sw32 = best.sw32;
+    irk_status st = build_items(h);
+    if (st != IRK_OK) return st;
+    st = upload_items(h);
+    if (st != IRK_OK) return st;
+    if (info) {
+        const SweepShape &sh = h->mixed ? h->sw32 : h->sw64;
+        info->matvec_teams = h->mixed ? h->tpw32 : h->tpw64;
+        info->sweep_big_min = sh.big_min;
+        info->sweep_teams = sh.tps_st;
+        info->from_cache = cached ? 1 : 0;
+        info->matvec_us = best.matvec_us;
+        info->sweep_us = best.sweep_us;
+    }
+    return IRK_OK;
+}
