@@ -24,6 +24,11 @@ struct f16s { uint16_t u; };
 // Blocks are stored column-major with a leading dimension that is a multiple
 // of V, so every load is one aligned dwordx4.
 // ---------------------------------------------------------------------------
+// 16-byte loads of one column piece of a matrix block, converted to the
+// compute type.  Every caller streams blocks that are read once per pass
+// (Jacobian, mass, pivot and cross blocks), so the loads are nontemporal:
+// the blocks do not displace the stage vectors, which neighbouring elements
+// re-read, from the caches.
 template <typename TS> struct Vec16;
 
 template <> struct Vec16<double> {
@@ -31,7 +36,7 @@ template <> struct Vec16<double> {
     using st = double;
     template <typename TC>
     __device__ __forceinline__ static void load(const GAS double *p, TC *o) {
-        const dbl2 v = *reinterpret_cast<const GAS dbl2 *>(p);
+        const dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const GAS dbl2 *>(p));
         o[0] = (TC)v.x; o[1] = (TC)v.y;
     }
 };
@@ -41,7 +46,7 @@ template <> struct Vec16<float> {
     using st = float;
     template <typename TC>
     __device__ __forceinline__ static void load(const GAS float *p, TC *o) {
-        const flt4 v = *reinterpret_cast<const GAS flt4 *>(p);
+        const flt4 v = __builtin_nontemporal_load(reinterpret_cast<const GAS flt4 *>(p));
         o[0] = (TC)v.x; o[1] = (TC)v.y; o[2] = (TC)v.z; o[3] = (TC)v.w;
     }
 };
@@ -59,7 +64,7 @@ template <> struct Vec16<bf16s> {
     using st = uint16_t;
     template <typename TC>
     __device__ __forceinline__ static void load(const GAS uint16_t *p, TC *o) {
-        const u32x4 v = *reinterpret_cast<const GAS u32x4 *>(p);
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const GAS u32x4 *>(p));
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -74,7 +79,7 @@ template <> struct Vec16<f16s> {
     using st = uint16_t;
     template <typename TC>
     __device__ __forceinline__ static void load(const GAS uint16_t *p, TC *o) {
-        const u32x4 v = *reinterpret_cast<const GAS u32x4 *>(p);
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const GAS u32x4 *>(p));
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {

@@ -12,6 +12,8 @@
 // single HBM read.  Partial sums of the column groups are combined through
 // LDS at the end.  Blocks are stored column-major (leading dimension ld), so
 // consecutive threads read consecutive rows of a column: fully coalesced.
+// Block loads are nontemporal (each block is read once per product), and the
+// first columns of a shared Jacobian row are requested before the gather.
 #include "irk_device.h"
 
 namespace irk {
@@ -50,6 +52,19 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
         p0 = row_ptr[row];
         p1 = row_ptr[row + 1];
         ncol = (p1 - p0) * m;
+    }
+    // The first PFU column loads of the shared Jacobian row go out before the
+    // gather (addresses clamped into the row; a team without a row reads
+    // block 0), so the stream starts while the gather waits on x.
+    constexpr int PFU = SHJ ? 8 : 1;
+    TC pre[PFU][V];
+    const auto Jb = jac_of<TM>(d);
+    const auto jrow = Jb + (size_t)p0 * m * ld + slot * V;
+    if (SHJ) {
+#pragma unroll
+        for (int u = 0; u < PFU; ++u) Vec16<TM>::load(jrow + (size_t)min(grp + G * u, max(ncol - 1, 0)) * ld, pre[u]);
+    }
+    if (has) {
         for (int q = tid; q < ncol; q += team) {
             const int b = q / m, c = q - b * m;
             const long long j = col_idx[p0 + b];
@@ -81,14 +96,25 @@ __global__ __launch_bounds__(NTHREADS) void k_matvec(const SysDesc *__restrict__
         for (int v = 0; v < V; ++v) { aj[k][v] = 0; am[k][v] = 0; }
 
     if (has && grp < G) {
-        const auto Jb = jac_of<TM>(d);
         const auto Mb = mass_of<TM>(d);
         if (SHJ) {
-            const auto base = Jb + (size_t)p0 * m * ld + slot * V;
+#pragma unroll
+            for (int u = 0; u < PFU; ++u) {
+                const int cg = grp + G * u;
+                if (cg < ncol) {
+#pragma unroll
+                    for (int k = 0; k < S; ++k) {
+                        if (k >= s) continue;
+                        const TC xv = xg[k * maxcols + cg];
+#pragma unroll
+                        for (int v = 0; v < V; ++v) aj[k][v] += pre[u][v] * xv;
+                    }
+                }
+            }
 #pragma unroll 4
-            for (int cg = grp; cg < ncol; cg += G) {
+            for (int cg = grp + G * PFU; cg < ncol; cg += G) {
                 TC a[V];
-                Vec16<TM>::load(base + (size_t)cg * ld, a);
+                Vec16<TM>::load(jrow + (size_t)cg * ld, a);
 #pragma unroll
                 for (int k = 0; k < S; ++k) {
                     if (k >= s) continue;
