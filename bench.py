@@ -203,28 +203,34 @@ def run_batched(args):
 
 
 def run_serve(args):
-    """Poisson arrivals of solve requests (75 % 2D up to 64x64 p 1..4, 25 % 3D
-    up to 16^3 p 2; s 2..4; 30 % re-use a resident operator), served by the
-    continuous-batching loop with FP32 inner / FP64 outer to 1e-8."""
+    """Poisson arrivals of solve requests (75 % 2D up to 48x48 p 1..4, 25 % 3D
+    up to 12^3 p 2; s 2..4; 30 % re-use a resident operator), served by the
+    continuous-batching loop with FP32 inner / FP64 outer to 1e-8.  The
+    stream replays 200 generated (operator, right-hand side) specifications
+    with fresh right-hand sides; each replay's operators count as new (set up
+    and factored again), which keeps input generation within a minute."""
     import numpy as np
     import torch
     import dgsynth
     import paper_1701_07181_amd as irk
     from paper_1701_07181_amd.serve import Request, Server, latency_stats
-    count = args.count or 200
-    stream = dgsynth.serve_requests(count, N2max=48, N3max=12)
+    count = args.count or 1000
+    NB = 200
+    stream = dgsynth.serve_requests(min(count, NB), N2max=48, N3max=12)
     systems, reqs_base = {}, []
     t0 = time.time()
-    for rid, (spec, reuse_of, rhs_seed) in enumerate(stream):
-        op = rid if reuse_of is None else reuse_of
-        if op not in systems:
+    for rid in range(count):
+        spec, reuse_of, rhs_seed = stream[rid % NB]
+        rep = rid // NB
+        base = rid % NB if reuse_of is None else reuse_of
+        if base not in systems:
             sy = spec.build()
             sy.J = torch.from_numpy(sy.J).cuda()
             sy.M = torch.from_numpy(sy.M).cuda()
-            systems[op] = sy
-        sy = systems[op]
-        rhs = torch.from_numpy(dgsynth.fresh_rhs(rhs_seed, sy.s, sy.T, sy.m)).cuda()
-        reqs_base.append((rid, op, sy, rhs))
+            systems[base] = sy
+        sy = systems[base]
+        rhs = torch.from_numpy(dgsynth.fresh_rhs((*rhs_seed, rep), sy.s, sy.T, sy.m)).cuda()
+        reqs_base.append((rid, base + NB * rep, sy, rhs))
     torch.cuda.synchronize()
     _log(f"built {len(systems)} operators for {count} requests in {time.time() - t0:.1f}s")
     opts = irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="fp32", rtol=1e-8,
@@ -247,7 +253,9 @@ def run_serve(args):
             "unit": "solves/s", "data": "synthetic",
             "config": {"workload": f"{count} requests per arrival rate (Poisson), 75% 2D N<=48 p 1..4, "
                                    "25% 3D N<=12 p=2, s 2..4, 30% operator re-use, FP32 inner / FP64 "
-                                   "outer, rtol 1e-8, capacity 64"},
+                                   f"outer, rtol 1e-8, capacity 64, {NB} generated specifications "
+                                   "replayed with fresh right-hand sides (replayed operators set up "
+                                   "and factored again), 120 GiB workspace pool"},
             "points": points}
 
 

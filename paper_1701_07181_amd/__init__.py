@@ -184,12 +184,15 @@ class Solver:
     ``system`` needs the attributes s, T, m, nJ, dt, row_ptr, col_idx (host
     int32), J [nJ, nnzb, m, m] and M [T, m, m] (NumPy or torch FP64; moved to
     the device here).  ``A`` is the s x s Butcher matrix (default: Radau IIA
-    from the library).
+    from the library).  ``workspace_alloc(nbytes)``, if given, supplies the
+    device workspace (a uint8 CUDA tensor of at least nbytes bytes, 256-byte
+    aligned) in place of a fresh allocation, e.g. a range of a pool that the
+    caller manages.
     """
 
     def __init__(self, system, options: Optional[Options] = None, A=None,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
-                 s: Optional[int] = None, dt: Optional[float] = None):
+                 s: Optional[int] = None, dt: Optional[float] = None, workspace_alloc=None):
         self.options = options or Options()
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.stream = stream or torch.cuda.current_stream(self.device)
@@ -213,7 +216,16 @@ class Solver:
         _check(_L.irk_workspace_size(C.byref(self._p), C.byref(self._o), C.byref(nbytes)),
                "irk_workspace_size")
         self.workspace_bytes = int(nbytes.value)
-        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        if workspace_alloc is None:
+            self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        else:
+            ws = workspace_alloc(self.workspace_bytes)
+            if (not isinstance(ws, torch.Tensor) or ws.dtype != torch.uint8 or ws.device.type != "cuda"
+                    or (self.device.index is not None and ws.device.index != self.device.index)
+                    or ws.numel() < self.workspace_bytes or ws.data_ptr() % 256):
+                raise ValueError("workspace_alloc must return an aligned uint8 tensor of at least "
+                                 f"{self.workspace_bytes} bytes on {self.device}")
+            self.workspace = ws
         h = _vp()
         _check(_L.irk_setup(C.byref(self._p), C.byref(self._o), self.workspace.data_ptr(),
                             self.workspace_bytes, _vp(self.stream.cuda_stream), C.byref(h)),

@@ -6,9 +6,11 @@ device memory) and a right-hand side; some re-use an operator whose
 factorization is still resident.  Two host threads share the device:
 
   * the preparation thread sets up and factors new operators on a side
-    stream (admission by device-memory budget: an operator waits until its
-    workspace fits, evicting idle resident factorizations, least recently
-    used first); re-used operators need no preparation;
+    stream; re-used operators need no preparation.  Admission is by device
+    memory: every operator's workspace is a range of one pool allocated when
+    the server starts (its memory budget), so serving itself never calls the
+    device allocator.  An operator waits until a range of its size is free,
+    evicting idle resident factorizations, least recently used first;
   * the main loop keeps one `Batch` iterating on its own stream: between
     GMRES cycles it admits prepared requests into free slots (a member
     joins at the next cycle boundary, so new work overlaps the members
@@ -30,6 +32,54 @@ import numpy as np
 import torch
 
 from . import Batch, Options, Solver, OK
+
+
+class WorkspacePool:
+    """First-fit ranges of one device allocation (offsets 256-byte aligned,
+    free neighbours merged).  Not thread-safe: the server holds its lock."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes: int, device: torch.device):
+        self.size = self.round(nbytes)
+        self.mem = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free: List[List[int]] = [[0, self.size]]      # [offset, bytes], ascending offsets
+
+    @classmethod
+    def round(cls, n: int) -> int:
+        return (int(n) + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    def take(self, nbytes: int) -> Optional[int]:
+        n = self.round(nbytes)
+        for q, (off, size) in enumerate(self.free):
+            if size >= n:
+                if size == n:
+                    del self.free[q]
+                else:
+                    self.free[q] = [off + n, size - n]
+                return off
+        return None
+
+    def give(self, off: int, nbytes: int):
+        n = self.round(nbytes)
+        q = 0
+        while q < len(self.free) and self.free[q][0] < off:
+            q += 1
+        self.free.insert(q, [off, n])
+        if q + 1 < len(self.free) and off + n == self.free[q + 1][0]:
+            self.free[q][1] += self.free.pop(q + 1)[1]
+        if q > 0 and self.free[q - 1][0] + self.free[q - 1][1] == off:
+            self.free[q - 1][1] += self.free.pop(q)[1]
+
+    def view(self, off: int, nbytes: int) -> torch.Tensor:
+        return self.mem[off:off + nbytes]
+
+    def free_bytes(self) -> int:
+        return sum(size for _, size in self.free)
+
+    def close(self):
+        self.mem = None
+        self.free = []
 
 
 @dataclasses.dataclass
@@ -62,11 +112,13 @@ class Server:
         self.batch = Batch(capacity, max_elements, device=self.device, stream=self.stream)
         self.capacity = capacity
         self.budget = budget_bytes
+        self.pool = WorkspacePool(budget_bytes, self.device)
         self.lock = threading.Lock()
         self.resident: "collections.OrderedDict[int, Solver]" = collections.OrderedDict()
         self.busy: Dict[int, bool] = {}                     # op_id -> member in the batch
-        self.bytes_of: Dict[int, int] = {}
-        self.reserved = 0
+        self.queued: Dict[int, int] = {}                    # op_id -> requests waiting in `ready`
+        self.range_of: Dict[int, tuple] = {}                # op_id -> (offset, bytes) in the pool
+        self._pending: Optional[tuple] = None               # range handed to the Solver being set up
         self.prep_q: "queue.Queue" = queue.Queue()
         self.ready: collections.deque = collections.deque()
         self.active: Dict[int, tuple] = {}                  # rid -> (request, reused)
@@ -79,23 +131,30 @@ class Server:
         self.worker.start()
 
     # -- device-memory budget --
-    def _estimate(self, sy) -> int:
-        n = sy.s * sy.T * sy.m
-        blocks = (sy.nJ * int(len(sy.col_idx)) + sy.T) * sy.m * sy.m
-        return int(8 * (5 * blocks + (self.options.restart + 12) * n))
-
-    def _reserve(self, need: int) -> bool:
-        with self.lock:
-            used = sum(self.bytes_of.values()) + self.reserved
-            while used + need > self.budget:
-                victim = next((k for k in self.resident if not self.busy.get(k, False)), None)
-                if victim is None:
-                    return False
-                self.resident.pop(victim).close()
-                used -= self.bytes_of.pop(victim)
-                self.evictions += 1
-            self.reserved += need
-            return True
+    def _alloc(self, nbytes: int):
+        """A pool range of nbytes for a new operator's workspace (called by
+        Solver during set-up, on the preparation thread): evicts idle
+        resident operators (neither in the batch nor waiting to join it),
+        least recently used first, until a range fits; waits while none is
+        idle."""
+        if WorkspacePool.round(nbytes) > self.budget:
+            raise MemoryError(f"operator workspace of {nbytes} bytes exceeds the pool ({self.budget})")
+        while True:
+            with self.lock:
+                while True:
+                    off = self.pool.take(nbytes)
+                    if off is not None:
+                        self._pending = (off, nbytes)
+                        return self.pool.view(off, nbytes)
+                    victim = next((k for k in self.resident
+                                   if not self.busy.get(k, False) and not self.queued.get(k, 0)), None)
+                    if victim is None:
+                        break
+                    self.resident.pop(victim).close()
+                    self.pool.give(*self.range_of.pop(victim))
+                    self.evictions += 1
+            self.stalls += 1
+            time.sleep(0.0005)
 
     # -- preparation thread --
     def _prep_loop(self):
@@ -106,22 +165,32 @@ class Server:
                 if req is None:
                     return
                 with self.lock:
-                    solver = self.resident.get(req.op_id)
-                if solver is not None:
+                    reused = req.op_id in self.resident
+                    if reused:
+                        self.queued[req.op_id] = self.queued.get(req.op_id, 0) + 1
+                if reused:
                     self.ready.append((req, True))
                     continue
-                need = self._estimate(req.system)
-                while not self._reserve(need):
-                    self.stalls += 1
-                    time.sleep(0.0005)
-                with torch.cuda.stream(self.side):
-                    solver = Solver(req.system, self.options, device=self.device, stream=self.side)
-                    solver.factor()
+                self._pending = None
+                solver = None
+                try:
+                    with torch.cuda.stream(self.side):
+                        solver = Solver(req.system, self.options, device=self.device, stream=self.side,
+                                        workspace_alloc=self._alloc)
+                        solver.factor()
+                except BaseException:
+                    if solver is not None:
+                        solver.close()
+                    if self._pending is not None:
+                        self.side.synchronize()
+                        with self.lock:
+                            self.pool.give(*self._pending)
+                    raise
                 self.side.synchronize()         # factors complete before the batch stream reads them
                 with self.lock:
-                    self.reserved -= need
                     self.resident[req.op_id] = solver
-                    self.bytes_of[req.op_id] = solver.workspace_bytes
+                    self.range_of[req.op_id] = self._pending
+                    self.queued[req.op_id] = self.queued.get(req.op_id, 0) + 1
                 self.ready.append((req, False))
         except BaseException as e:      # surfaced by the main loop
             self.error = e
@@ -135,13 +204,15 @@ class Server:
                 if self.busy.get(req.op_id, False):
                     skipped.append((req, reused))      # its handle is still iterating
                     continue
-                solver = self.resident[req.op_id]
+                solver = self.resident[req.op_id]    # queued operators are never evicted
                 self.resident.move_to_end(req.op_id)
                 self.busy[req.op_id] = True
+                self.queued[req.op_id] -= 1
             st = self.batch.admit(solver, req.rhs, tag=req.rid)
             if st != OK:
                 with self.lock:
                     self.busy[req.op_id] = False
+                    self.queued[req.op_id] += 1
                 skipped.append((req, reused))
                 self.stalls += 1
                 break
@@ -188,6 +259,8 @@ class Server:
         for s in self.resident.values():
             s.close()
         self.resident.clear()
+        self.range_of.clear()
+        self.pool.close()
 
 
 def latency_stats(results: List[Result]) -> dict:
