@@ -198,6 +198,21 @@ irk_status irk_batch_destroy(irk_batch *b);
 irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
                              double *const *x, int count, irk_solve_info *info);
 
+/* Block ILU(0) factorization of `count` handles together (the same
+ * factorization as irk_factor_ilu, Sec. 4.2-4.3): level l of every handle
+ * runs in the same launches (one per level and kernel class), so many small
+ * systems pay one chain of level launches instead of one chain each.  The
+ * batch b (no members allowed) lends its device table and item buffer; the
+ * handles may differ in every shape and option.  Runs on the batch's stream
+ * after the work already enqueued on each handle's stream and returns when
+ * the factors are complete.  status (HOST, may be NULL): one entry per
+ * handle, IRK_OK or IRK_ERR_SINGULAR (irk_last_bad_element names the
+ * element).  Returns IRK_ERR_SINGULAR if any handle has a singular pivot,
+ * IRK_ERR_STATE if the batch has members, IRK_ERR_ARG for a null or
+ * repeated handle.  Handles are processed in groups that fit the batch's
+ * capacity and item buffer. */
+irk_status irk_factor_batched(irk_batch *b, irk_handle *const *h, int count, irk_status *status);
+
 /* y = B x with the FP64 operator (Eq. big-irk); DEVICE vectors. */
 irk_status irk_apply_operator(irk_handle *h, const double *x, double *y);
 

@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 from dataclasses import dataclass
-from typing import Optional, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -97,6 +97,7 @@ _L.irk_profile_enable.argtypes = [_vp, C.c_int]
 _L.irk_quantize_blocks.argtypes = [_vp, C.c_longlong, C.c_int, C.c_int, _vp, _vp, _vp]
 _L.irk_profile_read.argtypes = [_vp, C.POINTER(_Prof)]
 _L.irk_autotune.argtypes = [_vp, C.c_int, C.POINTER(_Tune)]
+_L.irk_factor_batched.argtypes = [_vp, C.POINTER(_vp), C.c_int, C.POINTER(C.c_int)]
 
 EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_update_values",
             "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
@@ -104,7 +105,7 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_destroy", "irk_status_str", "irk_radau_iia", "irk_profile_enable",
             "irk_profile_read", "irk_quantize_blocks", "irk_batch_workspace_size",
             "irk_batch_create", "irk_batch_admit", "irk_batch_advance", "irk_batch_retire",
-            "irk_batch_pending", "irk_batch_destroy", "irk_autotune"]
+            "irk_batch_pending", "irk_batch_destroy", "irk_autotune", "irk_factor_batched"]
 
 
 def _check(st: int, where: str):
@@ -398,6 +399,27 @@ class Batch:
             if cnt.value < n:
                 break
         return out
+
+
+def factor_batched(batch: Batch, solvers: Sequence[Solver]) -> List[int]:
+    """Factor several systems together through irk_factor_batched (level l
+    of every system in the same launches; the batch must have no members).
+    Returns the per-system statuses; raises IrkError for the first system
+    with a singular pivot (the others are factored)."""
+    n = len(solvers)
+    if n == 0:
+        return []
+    H = (_vp * n)(*[s.handle for s in solvers])
+    sts = (C.c_int * n)()
+    st = _L.irk_factor_batched(batch._b, H, n, sts)
+    for s, q in zip(solvers, sts):
+        s.factored = (q == OK)
+    if st == ERR_SINGULAR:
+        q = next(q for q in range(n) if sts[q] == ERR_SINGULAR)
+        raise IrkError(st, f"irk_factor_batched (system {q}, element "
+                           f"{_L.irk_last_bad_element(solvers[q].handle)})")
+    _check(st, "irk_factor_batched")
+    return list(sts)
 
 
 def solve_batched(batch: Batch, solvers: Sequence[Solver], rhs: Sequence, x0: Optional[Sequence] = None):

@@ -416,6 +416,7 @@ struct irk_batch {
     std::vector<Member> retired;
     std::vector<int> free_slots;
     hipEvent_t ev_end;
+    hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr;   // span of a batched factorization
 };
 
 namespace {
@@ -1011,7 +1012,10 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     if (st != IRK_OK) { delete h; return st; }
     WorkSet &W = h->W;
     const int maxrow = h->sc.maxrow;
-    factor_set_lds_limit(h->shm_fac);
+    // the largest any factor kernel takes, whatever this handle's m: the
+    // attribute is per kernel and process-wide, and handles of other block
+    // orders (a batched factorization mixes them) launch the same kernels
+    factor_set_lds_limit(sizeof(double) * (size_t)std::max(D64_LDS_DOUBLES, std::max(DM_LDS_DOUBLES, DMI_LDS_DOUBLES)));
     // ---- device pointers ----
     char *ws = h->ws;
     SysDesc &d = h->hsys;
@@ -1333,6 +1337,8 @@ irk_status irk_batch_create(int capacity, long long max_elements, void *workspac
     }
     for (int q = capacity - 1; q >= 0; --q) b->free_slots.push_back(q);
     hipEventCreate(&b->ev_end);
+    hipEventCreate(&b->ev_f0);
+    hipEventCreate(&b->ev_f1);
     *out = b;
     return IRK_OK;
 }
@@ -1490,6 +1496,127 @@ irk_status irk_batch_retire(irk_batch *b, long long *tags, irk_status *status, i
     return IRK_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// One group of handles for irk_factor_batched: the batch's table holds their
+// descriptors; the items are one per handle (flags), then, level by level
+// and for each launch class (coupled, shared J, factor class of m), the
+// level's factor tasks of every handle of that class.  Each handle's phase-0
+// tasks come in whole groups of eight, so every task keeps its XCD.
+irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_status *status)
+{
+    const int n = (int)hs.size();
+    for (irk_handle *h : hs)
+        if (h->stream != b->stream) {
+            HIPCHK(hipEventRecord(h->ev_ready, h->stream));
+            HIPCHK(hipStreamWaitEvent(b->stream, h->ev_ready, 0));
+        }
+    for (int q = 0; q < n; ++q) b->htab[q] = hs[q]->hsys;
+    struct FL { int off, n, phase; bool coupled, sharedJ; int m; size_t shm; };
+    std::vector<Item> items;
+    std::vector<FL> launches;
+    for (int q = 0; q < n; ++q) items.push_back(Item{q, 0, 1, 0});
+    size_t levels = 0;
+    for (irk_handle *h : hs) levels = std::max(levels, h->fa.size());
+    std::vector<char> taken(n);
+    for (size_t l = 0; l < levels; ++l)
+        for (int phase = 0; phase < 2; ++phase) {
+            std::fill(taken.begin(), taken.end(), 0);
+            for (int q = 0; q < n; ++q) {
+                const irk_handle *h = hs[q];
+                if (taken[q] || l >= h->fa.size()) continue;
+                FL F{(int)items.size(), 0, phase, h->coupled, h->sharedJ, h->m, h->shm_fac};
+                for (int r = q; r < n; ++r) {
+                    const irk_handle *g = hs[r];
+                    if (taken[r] || l >= g->fa.size() || g->coupled != h->coupled ||
+                        g->sharedJ != h->sharedJ || factor_class(g->m) != factor_class(h->m))
+                        continue;
+                    taken[r] = 1;
+                    const Launch &L = phase == 0 ? g->fa[l] : g->fb[l];
+                    const size_t base = (size_t)L.off - g->W.items.size();
+                    for (int t = 0; t < L.n; ++t) {
+                        Item it = g->fitems[base + t];
+                        it.sys = r;
+                        items.push_back(it);
+                    }
+                    F.n += L.n;
+                    F.shm = std::max(F.shm, g->shm_fac);
+                }
+                if (F.n) launches.push_back(F);
+            }
+        }
+    if (items.size() > b->max_items) return IRK_ERR_NOMEM;
+    HIPCHK(hipMemcpyAsync(b->dtab, b->htab.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->ditems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice,
+                          b->stream));
+    launch_reset_factor_flags(b->dtab, b->ditems, n, b->stream);
+    HIPCHK(hipEventRecord(b->ev_f0, b->stream));
+    for (const FL &F : launches)
+        launch_factor(F.phase, b->dtab, b->ditems + F.off, F.n, F.coupled, F.sharedJ, F.m, F.shm, b->stream);
+    for (irk_handle *h : hs)
+        if (h->mixed && h->opt.pc != IRK_PC_NONE) launch_quantize(h->dsys, h->hsys, h->ftype, b->stream);
+    HIPCHK(hipEventRecord(b->ev_f1, b->stream));
+    HIPCHK(hipGetLastError());
+    launch_gather_state(b->dtab, b->ditems, n, b->dgather, b->stream);
+    HIPCHK(hipMemcpyAsync(b->hgather, b->dgather, sizeof(DevState) * n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    float ms = 0.0f;
+    hipEventElapsedTime(&ms, b->ev_f0, b->ev_f1);
+    irk_status worst = IRK_OK;
+    for (int q = 0; q < n; ++q) {
+        irk_handle *h = hs[q];
+        *h->hst = b->hgather[q];
+        h->ms_factor = ms;             // the whole group's time
+        irk_status st = IRK_OK;
+        if (h->opt.pc != IRK_PC_NONE && h->hst->singular) {
+            h->bad_element = h->hst->singular - 1;
+            h->factored = false;
+            st = worst = IRK_ERR_SINGULAR;
+        } else {
+            h->bad_element = -1;
+            h->factored = true;
+        }
+        if (status) status[q] = st;
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+irk_status irk_factor_batched(irk_batch *b, irk_handle *const *h, int count, irk_status *status)
+{
+    if (!b || count < 0 || (count > 0 && !h)) return IRK_ERR_ARG;
+    if (!b->members.empty()) return IRK_ERR_STATE;
+    for (int q = 0; q < count; ++q) {
+        if (!h[q]) return IRK_ERR_ARG;
+        for (int r = 0; r < q; ++r)
+            if (h[r] == h[q]) return IRK_ERR_ARG;
+    }
+    irk_status worst = IRK_OK;
+    for (int q0 = 0; q0 < count;) {
+        std::vector<irk_handle *> grp;
+        size_t nit = 0;
+        int q1 = q0;
+        while (q1 < count && (int)grp.size() < b->capacity) {
+            const size_t need = h[q1]->fitems.size() + 1;
+            if (need > b->max_items) return IRK_ERR_NOMEM;
+            if (nit + need > b->max_items) break;
+            grp.push_back(h[q1]);
+            nit += need;
+            ++q1;
+        }
+        const irk_status st = factor_group(b, grp, status ? status + q0 : nullptr);
+        if (st != IRK_OK && st != IRK_ERR_SINGULAR) return st;
+        if (st != IRK_OK) worst = st;
+        q0 = q1;
+    }
+    return worst;
+}
+
 irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
                              double *const *x, int count, irk_solve_info *info)
 {
@@ -1519,6 +1646,8 @@ irk_status irk_batch_destroy(irk_batch *b)
     for (auto &m : b->members) hipEventDestroy(m.t0);
     if (b->hgather) hipHostFree(b->hgather);
     if (b->ev_end) hipEventDestroy(b->ev_end);
+    if (b->ev_f0) hipEventDestroy(b->ev_f0);
+    if (b->ev_f1) hipEventDestroy(b->ev_f1);
     delete b;
     return IRK_OK;
 }

@@ -157,9 +157,11 @@ void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nre
 // P_{k,i} (and invert it when !coupled; set up cross blocks of column k when
 // coupled).  phase 1 (coupled): tasks = elements, sequential stage rounds.
 // The kernels are chosen by the block order m (all systems of one launch
-// share it): four-wave workgroups for m <= 64, eight-wave ones above.
+// share its class, factor_class(m)): four-wave workgroups for m <= 64,
+// eight-wave ones above.
 void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems,
                    bool coupled, bool sharedJ, int m, size_t shmem, hipStream_t st);
+int factor_class(int m);
 
 // Quantize nblk column-major blocks (leading dimensions ld in, ldq out).
 void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int m, int ld,
@@ -194,6 +196,8 @@ void launch_fill_zero_slot(const SysDesc *dsys, const Item *vec, int nvec, int s
 void launch_gather_state(const SysDesc *dsys, const Item *fin, int nfin, DevState *out, hipStream_t st);
 // per-solve counters and flags to zero
 void launch_reset_state(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st);
+// the factorization's flags (singular pivot, non-finite value) to zero
+void launch_reset_factor_flags(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st);
 // export FP64 factors to the caller's row-major stage-major layout
 void launch_export(const SysDesc &hsys, double *pinv, double *cross, hipStream_t st);
 void factor_set_lds_limit(size_t bytes);

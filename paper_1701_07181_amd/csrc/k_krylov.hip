@@ -367,6 +367,16 @@ __global__ void k_reset_state(const SysDesc *__restrict__ sysv, const Item *__re
     st->j = -1;
 }
 
+// clear the factorization flags of every system (items: one per system)
+__global__ void k_reset_factor_flags(const SysDesc *__restrict__ sysv, const Item *__restrict__ items, int n)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    DevState *st = sysv[items[q].sys].st;
+    st->singular = 0;
+    st->nonfinite = 0;
+}
+
 // ---------------------------------------------------------------------------
 template <int PASS>
 static void cgs_dispatch(const SysDesc *dsys, const Item *vec, int nvec, const Item *fin, int nfin,
@@ -456,6 +466,11 @@ void launch_gather_state(const SysDesc *dsys, const Item *fin, int nfin, DevStat
 void launch_reset_state(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st)
 {
     hipLaunchKernelGGL(k_reset_state, dim3((nfin + 63) / 64), dim3(64), 0, st, dsys, fin, nfin);
+}
+
+void launch_reset_factor_flags(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset_factor_flags, dim3((nfin + 63) / 64), dim3(64), 0, st, dsys, fin, nfin);
 }
 
 }  // namespace irk

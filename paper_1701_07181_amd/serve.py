@@ -6,7 +6,9 @@ device memory) and a right-hand side; some re-use an operator whose
 factorization is still resident.  Two host threads share the device:
 
   * the preparation thread sets up and factors new operators on a side
-    stream; re-used operators need no preparation.  Admission is by device
+    stream, all operators that arrived since its last round together (one
+    batched factorization: each level of every operator in the same
+    launches); re-used operators need no preparation.  Admission is by device
     memory: every operator's workspace is a range of one pool allocated when
     the server starts (its memory budget), so serving itself never calls the
     device allocator.  An operator waits until a range of its size is free,
@@ -31,7 +33,11 @@ from typing import Dict, List, Optional
 import numpy as np
 import torch
 
-from . import Batch, Options, Solver, OK
+from . import Batch, Options, Solver, OK, factor_batched
+
+
+class _NoRoom(Exception):
+    """No pool range fits now and the caller asked not to wait."""
 
 
 class WorkspacePool:
@@ -104,12 +110,15 @@ class Result:
 
 class Server:
     def __init__(self, options: Options, capacity: int = 64, max_elements: int = 1 << 20,
-                 budget_bytes: int = 96 << 30, device: Optional[torch.device] = None):
+                 budget_bytes: int = 96 << 30, device: Optional[torch.device] = None,
+                 prep_group: int = 32):
         self.options = options
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.Stream(self.device)        # batch iteration
         self.side = torch.cuda.Stream(self.device)          # setup + factorization
         self.batch = Batch(capacity, max_elements, device=self.device, stream=self.stream)
+        self.prep_batch = Batch(prep_group, max_elements, device=self.device, stream=self.side)
+        self.prep_group = prep_group
         self.capacity = capacity
         self.budget = budget_bytes
         self.pool = WorkspacePool(budget_bytes, self.device)
@@ -119,6 +128,7 @@ class Server:
         self.queued: Dict[int, int] = {}                    # op_id -> requests waiting in `ready`
         self.range_of: Dict[int, tuple] = {}                # op_id -> (offset, bytes) in the pool
         self._pending: Optional[tuple] = None               # range handed to the Solver being set up
+        self._may_wait = True                               # _alloc may wait for memory
         self.prep_q: "queue.Queue" = queue.Queue()
         self.ready: collections.deque = collections.deque()
         self.active: Dict[int, tuple] = {}                  # rid -> (request, reused)
@@ -135,8 +145,8 @@ class Server:
         """A pool range of nbytes for a new operator's workspace (called by
         Solver during set-up, on the preparation thread): evicts idle
         resident operators (neither in the batch nor waiting to join it),
-        least recently used first, until a range fits; waits while none is
-        idle."""
+        least recently used first, until a range fits; while none is idle it
+        waits, or raises _NoRoom when the caller may not wait."""
         if WorkspacePool.round(nbytes) > self.budget:
             raise MemoryError(f"operator workspace of {nbytes} bytes exceeds the pool ({self.budget})")
         while True:
@@ -153,6 +163,8 @@ class Server:
                     self.resident.pop(victim).close()
                     self.pool.give(*self.range_of.pop(victim))
                     self.evictions += 1
+            if not self._may_wait:
+                raise _NoRoom()
             self.stalls += 1
             time.sleep(0.0005)
 
@@ -161,39 +173,80 @@ class Server:
         torch.cuda.set_device(self.device)
         try:
             while True:
-                req = self.prep_q.get()
-                if req is None:
+                first = self.prep_q.get()
+                if first is None:
                     return
-                with self.lock:
-                    reused = req.op_id in self.resident
-                    if reused:
-                        self.queued[req.op_id] = self.queued.get(req.op_id, 0) + 1
-                if reused:
-                    self.ready.append((req, True))
-                    continue
-                self._pending = None
-                solver = None
-                try:
-                    with torch.cuda.stream(self.side):
-                        solver = Solver(req.system, self.options, device=self.device, stream=self.side,
-                                        workspace_alloc=self._alloc)
-                        solver.factor()
-                except BaseException:
-                    if solver is not None:
-                        solver.close()
-                    if self._pending is not None:
-                        self.side.synchronize()
-                        with self.lock:
-                            self.pool.give(*self._pending)
-                    raise
-                self.side.synchronize()         # factors complete before the batch stream reads them
-                with self.lock:
-                    self.resident[req.op_id] = solver
-                    self.range_of[req.op_id] = self._pending
-                    self.queued[req.op_id] = self.queued.get(req.op_id, 0) + 1
-                self.ready.append((req, False))
+                group = [first]
+                while len(group) < self.prep_group:
+                    try:
+                        req = self.prep_q.get_nowait()
+                    except queue.Empty:
+                        break
+                    if req is None:
+                        self.prep_q.put(None)       # seen again after this round
+                        break
+                    group.append(req)
+                self._prepare(group)
         except BaseException as e:      # surfaced by the main loop
             self.error = e
+
+    def _prepare(self, group: List[Request]):
+        """Queue every request of the group; operators that are not resident
+        are set up and then factored together.  Only the first new operator
+        of a round waits for memory; when a later one does not fit, the
+        round is factored and the rest of the group starts a new round."""
+        pending = list(group)
+        while pending:
+            new: Dict[int, Solver] = {}
+            ranges: Dict[int, tuple] = {}
+            later = set()                   # ids of requests for an operator set up in this round
+            done = len(pending)
+            try:
+                for i, req in enumerate(pending):
+                    with self.lock:
+                        reused = req.op_id in self.resident
+                        if reused:
+                            self.queued[req.op_id] = self.queued.get(req.op_id, 0) + 1
+                    if reused:
+                        self.ready.append((req, True))
+                        continue
+                    if req.op_id in new:
+                        later.add(id(req))
+                        continue
+                    self._pending = None
+                    self._may_wait = not new
+                    try:
+                        with torch.cuda.stream(self.side):
+                            solver = Solver(req.system, self.options, device=self.device,
+                                            stream=self.side, workspace_alloc=self._alloc)
+                    except _NoRoom:
+                        done = i
+                        break
+                    new[req.op_id] = solver
+                    ranges[req.op_id] = self._pending
+                if new:
+                    factor_batched(self.prep_batch, list(new.values()))
+            except BaseException:
+                self.side.synchronize()
+                for solver in new.values():
+                    solver.close()
+                if self._pending is not None and self._pending not in ranges.values():
+                    ranges[None] = self._pending        # a set-up that failed after its range
+                with self.lock:
+                    for r in ranges.values():
+                        self.pool.give(*r)
+                raise
+            with self.lock:
+                for op, solver in new.items():
+                    self.resident[op] = solver
+                    self.range_of[op] = ranges[op]
+                for req in pending[:done]:
+                    if req.op_id in new:
+                        self.queued[req.op_id] = self.queued.get(req.op_id, 0) + 1
+            for req in pending[:done]:
+                if req.op_id in new:
+                    self.ready.append((req, id(req) in later))
+            pending = pending[done:]
 
     # -- main loop --
     def _admit_ready(self):
@@ -256,6 +309,7 @@ class Server:
         self.prep_q.put(None)
         self.worker.join(timeout=60)
         self.batch.close()
+        self.prep_batch.close()
         for s in self.resident.values():
             s.close()
         self.resident.clear()
