@@ -707,7 +707,14 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
     WorkSet &W = *C.W;
     const Item *vec = W.ditems + W.vec.off, *fin = W.ditems + W.fin.off;
     const bool fp64 = !W.mixed;
+    // The host reads the systems' state only at some steps (the device ends
+    // a system's cycle by itself: steps after its convergence do nothing).
+    // Several systems: every second step.  One system: the next read is
+    // placed one step before the step at which the estimate, shrinking at
+    // its last observed rate, would meet the tolerance.
     const int check_every = (W.nsys == 1) ? 1 : 2;
+    int next_check = check_every - 1;
+    double prev_est = -1.0;
     for (int j = 0; j < W.restart; ++j) {
         if (W.has_pc) {
             enqueue_pc(C, fp64, SL_V, j, -1, 1);
@@ -719,12 +726,21 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
         const int po = prof_begin(C.prof);
         launch_arnoldi(W.dsys, vec, W.vec.n, fin, W.fin.n, j, C.st);
         prof_end(C.prof, po, PK_ORTH);
-        if ((j + 1) % check_every == 0 || j + 1 == W.restart) {
+        if (j >= next_check || j + 1 == W.restart) {
             irk_status st = sync_states(C, dg, hg);
             if (st != IRK_OK) return st;
             bool all_done = true;
             for (int q = 0; q < W.nsys; ++q) all_done = all_done && hg[q].done;
             if (all_done) break;
+            next_check = j + check_every;
+            if (W.nsys == 1) {
+                const double est = hg[0].est, tol = hg[0].tol_abs;
+                if (prev_est > 0.0 && est > 0.0 && est < prev_est && tol > 0.0 && tol < est) {
+                    const double steps = std::log(tol / est) / std::log(est / prev_est);
+                    if (steps > 2.0 && steps < 1e6) next_check = j + (int)steps - 1;
+                }
+                prev_est = est;
+            }
         }
     }
     // x += Z y with the stored z_j = P^{-1} v_j (equal to P^{-1} V y, without
