@@ -243,7 +243,7 @@ def run_serve(args):
         arr = np.cumsum(rng.exponential(1.0 / qps, size=count))
         reqs = [Request(rid, op, sy, rhs, float(a)) for (rid, op, sy, rhs), a in zip(reqs_base, arr)]
         srv = Server(opts, capacity=64, max_elements=1 << 20, budget_bytes=120 << 30)
-        results = srv.run(reqs)
+        results = srv.run(reqs, progress=lambda d, n: _log(f"serve qps={qps}: {d}/{n} done"))
         st = latency_stats(results)
         st["stalls"], st["evictions"] = srv.stalls, srv.evictions
         srv.close()

@@ -286,14 +286,19 @@ class Server:
             self.results.append(Result(req.rid, req.op_id, x, info, req.arrival,
                                        time.perf_counter() - self.t0, reused))
 
-    def run(self, requests: List[Request]) -> List[Result]:
-        """Replay requests at their arrival times until all have completed."""
+    def run(self, requests: List[Request], progress=None, every: float = 10.0) -> List[Result]:
+        """Replay requests at their arrival times until all have completed;
+        progress(done, total), if given, is called every `every` seconds."""
         torch.cuda.synchronize(self.device)     # right-hand sides written on other streams
         self.t0 = time.perf_counter()
         pending = sorted(requests, key=lambda r: r.arrival)
         k = 0
+        next_report = every
         while k < len(pending) or len(self.results) < len(pending):
             now = time.perf_counter() - self.t0
+            if progress is not None and now >= next_report:
+                progress(len(self.results), len(pending))
+                next_report = now + every
             while k < len(pending) and pending[k].arrival <= now:
                 self.prep_q.put(pending[k])
                 k += 1
