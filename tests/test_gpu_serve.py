@@ -92,3 +92,24 @@ def test_served_results_with_evictions():
         assert info["iters"] == r.info["iters"], (r.rid, info["iters"], r.info["iters"])
         assert torch.equal(x, r.x), r.rid
         solo.close()
+
+
+def test_singular_operator_surfaces_and_frees_its_range():
+    """A request whose operator has a singular pivot ends the run with the
+    library's error; the pool gets the operator's range back."""
+    import paper_1701_07181_amd as irk
+    from paper_1701_07181_amd.serve import Request, Server
+
+    sy = dgsynth.config_system("cfg0")
+    col = int(np.flatnonzero(sy.col_idx == 0)[0])     # the (0, 0) block
+    sy.M[0] = 0.0
+    sy.J[:, col] = 0.0
+    sy.J = torch.from_numpy(sy.J).cuda()
+    sy.M = torch.from_numpy(sy.M).cuda()
+    rhs = torch.from_numpy(sy.rhs).cuda()
+    srv = Server(irk.Options(pc="uncoupled"), capacity=2, max_elements=1 << 12, budget_bytes=1 << 30)
+    with pytest.raises(irk.IrkError) as ei:
+        srv.run([Request(0, 0, sy, rhs, arrival=0.0)])
+    assert ei.value.status == irk.ERR_SINGULAR
+    assert srv.pool.free_bytes() == srv.pool.size and not srv.resident
+    srv.close()
