@@ -199,3 +199,49 @@ def test_singular_pivot_reported():
     B0 = oracle.build_stage(P, 0, 1.0)
     with pytest.raises(np.linalg.LinAlgError):
         B0.ilu0()
+
+
+# The uncoupled preconditioners on a tree.  Along a non-periodic path in
+# natural order the per-stage block ILU(0) is an exact LU, so the stage-
+# uncoupled preconditioner of Sec. 4.3.2 must be the exact block-diagonal
+# solve  z_k = ((A^{-1}_kk + alpha_k) M - dt J_k)^{-1} v_k.  For s = 2 the
+# Radau IIA inverse is A^{-1} = [[3/2, 1/2], [-9/2, 5/2]] (exact rationals),
+# so the column-sum shifts of Sec. 4.3.2 are alpha = (9/2, 1/2) and the
+# pivot coefficients (6, 3); they are written out here, not taken from the
+# oracle.  A dropped shift, a row-sum shift (1/2, 9/2), a wrong stage offset
+# or the wrong stage Jacobian fails one of these cases.
+S2_AINV_DIAG = (1.5, 2.5)
+
+
+@pytest.mark.parametrize("nJ", [1, 2])
+@pytest.mark.parametrize("pc,alpha", [("uncoupled_shifted", (4.5, 0.5)), ("uncoupled", (0.0, 0.0))])
+def test_uncoupled_apply_exact_on_tree(pc, alpha, nJ):
+    sys = _sys(s=2, m=3, nJ=nJ, seed=77, dt=0.4, mesh=dgsynth.path_mesh(7), permute=False)
+    A, _, _ = oracle.radau_iia(2)
+    P = oracle.Problem(sys)
+    v = np.random.default_rng(78).standard_normal(P.N)
+    z = oracle.pc_apply(P, A, pc, v)
+    n = sys.T * sys.m
+    for k in range(2):
+        Bk = (S2_AINV_DIAG[k] + alpha[k]) * dense.dense_M(sys) - sys.dt * dense.dense_J(sys, k)
+        zk = np.linalg.solve(Bk, v[k * n:(k + 1) * n])
+        np.testing.assert_allclose(z[k * n:(k + 1) * n], zk, rtol=0, atol=1e-12 * np.abs(zk).max())
+
+
+def test_uncoupled_shifted_apply_exact_on_tree_three_stages():
+    """s = 3 with one Jacobian per stage: the third stage's offset and J_3
+    are reached.  Shifts from the column sums of A^{-1}, which the tableau
+    pins fix (C(3), B(5), App. A closed forms)."""
+    s = 3
+    sys = _sys(s=s, m=4, nJ=s, seed=79, dt=0.25, mesh=dgsynth.path_mesh(6), permute=False)
+    A, _, _ = oracle.radau_iia(s)
+    Ainv = np.linalg.inv(A)
+    alpha = [sum(abs(Ainv[j, k]) for j in range(s) if j != k) for k in range(s)]
+    P = oracle.Problem(sys)
+    v = np.random.default_rng(80).standard_normal(P.N)
+    z = oracle.pc_apply(P, A, "uncoupled_shifted", v)
+    n = sys.T * sys.m
+    for k in range(s):
+        Bk = (Ainv[k, k] + alpha[k]) * dense.dense_M(sys) - sys.dt * dense.dense_J(sys, k)
+        zk = np.linalg.solve(Bk, v[k * n:(k + 1) * n])
+        np.testing.assert_allclose(z[k * n:(k + 1) * n], zk, rtol=0, atol=1e-12 * np.abs(zk).max())
