@@ -123,17 +123,27 @@ irk_status irk_default_options(irk_options *o);
  * these options.  Pure host computation. */
 irk_status irk_workspace_size(const irk_problem *p, const irk_options *o, size_t *bytes);
 
-/* Validate the problem, build the ILU level schedule on the host, and copy
- * J and M into the caller-owned device workspace (re-laid for the kernels).
- * The caller may free J and M afterwards.  The handle keeps host memory
- * only; it never allocates device memory.  `workspace` must stay valid and
- * untouched until irk_destroy.  Work goes to `stream`; returns after the
- * copies are done. */
+/* Set up the solver of the transformed Newton system B W = R (Sec. 4.1,
+ * Eq. modified-IRK, written as Eq. big-irk in Sec. 4.3; the tableau A of Sec. 3, the block Jacobians of Sec. 2.1 and
+ * the block-diagonal mass matrix M).  Validates the problem, computes A^{-1}
+ * and the shifts of Sec. 4.3.2, builds the level schedule of the block
+ * ILU(0) sweeps on the host, and copies J and M into the caller-owned device
+ * workspace (re-laid for the kernels).  The caller may free J and M
+ * afterwards.  The handle keeps host memory only; it never allocates device
+ * memory.  `workspace` must stay valid and untouched until irk_destroy.
+ * Work goes to `stream`; returns after the copies are done.  Errors:
+ * IRK_ERR_ARG (invalid shape, pattern not structurally symmetric or not
+ * triangle-free, malformed row_ptr), IRK_ERR_NOMEM (ws_bytes below
+ * irk_workspace_size), IRK_ERR_DEVICE. */
 irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace,
                      size_t ws_bytes, hipStream_t stream, irk_handle **out);
 
-/* Replace J, M and dt (same pattern, same nJ); the factors become stale
- * until the next irk_factor_ilu. */
+/* Replace J, M and dt (same pattern, same nJ): a new Newton iteration or
+ * time step re-evaluates the Jacobians (Sec. 4.1) and must refactor
+ * (Sec. 4.4: the preconditioner is computed once per linear solve).  J, M:
+ * DEVICE, same layout as in irk_problem; read before the call returns (the
+ * caller may free them afterwards).  The factors are stale until the next
+ * irk_factor_ilu.  IRK_ERR_ARG for null pointers or dt <= 0. */
 irk_status irk_update_values(irk_handle *h, const double *J, const double *M, double dt);
 
 /* Block ILU(0) factorization chosen by the options (Sec. 4.2.1 Alg. 2,
@@ -142,11 +152,18 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
  * Synchronizes; IRK_ERR_SINGULAR names the element in irk_last_bad_element. */
 irk_status irk_factor_ilu(irk_handle *h);
 
-/* Solve B x = rhs to the options' tolerance.  rhs, x: DEVICE [s][T][m];
- * x is the initial guess on entry (zero-fill it for x0 = 0) and the
- * solution on return (updated in place during the solve).  info (HOST, may
- * be NULL) is filled.  Synchronizes once per GMRES step to test
- * convergence and once per restart cycle. */
+/* Solve B x = rhs (Sec. 4.3, Eq. big-irk) by restarted GMRES, right-
+ * preconditioned with the factored block ILU(0) (Sec. 4.2-4.3), to
+ * ||rhs - B x||_2 <= rtol ||rhs||_2 with the FP64 operator (the true
+ * residual, recomputed at the end of every restart cycle).  rhs, x: DEVICE
+ * [s][T][m]; x is the initial guess on entry (zero-fill it for x0 = 0) and
+ * the solution on return (updated in place during the solve).  info (HOST,
+ * may be NULL) is filled.  The device decides when a cycle ends; the host
+ * reads the convergence state at the end of each cycle and at a few steps
+ * inside it, placed where the residual estimate is about to meet the
+ * tolerance, and waits for the stream before returning.  Returns
+ * IRK_ERR_STATE before irk_factor_ilu, IRK_ERR_NOCONV (x holds the last
+ * iterate), IRK_ERR_BREAKDOWN or IRK_ERR_NONFINITE with info filled. */
 irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solve_info *info);
 
 /* ---- batches: many independent systems in the same kernel launches ----
@@ -192,9 +209,13 @@ int irk_batch_pending(const irk_batch *b);
 
 irk_status irk_batch_destroy(irk_batch *b);
 
-/* Admit `count` handles (tags 0..count-1), advance until all have left,
- * retire them; info (HOST, may be NULL) receives one entry per handle.
- * The batch must be empty.  Returns the first non-OK member status. */
+/* Solve `count` independent systems B_q x_q = rhs_q (Sec. 4.3, Eq.
+ * big-irk, each with its own factored block ILU(0), Sec. 4.2-4.3) in the
+ * batch: admit the handles (tags 0..count-1), advance until all have left,
+ * retire them.  rhs[q], x[q]: DEVICE [s_q][T_q][m_q] (x[q] is the initial
+ * guess on entry and the solution on return).  info (HOST, may be NULL)
+ * receives one entry per handle.  The batch must be empty (IRK_ERR_STATE
+ * otherwise).  Returns the first non-OK member status. */
 irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
                              double *const *x, int count, irk_solve_info *info);
 
@@ -220,6 +241,28 @@ irk_status irk_apply_operator(irk_handle *h, const double *x, double *y);
  * block-triangular sweeps); DEVICE vectors; requires irk_factor_ilu. */
 irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z);
 
+/* y = (I (x) M - dt [a_kl J_k]_{kl}) x: the untransformed Newton operator of
+ * Sec. 4.1 (Eq. newton-system-2) for the same problem, the operator that the
+ * transformation W = (A (x) I) K replaces by B (kept as the baseline that
+ * Table 2 compares against).  form 0: block by block, one pass over J_k for
+ * each of the s^2 blocks (k, l) of the s x s block matrix (the
+ * s^2 (r+1) m^2 T multiply-adds Table 2 counts); form 1: fused, each
+ * element's Jacobian row streamed once and applied to the combinations
+ * sum_l a_kl x_l.  FP64; x, y DEVICE [s][T][m]; IRK_ERR_ARG for another
+ * form.  Timed as `untr` while profiling is on. */
+irk_status irk_apply_operator_untransformed(irk_handle *h, int form, const double *x, double *y);
+
+/* The inner-iteration kernels of a mixed-precision handle, the ones its
+ * GMRES cycles run: y = B x (Eq. big-irk) with the FP32 copies of J and M
+ * and FP32 arithmetic, x rounded to FP32 first; z = P^{-1} v (Sec. 4.2.1)
+ * with the stored FP32 / BF16 / FP16-scaled factors and FP32 sweeps.
+ * Vectors are FP64 on the DEVICE.  For an FP64 handle these are
+ * irk_apply_operator and irk_apply_preconditioner.  The preconditioner
+ * needs irk_factor_ilu (IRK_ERR_STATE otherwise); both overwrite the
+ * handle's work vectors and its per-solve state (not x, rhs or factors). */
+irk_status irk_apply_operator_inner(irk_handle *h, const double *x, double *y);
+irk_status irk_apply_preconditioner_inner(irk_handle *h, const double *v, double *z);
+
 /* Copy the FP64 inverse pivot blocks P_{k,i}^{-1} to pinv (DEVICE,
  * [s][T][m][m] row-major) and, for the coupled form, the cross-stage blocks
  * C_{kl,i} (k != l) to cross (DEVICE, [s][s][T][m][m] row-major, diagonal
@@ -240,6 +283,7 @@ typedef struct {
     int orth_count;    double orth_ms;     /* CGS2 + Givens steps               */
     int factor_count;  double factor_ms;   /* factorizations (incl. quantize)   */
     int dropped;
+    int untr_count;    double untr_ms;     /* untransformed operator products   */
 } irk_profile_stats;
 
 irk_status irk_profile_enable(irk_handle *h, int on);
@@ -288,6 +332,83 @@ irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *info);
  * else may be NULL).  Enqueued on `stream` and waited for. */
 irk_status irk_quantize_blocks(const double *src, long long nblk, int m, irk_prec prec,
                                void *dst, int *exps, hipStream_t stream);
+
+/* ---- one implicit Runge-Kutta time step by Newton's method ----
+ * The ODE is M u' = f(t, u) (Sec. 3) with the right-hand side
+ *     f(t, u) = J u + cos(omega t) g - eps u^3     (u^3 component-wise),
+ * J and M being the problem given to irk_setup / irk_update_values (with
+ * nJ = s the stage Jacobians given there must all equal J) and dt its time
+ * step.  The step solves the stage equations in the variables
+ * W = (A (x) I) K, Eq. modified-IRK of Sec. 4.1,
+ *     (A^{-1} (x) M) W = F(t0 + dt c, U0 + dt W),   c_k = sum_l a_kl,
+ * by Newton's method: every iteration solves the Eq. big-irk system with
+ * the stage Jacobians J_k = J - 3 eps diag(U_k^2), U_k = u0 + dt w_k
+ * (re-evaluated and refactored per iteration, Sec. 4.4; with eps = 0 the
+ * matrix is the handle's own and an existing factorization is reused), by
+ * the handle's preconditioned GMRES to its rtol.  It stops when the update
+ * has ||delta W||_inf <= newton_tol (the Newton test of Sec. 5.1.1) and
+ * returns u1 = u0 + dt (b^T A^{-1} (x) I) W, which is u0 + dt w_s for the
+ * stiffly accurate Radau IIA methods. */
+typedef struct {
+    const double *g;       /* DEVICE [T][m] forcing direction, or NULL (none)   */
+    double omega;          /* forcing frequency                                 */
+    double eps;            /* cubic term; 0 makes f linear                      */
+} irk_rhs;
+
+typedef struct {
+    int converged;         /* ||delta W||_inf <= newton_tol reached             */
+    int newton_iters;      /* Newton iterations (linear solves)                 */
+    int gmres_iters;       /* Arnoldi steps summed over them                    */
+    int equiv_mults;       /* n x n operator products of those steps: the
+                              paper's equivalent multiplications (Sec. 5.1.1),
+                              gmres_iters * s for a Radau step, gmres_iters
+                              for a DIRK step                                   */
+    int factorizations;    /* block ILU(0) factorizations done by the step      */
+    double update_norm;    /* ||delta W||_inf of the last iteration             */
+    float ms;              /* device time of the step                           */
+} irk_step_info;
+
+/* Device bytes of the `work` buffer irk_radau_step needs for this handle. */
+irk_status irk_step_workspace_size(const irk_handle *h, size_t *bytes);
+
+/* One step from (t0, u0) to u1 (DEVICE [T][m] each; u1 may not alias u0).
+ * b: HOST s weights, or NULL for a stiffly accurate tableau (b^T A^{-1} =
+ * e_s).  work: DEVICE, irk_step_workspace_size bytes, caller-owned, scratch.
+ * The handle's work vectors are overwritten; with eps != 0 its Jacobians are
+ * restored on return and its factors are left stale (the next solve must
+ * factor).  FP64 handles only (IRK_ERR_ARG for mixed precision, and for
+ * eps != 0 unless nJ = s).  Returns IRK_ERR_NOCONV when max_newton
+ * iterations do not meet newton_tol (u1 is then not written), or the first
+ * error of a factorization or linear solve.  Synchronizes. */
+irk_status irk_radau_step(irk_handle *h, const irk_rhs *f, const double *b, double t0,
+                          const double *u0, double *u1, double newton_tol, int max_newton,
+                          void *work, size_t work_bytes, irk_step_info *info);
+
+/* Tableaux of the diagonally implicit comparison methods (App. A):
+ * IRK_DIRK33 (3 stages, order 3) and IRK_ESDIRK65 (6 stages, order 5, first
+ * stage explicit).  A: HOST, room for 8 x 8 doubles, filled row-major
+ * stages x stages; b, c: HOST, room for 8 (b = last row of A, c = row
+ * sums).  IRK_ERR_ARG for another `which`. */
+enum { IRK_DIRK33 = 0, IRK_ESDIRK65 = 1 };
+irk_status irk_dirk_tableau(int which, int *stages, double *A, double *b, double *c);
+
+/* The diagonally implicit comparison methods (Sec. 3; DIRK33, ESDIRK65 of
+ * App. A): `stages` (1..8) stages of a lower-triangular tableau A (HOST,
+ * row-major stages x stages) whose implicit diagonal entries all equal the
+ * handle's own one-stage tableau entry a (irk_setup with s = 1, A = [[a]],
+ * so the handle's matrix is (1/a) M - dt J, Eq. big-irk at s = 1); only a
+ * first stage with a zero row may be explicit, and the method must be
+ * stiffly accurate (b = last row of A, c = row sums).  Stage i solves
+ *     M (U_i - u0) = dt sum_{j<i} a_ij F_j + dt a_ii f(t_i, U_i),
+ * F_j = f(t_j, U_j), by Newton in W = (U_i - u0)/dt with the handle's block
+ * ILU(0) and GMRES, one n x n system per stage in sequence; u1 = U_s.  f,
+ * newton_tol, max_newton, info and errors as for irk_radau_step
+ * (IRK_ERR_ARG for another tableau shape or a handle with s != 1).  work:
+ * DEVICE scratch of irk_dirk_workspace_size(h, stages) bytes. */
+irk_status irk_dirk_workspace_size(const irk_handle *h, int stages, size_t *bytes);
+irk_status irk_dirk_step(irk_handle *h, const irk_rhs *f, int stages, const double *A, double t0,
+                         const double *u0, double *u1, double newton_tol, int max_newton,
+                         void *work, size_t work_bytes, irk_step_info *info);
 
 /* Element of the last singular pivot, or -1. */
 int irk_last_bad_element(const irk_handle *h);

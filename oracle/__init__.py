@@ -19,6 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 PC_COUPLED, PC_SHIFTED, PC_UNSHIFTED, PC_NONE = 0, 1, 2, 3
 PC_NAMES = {"coupled": PC_COUPLED, "uncoupled_shifted": PC_SHIFTED,
@@ -26,21 +27,42 @@ PC_NAMES = {"coupled": PC_COUPLED, "uncoupled_shifted": PC_SHIFTED,
 
 
 def build(openmp: bool = False) -> str:
-    """Compile oracle.c into liboracle.so (plain -O2, single-threaded)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", LIB, SRC, "-lm"]
+    """Compile oracle.c: liboracle.so (plain -O2, single-threaded: the
+    library every test uses) or, with openmp, liboracle_omp.so (the same
+    source with its OpenMP loops enabled, for the all-cores CPU baseline
+    only; its reductions sum in a thread-dependent order)."""
+    out = LIB_OMP if openmp else LIB
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + (["-fopenmp"] if openmp else []) + \
+          ["-o", out, SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    return LIB
+    return out
 
 
 _lib = None
+_omp = False
+
+
+def use_openmp(on: bool = True):
+    """Select the OpenMP build for the calls that follow (bench only).  Must
+    be called before the first oracle call of the process."""
+    global _omp
+    if _lib is not None and on != _omp:
+        raise RuntimeError("the oracle library is already loaded")
+    _omp = on
+    # idle threads sleep between the many short parallel loops instead of
+    # spinning on the cores the serial parts run on (read by the OpenMP
+    # runtime when the library loads)
+    if on:
+        os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = C.CDLL(LIB)
+        path = LIB_OMP if _omp else LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+            build(openmp=_omp)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         L.orc_radau_iia.argtypes = [C.c_int, dp, dp, dp]

@@ -251,9 +251,12 @@ void orc_matvec_transformed(const orc_problem *p, const double *Ainv,
 {
     int s = p->s, T = p->T, m = p->m;
     size_t n = (size_t)T * m;
-    double *mx = malloc(sizeof(double) * m);
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(static)
+#endif
     for (int k = 0; k < s; ++k)
         for (int i = 0; i < T; ++i) {
+            double *mx = malloc(sizeof(double) * m);
             double *yk = y + k * n + (size_t)i * m;
             for (int r = 0; r < m; ++r) yk[r] = 0.0;
             const double *Mi = p->M + (size_t)i * m * m;
@@ -266,8 +269,8 @@ void orc_matvec_transformed(const orc_problem *p, const double *Ainv,
                 int j = p->col_idx[q];
                 mv_add(m, -p->dt, jblk(p, k, q), x + k * n + (size_t)j * m, yk);
             }
+            free(mx);
         }
-    free(mx);
 }
 
 /* Untransformed Newton operator (Sec. 4.1, Eq. newton-system-2):
@@ -396,7 +399,6 @@ int orc_ilu0(int nb, int m, const int32_t *ptr, const int32_t *col, double *val,
 {
     size_t bs = (size_t)m * m;
     double *inv = malloc(sizeof(double) * bs);
-    double *tmp = malloc(sizeof(double) * bs);
     int rc = 0;
     for (int pv = 0; pv < nb && rc == 0; ++pv) {
         long dpp = find_block(ptr, col, pv, pv);
@@ -405,14 +407,19 @@ int orc_ilu0(int nb, int m, const int32_t *ptr, const int32_t *col, double *val,
         if (orc_lu(m, dlu + (size_t)pv * bs, dpiv + (size_t)pv * m) != 0) { rc = 1 + pv; break; }
         if (orc_inverse(m, val + dpp * bs, inv) != 0) { rc = 1 + pv; break; }
         /* column pv below the pivot: rows q in row pv's pattern with q > pv
-         * (pattern symmetric) */
+         * (pattern symmetric); each row q only touches its own blocks */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic)
+#endif
         for (int a = ptr[pv]; a < ptr[pv + 1]; ++a) {
             int q = col[a];
             if (q <= pv) continue;
             long qp = find_block(ptr, col, q, pv);
             if (qp < 0) continue;
+            double *tmp = malloc(sizeof(double) * bs);
             mm(m, val + qp * bs, inv, tmp);
             memcpy(val + qp * bs, tmp, sizeof(double) * bs);
+            free(tmp);
             for (int b2 = ptr[pv]; b2 < ptr[pv + 1]; ++b2) {
                 int t = col[b2];
                 if (t <= pv) continue;
@@ -422,7 +429,7 @@ int orc_ilu0(int nb, int m, const int32_t *ptr, const int32_t *col, double *val,
             }
         }
     }
-    free(inv); free(tmp);
+    free(inv);
     return rc;
 }
 
@@ -565,6 +572,9 @@ static void op_pc(void *ctx, const double *v, double *z)
                        pc->dlu[0], pc->dpiv[0], v, z);
         return;
     }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int k = 0; k < pc->s; ++k)
         orc_ilu0_apply(pc->nb[k], pc->m, pc->ptr[k], pc->col[k], pc->val[k],
                        pc->dlu[k], pc->dpiv[k], v + k * n, z + k * n);
@@ -601,6 +611,10 @@ static int pc_setup(orc_pc *pc, const orc_problem *p, const double *Ainv, int ki
     }
     pc->nfac = p->s;
     long nnz = p->row_ptr[p->T];
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
     for (int k = 0; k < p->s; ++k) {
         double dcoef = Ainv[k * p->s + k] + ((kind == ORC_PC_SHIFTED) ? alpha[k] : 0.0);
         pc->nb[k] = p->T;
@@ -611,9 +625,14 @@ static int pc_setup(orc_pc *pc, const orc_problem *p, const double *Ainv, int ki
         pc->dpiv[k] = malloc(sizeof(int) * (size_t)p->T * p->m);
         orc_build_stage(p, k, dcoef, pc->ptr[k], pc->col[k], pc->val[k]);
         int rc = orc_ilu0(p->T, p->m, pc->ptr[k], pc->col[k], pc->val[k], pc->dlu[k], pc->dpiv[k]);
-        if (rc) return 1 + k * p->T + (rc - 1);
+        if (rc) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+            if (!bad || 1 + k * p->T + (rc - 1) < bad) bad = 1 + k * p->T + (rc - 1);
+        }
     }
-    return 0;
+    return bad;
 }
 
 typedef void (*orc_op)(void *ctx, const double *in, double *out);
@@ -626,6 +645,9 @@ typedef struct {
 static double dot(size_t n, const double *a, const double *b)
 {
     double t = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for reduction(+:t) schedule(static)
+#endif
     for (size_t e = 0; e < n; ++e) t += a[e] * b[e];
     return t;
 }

@@ -62,7 +62,17 @@ class _Prof(C.Structure):
                 ("pc_count", C.c_int), ("pc_ms", C.c_double),
                 ("orth_count", C.c_int), ("orth_ms", C.c_double),
                 ("factor_count", C.c_int), ("factor_ms", C.c_double),
-                ("dropped", C.c_int)]
+                ("dropped", C.c_int), ("untr_count", C.c_int), ("untr_ms", C.c_double)]
+
+
+class _Rhs(C.Structure):
+    _fields_ = [("g", C.c_void_p), ("omega", C.c_double), ("eps", C.c_double)]
+
+
+class _StepInfo(C.Structure):
+    _fields_ = [("converged", C.c_int), ("newton_iters", C.c_int), ("gmres_iters", C.c_int),
+                ("equiv_mults", C.c_int), ("factorizations", C.c_int), ("update_norm", C.c_double),
+                ("ms", C.c_float)]
 
 
 class _Tune(C.Structure):
@@ -89,6 +99,9 @@ _L.irk_batch_pending.argtypes = [_vp]
 _L.irk_batch_destroy.argtypes = [_vp]
 _L.irk_apply_operator.argtypes = [_vp, _vp, _vp]
 _L.irk_apply_preconditioner.argtypes = [_vp, _vp, _vp]
+_L.irk_apply_operator_inner.argtypes = [_vp, _vp, _vp]
+_L.irk_apply_operator_untransformed.argtypes = [_vp, C.c_int, _vp, _vp]
+_L.irk_apply_preconditioner_inner.argtypes = [_vp, _vp, _vp]
 _L.irk_export_factors.argtypes = [_vp, _vp, _vp]
 _L.irk_last_bad_element.argtypes = [_vp]
 _L.irk_destroy.argtypes = [_vp]
@@ -98,6 +111,13 @@ _L.irk_quantize_blocks.argtypes = [_vp, C.c_longlong, C.c_int, C.c_int, _vp, _vp
 _L.irk_profile_read.argtypes = [_vp, C.POINTER(_Prof)]
 _L.irk_autotune.argtypes = [_vp, C.c_int, C.POINTER(_Tune)]
 _L.irk_factor_batched.argtypes = [_vp, C.POINTER(_vp), C.c_int, C.POINTER(C.c_int)]
+_L.irk_step_workspace_size.argtypes = [_vp, C.POINTER(C.c_size_t)]
+_L.irk_radau_step.argtypes = [_vp, C.POINTER(_Rhs), _vp, C.c_double, _vp, _vp, C.c_double, C.c_int,
+                              _vp, C.c_size_t, C.POINTER(_StepInfo)]
+_L.irk_dirk_tableau.argtypes = [C.c_int, C.POINTER(C.c_int), _vp, _vp, _vp]
+_L.irk_dirk_workspace_size.argtypes = [_vp, C.c_int, C.POINTER(C.c_size_t)]
+_L.irk_dirk_step.argtypes = [_vp, C.POINTER(_Rhs), C.c_int, _vp, C.c_double, _vp, _vp, C.c_double,
+                             C.c_int, _vp, C.c_size_t, C.POINTER(_StepInfo)]
 
 EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_update_values",
             "irk_factor_ilu", "irk_gmres_solve", "irk_solve_batched", "irk_apply_operator",
@@ -105,7 +125,10 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_destroy", "irk_status_str", "irk_radau_iia", "irk_profile_enable",
             "irk_profile_read", "irk_quantize_blocks", "irk_batch_workspace_size",
             "irk_batch_create", "irk_batch_admit", "irk_batch_advance", "irk_batch_retire",
-            "irk_batch_pending", "irk_batch_destroy", "irk_autotune", "irk_factor_batched"]
+            "irk_batch_pending", "irk_batch_destroy", "irk_autotune", "irk_factor_batched",
+            "irk_apply_operator_inner", "irk_apply_preconditioner_inner",
+            "irk_apply_operator_untransformed", "irk_step_workspace_size", "irk_radau_step",
+            "irk_dirk_workspace_size", "irk_dirk_step", "irk_dirk_tableau"]
 
 
 def _check(st: int, where: str):
@@ -122,6 +145,17 @@ def radau_iia(s: int):
     A = np.zeros((s, s)); b = np.zeros(s); c = np.zeros(s)
     _check(_L.irk_radau_iia(s, A.ctypes.data, b.ctypes.data, c.ctypes.data), "irk_radau_iia")
     return A, b, c
+
+
+def dirk_tableau(name: str):
+    """(A, b, c) of DIRK33 or ESDIRK65 (App. A), from the library."""
+    which = {"DIRK33": 0, "ESDIRK65": 1}[name]
+    A = np.zeros(64); b = np.zeros(8); c = np.zeros(8)
+    st = C.c_int()
+    _check(_L.irk_dirk_tableau(which, C.byref(st), A.ctypes.data, b.ctypes.data, c.ctypes.data),
+           "irk_dirk_tableau")
+    s = st.value
+    return A[:s * s].reshape(s, s).copy(), b[:s].copy(), c[:s].copy()
 
 
 def quantize_blocks(src: torch.Tensor, prec: str):
@@ -303,6 +337,94 @@ class Solver:
             z = torch.empty_like(vv)
         _check(_L.irk_apply_preconditioner(self._h, vv.data_ptr(), z.data_ptr()),
                "irk_apply_preconditioner")
+        return z
+
+    def _step_vectors(self, u0, g):
+        n = self.T * self.m
+        with torch.cuda.stream(self.stream):
+            u = torch.as_tensor(u0, dtype=torch.float64).to(self.device).contiguous().view(-1)
+            gv = None if g is None else \
+                torch.as_tensor(g, dtype=torch.float64).to(self.device).contiguous().view(-1)
+            u1 = torch.empty(n, dtype=torch.float64, device=self.device)
+        if u.numel() != n or (gv is not None and gv.numel() != n):
+            raise ValueError(f"vectors of {n} entries expected")
+        return u, gv, u1
+
+    def _scratch(self, nbytes: int) -> torch.Tensor:
+        if getattr(self, "_step_ws", None) is None or self._step_ws.numel() < nbytes:
+            with torch.cuda.stream(self.stream):
+                self._step_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._step_ws
+
+    def step(self, u0, t0: float = 0.0, g=None, omega: float = 0.0, eps: float = 0.0, b=None,
+             newton_tol: float = 1e-10, max_newton: int = 20, raise_on_error: bool = True):
+        """One implicit Runge-Kutta step of M u' = J u + cos(omega t) g - eps u^3
+        from (t0, u0) with this solver's dt, by Newton's method on the
+        transformed stage equations (irk_radau_step).  Returns (u1, info)."""
+        u, gv, u1 = self._step_vectors(u0, g)
+        nb = C.c_size_t()
+        _check(_L.irk_step_workspace_size(self._h, C.byref(nb)), "irk_step_workspace_size")
+        ws = self._scratch(int(nb.value))
+        rhs = _Rhs(gv.data_ptr() if gv is not None else None, float(omega), float(eps))
+        bw = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        inf = _StepInfo()
+        st = _L.irk_radau_step(self._h, C.byref(rhs), bw.ctypes.data if bw is not None else None,
+                               float(t0), u.data_ptr(), u1.data_ptr(), float(newton_tol),
+                               int(max_newton), ws.data_ptr(), ws.numel(), C.byref(inf))
+        if raise_on_error and st != OK:
+            raise IrkError(st, "irk_radau_step")
+        return u1, dict(status=st, **{f: getattr(inf, f) for f, _ in _StepInfo._fields_})
+
+    def dirk_step(self, A, u0, t0: float = 0.0, g=None, omega: float = 0.0, eps: float = 0.0,
+                  newton_tol: float = 1e-10, max_newton: int = 20, raise_on_error: bool = True):
+        """One step of the stiffly accurate DIRK tableau A (irk_dirk_step);
+        this solver must be a one-stage system whose tableau entry is A's
+        implicit diagonal.  Returns (u1, info)."""
+        Ad = np.ascontiguousarray(A, dtype=np.float64)
+        stages = int(Ad.shape[0])
+        u, gv, u1 = self._step_vectors(u0, g)
+        nb = C.c_size_t()
+        _check(_L.irk_dirk_workspace_size(self._h, stages, C.byref(nb)), "irk_dirk_workspace_size")
+        ws = self._scratch(int(nb.value))
+        rhs = _Rhs(gv.data_ptr() if gv is not None else None, float(omega), float(eps))
+        inf = _StepInfo()
+        st = _L.irk_dirk_step(self._h, C.byref(rhs), stages, Ad.ctypes.data, float(t0), u.data_ptr(),
+                              u1.data_ptr(), float(newton_tol), int(max_newton), ws.data_ptr(),
+                              ws.numel(), C.byref(inf))
+        if raise_on_error and st != OK:
+            raise IrkError(st, "irk_dirk_step")
+        return u1, dict(status=st, **{f: getattr(inf, f) for f, _ in _StepInfo._fields_})
+
+    def apply_operator_untransformed(self, x, form: str = "fused") -> torch.Tensor:
+        """y = (I (x) M - dt [a_kl J_k]) x, the untransformed operator
+        (form "blocks": one pass over J_k per block of the s x s block
+        matrix; "fused": one pass per element row)."""
+        xv = self._vec(x)
+        with torch.cuda.stream(self.stream):
+            y = torch.empty_like(xv)
+        f = {"blocks": 0, "fused": 1}[form]
+        _check(_L.irk_apply_operator_untransformed(self._h, f, xv.data_ptr(), y.data_ptr()),
+               "irk_apply_operator_untransformed")
+        return y
+
+    def apply_operator_inner(self, x) -> torch.Tensor:
+        """y = B x with the inner-iteration operator (FP32 for a mixed-
+        precision solver, FP64 otherwise)."""
+        xv = self._vec(x)
+        with torch.cuda.stream(self.stream):
+            y = torch.empty_like(xv)
+        _check(_L.irk_apply_operator_inner(self._h, xv.data_ptr(), y.data_ptr()),
+               "irk_apply_operator_inner")
+        return y
+
+    def apply_preconditioner_inner(self, v) -> torch.Tensor:
+        """z = P^{-1} v with the inner-iteration sweeps (reduced-precision
+        factors and FP32 sweeps for a mixed-precision solver)."""
+        vv = self._vec(v)
+        with torch.cuda.stream(self.stream):
+            z = torch.empty_like(vv)
+        _check(_L.irk_apply_preconditioner_inner(self._h, vv.data_ptr(), z.data_ptr()),
+               "irk_apply_preconditioner_inner")
         return z
 
     def autotune(self, retime: bool = False) -> dict:

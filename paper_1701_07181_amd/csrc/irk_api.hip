@@ -110,12 +110,15 @@ irk_status analyze(const irk_problem *p, Schedule &sc)
 {
     const int T = p->T;
     const int32_t *rp = p->row_ptr, *ci = p->col_idx;
+    // the whole row pointer first: every later read of col_idx stays inside
+    // [0, nnzb) only if rp starts at 0, never decreases and ends at nnzb
     if (rp[0] != 0 || rp[T] != p->nnzb) return IRK_ERR_ARG;
+    for (int i = 0; i < T; ++i)
+        if (rp[i + 1] < rp[i] || rp[i + 1] > p->nnzb) return IRK_ERR_ARG;
     sc.diag.assign(T, -1);
     sc.tpos.assign(p->nnzb, -1);
     sc.maxrow = 0;
     for (int i = 0; i < T; ++i) {
-        if (rp[i + 1] < rp[i]) return IRK_ERR_ARG;
         sc.maxrow = std::max(sc.maxrow, rp[i + 1] - rp[i]);
         for (int q = rp[i]; q < rp[i + 1]; ++q) {
             if (ci[q] < 0 || ci[q] >= T) return IRK_ERR_ARG;
@@ -380,6 +383,7 @@ struct irk_handle {
     int bad_element;
     float ms_factor;
     hipEvent_t ev0, ev1, ev_ready;
+    hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr;   // span of a time step
     SysDesc solve_desc;  // descriptor with the caller's rhs / x (staging for the copy)
     // profiling: event pool and recorded intervals (kind, event index)
     bool prof;
@@ -420,7 +424,7 @@ struct irk_batch {
 };
 
 namespace {
-enum ProfKind { PK_MV64 = 0, PK_MV32, PK_PC, PK_ORTH, PK_FACTOR, PK_N };
+enum ProfKind { PK_MV64 = 0, PK_MV32, PK_PC, PK_ORTH, PK_FACTOR, PK_UNTR, PK_N };
 
 // Start an interval; returns its pool index or -1.
 int prof_begin(irk_handle *h)
@@ -875,6 +879,47 @@ irk_status irk_radau_iia(int s, double *A, double *b, double *c)
     return IRK_OK;
 }
 
+irk_status irk_dirk_tableau(int which, int *stages, double *A, double *b, double *c)
+{
+    if (!stages || !A || !b || !c) return IRK_ERR_ARG;
+    if (which == IRK_DIRK33) {
+        // L-stable three-stage SDIRK of order 3: the diagonal is the root of
+        // 6 a^3 - 18 a^2 + 9 a - 1 in (1/3, 1/2), in the trigonometric form
+        const double th = std::atan(std::sqrt(2.0) / 4.0) / 3.0;
+        const double a = 1.0 + std::sqrt(6.0) / 2.0 * std::sin(th) - std::sqrt(2.0) / 2.0 * std::cos(th);
+        const double t2 = 0.5 * (1.0 + a);
+        const double b1 = -(6.0 * a * a - 16.0 * a + 1.0) / 4.0, b2 = (6.0 * a * a - 20.0 * a + 5.0) / 4.0;
+        const double T[9] = {a, 0.0, 0.0, t2 - a, a, 0.0, b1, b2, a};
+        *stages = 3;
+        std::memcpy(A, T, sizeof(T));
+        b[0] = b1; b[1] = b2; b[2] = a;
+        c[0] = a; c[1] = t2; c[2] = 1.0;
+        return IRK_OK;
+    }
+    if (which == IRK_ESDIRK65) {
+        // six stages, explicit first stage, common implicit diagonal
+        static const double T[36] = {
+            0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+            0.2780538411364465, 0.2780538411364465, 0.0, 0.0, 0.0, 0.0,
+            0.3137405401502951, 0.4363327154020044, 0.2780538411364465, 0.0, 0.0, 0.0,
+            0.2741986534107860, -0.0164268277321164, 0.0048197082596452, 0.2780538411364465, 0.0, 0.0,
+            -0.2441776975175844, -3.3203529439447852, 0.0477747285706825, 3.2974431145814931,
+            0.2780538411364465, 0.0,
+            -0.2786732780227907, 1.8929947094010862, -0.1280948204262490, -1.3574693381380240,
+            0.5931888860495311, 0.2780538411364465};
+        *stages = 6;
+        std::memcpy(A, T, sizeof(T));
+        for (int i = 0; i < 6; ++i) {
+            b[i] = T[30 + i];
+            double r = 0.0;
+            for (int j = 0; j < 6; ++j) r += T[6 * i + j];
+            c[i] = r;
+        }
+        return IRK_OK;
+    }
+    return IRK_ERR_ARG;
+}
+
 // Work items of a handle (matvec rows, reduction chunks, sweep records per
 // level, factor tasks) and the LDS sizes of its launches, from the launch
 // shapes in the handle (tpw64/32, sw64/32) and the host copy of the
@@ -1049,7 +1094,10 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     d.N = (long long)s * T * m;
     d.dt = p->dt;
     for (int k = 0; k < s; ++k) {
-        for (int l = 0; l < s; ++l) d.Ainv[k * SMAX + l] = Ainv[k * s + l];
+        for (int l = 0; l < s; ++l) {
+            d.Ainv[k * SMAX + l] = Ainv[k * s + l];
+            d.A[k * SMAX + l] = p->A[k * s + l];
+        }
         d.dcoef[k] = Ainv[k * s + k] + ((o->pc == IRK_PC_UNCOUPLED_SHIFTED) ? h->alpha[k] : 0.0);
     }
     int *ip = (int *)(ws + P.o_ints);
@@ -1101,6 +1149,8 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     hipEventCreate(&h->ev0);
     hipEventCreate(&h->ev1);
     hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming);
+    hipEventCreate(&h->ev_s0);
+    hipEventCreate(&h->ev_s1);
     std::vector<Item> all(W.items);
     all.insert(all.end(), h->fitems.begin(), h->fitems.end());
     bool ok = true;
@@ -1218,6 +1268,58 @@ irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z)
     return IRK_OK;
 }
 
+irk_status irk_apply_operator_untransformed(irk_handle *h, int form, const double *x, double *y)
+{
+    if (!h || !x || !y || (form != 0 && form != 1)) return IRK_ERR_ARG;
+    const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
+    HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], x, bytes, hipMemcpyDeviceToDevice, h->stream));
+    const int pi = prof_begin(h);
+    launch_untransformed(h->dsys, h->W.ditems + h->W.mv64.off, h->W.mv64.n, h->s, form == 1,
+                         SL_EXT0, SL_EXT1, h->W.shm_mv64, h->stream);
+    prof_end(h, pi, PK_UNTR);
+    HIPCHK(hipMemcpyAsync(y, h->hsys.vec[SL_EXT1], bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+irk_status irk_apply_operator_inner(irk_handle *h, const double *x, double *y)
+{
+    if (!h || !x || !y) return IRK_ERR_ARG;
+    if (!h->mixed) return irk_apply_operator(h, x, y);
+    const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
+    const Item *vec = h->W.ditems + h->W.vec.off;
+    HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], x, bytes, hipMemcpyDeviceToDevice, h->stream));
+    // the FP32 operator reads its input in the compute type from SL_YH
+    launch_copy_to_yh(h->dsys, vec, h->W.vec.n, false, SL_EXT0, 0, 0, h->stream);
+    Ctx C{&h->W, h->stream, h};
+    enqueue_matvec(C, false, SL_YH, SL_EXT1, -1, 0, 0);
+    HIPCHK(hipMemcpyAsync(y, h->hsys.vec[SL_EXT1], bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
+irk_status irk_apply_preconditioner_inner(irk_handle *h, const double *v, double *z)
+{
+    if (!h || !v || !z) return IRK_ERR_ARG;
+    if (!h->factored) return IRK_ERR_STATE;
+    if (!h->mixed || h->opt.pc == IRK_PC_NONE) return irk_apply_preconditioner(h, v, z);
+    const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
+    const Item *vec = h->W.ditems + h->W.vec.off;
+    HIPCHK(hipMemcpyAsync(h->hsys.vec[SL_EXT0], v, bytes, hipMemcpyDeviceToDevice, h->stream));
+    Ctx C{&h->W, h->stream, h};
+    enqueue_pc(C, false, SL_EXT0, 0, -1, 0);
+    // SL_ZB[0] = (double) SL_YH; the copy kernel runs only while the
+    // system's cycle flag is clear, so the per-solve state is reset first
+    launch_reset_state(h->dsys, h->W.ditems + h->W.fin.off, h->W.fin.n, h->stream);
+    launch_store_z(h->dsys, vec, h->W.vec.n, false, 0, h->stream);
+    HIPCHK(hipMemcpyAsync(z, h->hsys.vec[SL_ZB], bytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return IRK_OK;
+}
+
 irk_status irk_export_factors(irk_handle *h, double *pinv, double *cross)
 {
     if (!h) return IRK_ERR_ARG;
@@ -1254,6 +1356,264 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
     return S.status;
 }
 
+// ---------------------------------------------------------------------------
+// one time step by Newton's method (Sec. 4.1, Eq. modified-IRK)
+// ---------------------------------------------------------------------------
+namespace {
+struct StepPlan { size_t o_dbase, o_ju0, o_w, o_delta, o_part, o_res, o_f, o_hist, o_u, total; };
+
+// Scratch of one step: the linear part's diagonal blocks, J u0, the Newton
+// iterate W and update (s vectors for a Radau step, one for a DIRK stage),
+// the max-reduction partials; a DIRK step (dirk_stages > 0) adds the stage
+// right-hand sides F_j, the history term and the stage state.
+StepPlan step_plan(const irk_handle *h, int dirk_stages)
+{
+    StepPlan P{};
+    const size_t n = (size_t)h->T * h->m, N = (size_t)h->s * n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
+    P.o_dbase = take(sizeof(double) * (size_t)h->T * h->m * h->plan.ld);
+    P.o_ju0 = take(sizeof(double) * n);
+    P.o_w = take(sizeof(double) * N);
+    P.o_delta = take(sizeof(double) * N);
+    P.o_part = take(sizeof(double) * 1024);
+    P.o_res = take(sizeof(double));
+    P.o_f = P.o_hist = P.o_u = (size_t)-1;
+    if (dirk_stages > 0) {
+        P.o_f = take(sizeof(double) * n * (size_t)dirk_stages);
+        P.o_hist = take(sizeof(double) * n);
+        P.o_u = take(sizeof(double) * n);
+    }
+    P.total = off;
+    return P;
+}
+}  // namespace
+
+irk_status irk_step_workspace_size(const irk_handle *h, size_t *bytes)
+{
+    if (!h || !bytes) return IRK_ERR_ARG;
+    *bytes = step_plan(h, 0).total;
+    return IRK_OK;
+}
+
+namespace {
+// Pointers into a step's scratch (see step_plan).
+struct StepBufs { double *Dbase, *Ju0, *W, *delta, *part, *res, *F, *hist, *U; };
+
+StepBufs step_bufs(const StepPlan &P, void *work)
+{
+    char *wk = (char *)work;
+    auto at = [&](size_t o) { return o == (size_t)-1 ? nullptr : (double *)(wk + o); };
+    return StepBufs{at(P.o_dbase), at(P.o_ju0), at(P.o_w), at(P.o_delta), at(P.o_part),
+                    at(P.o_res), at(P.o_f), at(P.o_hist), at(P.o_u)};
+}
+
+bool rhs_ok(const irk_rhs *f)
+{
+    return f && std::isfinite(f->omega) && std::isfinite(f->eps);
+}
+
+// Newton's method on the handle's stage equations (s = h->s stages, stage
+// times entering through the forcing factors gam[k]): W (DEVICE, s n) holds
+// the initial guess and receives the iterate; hist (DEVICE n or null) is the
+// constant history term of a diagonally implicit stage.  Every iteration:
+// stage Jacobians from u0 + dt W (nonlinear f), refactor when stale, the
+// Newton residual b' - B_N W, GMRES on B_N delta = residual, W += delta,
+// ||delta||_inf read back.
+irk_status newton_solve(irk_handle *h, const irk_rhs *f, const double *gam, const double *u0,
+                        const StepBufs &B, const double *hist, double newton_tol, int max_newton,
+                        irk_step_info &inf, bool &converged)
+{
+    const int s = h->s;
+    const long long n = (long long)h->T * h->m, N = (long long)s * n;
+    const double dt = h->dt;
+    double *bp = (double *)h->hsys.vec[SL_EXT1];   // b', then the Newton residual
+    double *Wslot = (double *)h->hsys.vec[SL_EXT0];
+    const bool nonlin = f->eps != 0.0;
+    converged = false;
+    for (int it = 0; it < max_newton; ++it) {
+        if (nonlin) {
+            launch_stage_jac(h->dsys, h->hsys, B.Dbase, u0, B.W, dt, f->eps, h->stream);
+            h->factored = false;
+        }
+        if (!h->factored) {
+            const irk_status st = irk_factor_ilu(h);
+            if (st != IRK_OK) return st;
+            inf.factorizations++;
+        }
+        launch_stage_rhs(s, n, B.Ju0, f->g, u0, B.W, dt, f->eps, gam, hist, bp, h->stream);
+        HIPCHK(hipMemcpyAsync(Wslot, B.W, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+        {
+            Ctx C{&h->W, h->stream, h};
+            enqueue_matvec(C, true, SL_EXT0, SL_EXT1, SL_EXT1, 1, 0);
+        }
+        HIPCHK(hipMemsetAsync(B.delta, 0, sizeof(double) * N, h->stream));
+        irk_solve_info si{};
+        const irk_status st = irk_gmres_solve(h, bp, B.delta, &si);
+        inf.gmres_iters += si.iters;
+        if (st != IRK_OK) return st;
+        launch_newton_update(N, B.W, B.delta, B.part, B.res, h->stream);
+        HIPCHK(hipGetLastError());
+        double nrm = 0.0;
+        HIPCHK(hipMemcpyAsync(&nrm, B.res, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        inf.newton_iters++;
+        inf.update_norm = nrm;
+        if (!std::isfinite(nrm)) return IRK_ERR_NONFINITE;
+        if (nrm <= newton_tol) { converged = true; return IRK_OK; }
+    }
+    return IRK_OK;
+}
+}  // namespace
+
+irk_status irk_radau_step(irk_handle *h, const irk_rhs *f, const double *b, double t0,
+                          const double *u0, double *u1, double newton_tol, int max_newton,
+                          void *work, size_t work_bytes, irk_step_info *info)
+{
+    if (!h || !rhs_ok(f) || !u0 || !u1 || !work) return IRK_ERR_ARG;
+    if (!(newton_tol > 0.0) || max_newton < 1 || !std::isfinite(t0)) return IRK_ERR_ARG;
+    if (h->mixed) return IRK_ERR_ARG;                       // the FP64 solve only
+    if (f->eps != 0.0 && h->nJ != h->s) return IRK_ERR_ARG; // stage Jacobians differ
+    const StepPlan SP = step_plan(h, 0);
+    if (work_bytes < SP.total) return IRK_ERR_NOMEM;
+    const StepBufs B = step_bufs(SP, work);
+    const int s = h->s;
+    const long long n = (long long)h->T * h->m, N = (long long)s * n;
+    const double dt = h->dt;
+    // stage times c_k = sum_l a_kl, forcing factors, output weights d = b^T A^{-1}
+    double gam[SMAX], dco[SMAX];
+    for (int k = 0; k < s; ++k) {
+        double c = 0.0;
+        for (int l = 0; l < s; ++l) c += h->A[k * s + l];
+        gam[k] = std::cos(f->omega * (t0 + c * dt));
+        dco[k] = 0.0;
+    }
+    if (b) {
+        for (int k = 0; k < s; ++k)
+            for (int l = 0; l < s; ++l) dco[k] += b[l] * h->Ainv[l * s + k];
+    } else {
+        dco[s - 1] = 1.0;     // stiffly accurate: b^T A^{-1} = e_s
+    }
+    irk_step_info inf{};
+    hipEventRecord(h->ev_s0, h->stream);
+    // the linear part's diagonal blocks (restored at the end), J u0, W = 0
+    launch_save_diag(h->dsys, h->hsys, B.Dbase, h->stream);
+    launch_jac_u0(h->dsys, h->hsys, B.Dbase, u0, B.Ju0, h->stream);
+    HIPCHK(hipMemsetAsync(B.W, 0, sizeof(double) * N, h->stream));
+    HIPCHK(hipGetLastError());
+    bool conv = false;
+    irk_status st = newton_solve(h, f, gam, u0, B, nullptr, newton_tol, max_newton, inf, conv);
+    inf.converged = conv ? 1 : 0;
+    inf.equiv_mults = inf.gmres_iters * s;
+    if (st == IRK_OK && conv) launch_step_finish(s, n, u0, B.W, dt, dco, u1, h->stream);
+    if (f->eps != 0.0) {
+        // leave the handle's Jacobians as they were given; its factors are
+        // those of the last Newton matrix, so they are stale
+        launch_stage_jac(h->dsys, h->hsys, B.Dbase, u0, B.W, dt, 0.0, h->stream);
+        h->factored = false;
+    }
+    hipEventRecord(h->ev_s1, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    hipEventElapsedTime(&inf.ms, h->ev_s0, h->ev_s1);
+    if (info) *info = inf;
+    if (st != IRK_OK) return st;
+    return conv ? IRK_OK : IRK_ERR_NOCONV;
+}
+
+irk_status irk_dirk_workspace_size(const irk_handle *h, int stages, size_t *bytes)
+{
+    if (!h || !bytes || stages < 1 || stages > DIRK_STAGES_MAX) return IRK_ERR_ARG;
+    *bytes = step_plan(h, stages).total;
+    return IRK_OK;
+}
+
+irk_status irk_dirk_step(irk_handle *h, const irk_rhs *f, int stages, const double *A, double t0,
+                         const double *u0, double *u1, double newton_tol, int max_newton,
+                         void *work, size_t work_bytes, irk_step_info *info)
+{
+    if (!h || !rhs_ok(f) || !A || !u0 || !u1 || !work) return IRK_ERR_ARG;
+    if (stages < 1 || stages > DIRK_STAGES_MAX) return IRK_ERR_ARG;
+    if (!(newton_tol > 0.0) || max_newton < 1 || !std::isfinite(t0)) return IRK_ERR_ARG;
+    if (h->s != 1 || h->mixed) return IRK_ERR_ARG;
+    // a lower-triangular tableau whose implicit diagonal is the handle's a_11;
+    // only a first stage with a zero row may be explicit
+    const double diag = h->A[0];
+    for (int i = 0; i < stages; ++i) {
+        for (int j = 0; j < stages; ++j)
+            if (!std::isfinite(A[i * stages + j]) || (j > i && A[i * stages + j] != 0.0)) return IRK_ERR_ARG;
+        const double aii = A[i * stages + i];
+        if (aii == 0.0) {
+            if (i != 0) return IRK_ERR_ARG;
+            for (int j = 0; j < stages; ++j)
+                if (A[j] != 0.0) return IRK_ERR_ARG;
+        } else if (aii != diag) {
+            return IRK_ERR_ARG;
+        }
+    }
+    const StepPlan SP = step_plan(h, stages);
+    if (work_bytes < SP.total) return IRK_ERR_NOMEM;
+    const StepBufs B = step_bufs(SP, work);
+    const long long n = (long long)h->T * h->m;
+    const double dt = h->dt;
+    irk_step_info inf{};
+    hipEventRecord(h->ev_s0, h->stream);
+    launch_save_diag(h->dsys, h->hsys, B.Dbase, h->stream);
+    launch_jac_u0(h->dsys, h->hsys, B.Dbase, u0, B.Ju0, h->stream);
+    HIPCHK(hipGetLastError());
+    irk_status st = IRK_OK;
+    bool all_conv = true;
+    for (int i = 0; i < stages && st == IRK_OK && all_conv; ++i) {
+        double ci = 0.0;
+        for (int j = 0; j < stages; ++j) ci += A[i * stages + j];
+        const double gam = std::cos(f->omega * (t0 + ci * dt));
+        const double aii = A[i * stages + i];
+        double *Fi = B.F + (long long)i * n;
+        if (aii == 0.0) {
+            // explicit first stage: U_1 = u0, F_1 = f(t0, u0)
+            launch_rhs_eval(n, B.Ju0, u0, f->g, gam, f->eps, Fi, h->stream);
+            continue;
+        }
+        // history term h_i = (1/a_ii) sum_{j<i} a_ij F_j; Newton from W = 0
+        if (i > 0) {
+            double coef[DIRK_STAGES_MAX];
+            for (int j = 0; j < i; ++j) coef[j] = A[i * stages + j] / aii;
+            launch_combine(i, n, coef, B.F, B.hist, h->stream);
+        }
+        HIPCHK(hipMemsetAsync(B.W, 0, sizeof(double) * n, h->stream));
+        bool conv = false;
+        st = newton_solve(h, f, &gam, u0, B, i > 0 ? B.hist : nullptr, newton_tol, max_newton, inf, conv);
+        all_conv = all_conv && conv;
+        if (st != IRK_OK || !conv) break;
+        // F_i = f(t_i, U_i) with U_i = u0 + dt W (the linear part's Jacobian)
+        launch_stage_state(n, u0, B.W, dt, B.U, h->stream);
+        launch_jac_u0(h->dsys, h->hsys, B.Dbase, B.U, B.hist, h->stream);
+        launch_rhs_eval(n, B.hist, B.U, f->g, gam, f->eps, Fi, h->stream);
+    }
+    inf.converged = (st == IRK_OK && all_conv) ? 1 : 0;
+    inf.equiv_mults = inf.gmres_iters;          // each Arnoldi step is one n x n product
+    // stiffly accurate: u1 = U_s (the last stage is implicit here unless s = 1
+    // and explicit, which the checks above exclude for a one-stage tableau
+    // only through a zero diagonal: then u1 = u0)
+    if (inf.converged) {
+        if (A[(stages - 1) * stages + stages - 1] == 0.0)
+            HIPCHK(hipMemcpyAsync(u1, u0, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+        else
+            launch_stage_state(n, u0, B.W, dt, u1, h->stream);
+    }
+    if (f->eps != 0.0) {
+        launch_stage_jac(h->dsys, h->hsys, B.Dbase, u0, B.W, dt, 0.0, h->stream);
+        h->factored = false;
+    }
+    hipEventRecord(h->ev_s1, h->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    hipEventElapsedTime(&inf.ms, h->ev_s0, h->ev_s1);
+    if (info) *info = inf;
+    if (st != IRK_OK) return st;
+    return inf.converged ? IRK_OK : IRK_ERR_NOCONV;
+}
+
 irk_status irk_profile_enable(irk_handle *h, int on)
 {
     if (!h) return IRK_ERR_ARG;
@@ -1281,6 +1641,7 @@ irk_status irk_profile_read(irk_handle *h, irk_profile_stats *out)
         case PK_MV32: out->matvec32_count++; out->matvec32_ms += ms; break;
         case PK_PC: out->pc_count++; out->pc_ms += ms; break;
         case PK_ORTH: out->orth_count++; out->orth_ms += ms; break;
+        case PK_UNTR: out->untr_count++; out->untr_ms += ms; break;
         default: out->factor_count++; out->factor_ms += ms; break;
         }
     }
@@ -1298,6 +1659,8 @@ irk_status irk_destroy(irk_handle *h)
     if (h->ev0) hipEventDestroy(h->ev0);
     if (h->ev1) hipEventDestroy(h->ev1);
     if (h->ev_ready) hipEventDestroy(h->ev_ready);
+    if (h->ev_s0) hipEventDestroy(h->ev_s0);
+    if (h->ev_s1) hipEventDestroy(h->ev_s1);
     delete h;
     return IRK_OK;
 }

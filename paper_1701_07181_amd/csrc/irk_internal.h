@@ -67,6 +67,7 @@ struct SysDesc {
     double dt;
     double rtol, inner_rtol;
     double Ainv[SMAX * SMAX];
+    double A[SMAX * SMAX];  // the tableau itself (untransformed operator)
     double dcoef[SMAX];     // diagonal mass coefficient of each stage's pivot
     // structure (device)
     const int *row_ptr, *col_idx, *diag_pos, *tpos;
@@ -138,6 +139,33 @@ void launch_relayout(const double *src, void *dst, int dst_type, long long nblk,
 void launch_matvec(const SysDesc *dsys, const Item *items, int nitems, int s_max,
                    int prec, bool sharedJ, int x_slot, int y_slot, int b_slot, int mode,
                    int skip_done, size_t shmem, hipStream_t st);
+
+// Untransformed operator y = (I (x) M - dt [a_kl J_k]) x (FP64): fused (one
+// launch, each Jacobian row streamed once for all stages) or block by block
+// (s^2 launches, block (k, l) streams J_k).  Items and LDS as the FP64 matvec.
+void launch_untransformed(const SysDesc *dsys, const Item *items, int nitems, int s, bool fused,
+                          int x_slot, int y_slot, size_t shmem, hipStream_t st);
+
+// ---- one Newton time step (k_step.hip); raw device pointers ----
+void launch_save_diag(const SysDesc *dsys, const SysDesc &hsys, double *Dbase, hipStream_t st);
+void launch_stage_jac(const SysDesc *dsys, const SysDesc &hsys, const double *Dbase, const double *u0,
+                      const double *W, double dt, double eps, hipStream_t st);
+void launch_jac_u0(const SysDesc *dsys, const SysDesc &hsys, const double *Dbase, const double *u0,
+                   double *y, hipStream_t st);
+void launch_stage_rhs(int s, long long n, const double *Ju0, const double *g, const double *u0,
+                      const double *W, double dt, double eps, const double *gam, const double *hist,
+                      double *out, hipStream_t st);
+constexpr int DIRK_STAGES_MAX = 8;
+void launch_combine(int cnt, long long n, const double *coef, const double *F, double *out,
+                    hipStream_t st);
+void launch_stage_state(long long n, const double *u0, const double *W, double dt, double *U,
+                        hipStream_t st);
+void launch_rhs_eval(long long n, const double *JU, const double *U, const double *g, double gam,
+                     double eps, double *F, hipStream_t st);
+void launch_newton_update(long long N, double *W, const double *delta, double *part, double *out,
+                          hipStream_t st);
+void launch_step_finish(int s, long long n, const double *u0, const double *W, double dt,
+                        const double *dcoef, double *u1, hipStream_t st);
 
 // One level of the forward sweep (L~ y = v, then y^ = P^{-1} y per element),
 // or of the backward sweep (z = y^ + P^{-1} (dt J_upper z - C z)).

@@ -142,3 +142,42 @@ def test_setup_rejects_small_workspace():
     h = C.c_void_p()
     st = irk._L.irk_setup(C.byref(p), C.byref(o), C.c_void_p(0x1000), nb.value - 1, None, C.byref(h))
     assert st == irk.ERR_NOMEM and not h.value
+
+
+@pytest.mark.parametrize("bad", ["jump_past_end", "decreasing", "last_not_nnzb"])
+def test_setup_rejects_malformed_row_ptr(bad):
+    """The whole row pointer is validated before any col_idx entry is read:
+    a row pointer that jumps past nnzb (here 1000 with nnzb = 5) must come
+    back as an argument error, not as a read beyond col_idx."""
+    if not os.path.exists(LIB):
+        pytest.skip("libirk.so not built")
+    import ctypes as C
+    import paper_1701_07181_amd as irk
+    T, m, s = 4, 4, 2
+    if bad == "jump_past_end":
+        rp = np.array([0, 1000, 5, 5, 5], dtype=np.int32)
+    elif bad == "decreasing":
+        rp = np.array([0, 3, 2, 4, 5], dtype=np.int32)
+    else:
+        rp = np.array([0, 1, 2, 3, 4], dtype=np.int32)
+    ci = np.array([0, 1, 2, 3, 0], dtype=np.int32)
+    A = np.ascontiguousarray(oracle.radau_iia(s)[0])
+    p = irk._Problem(s, A.ctypes.data, T, m, 5, rp.ctypes.data, ci.ctypes.data, 0x1000, 1,
+                     0x1000, 0.1)
+    o = irk.Options()._c()
+    h = C.c_void_p()
+    st = irk._L.irk_setup(C.byref(p), C.byref(o), C.c_void_p(0x1000), 1 << 40, None, C.byref(h))
+    assert st == irk.ERR_ARG and not h.value
+
+
+@pytest.mark.parametrize("name", ["DIRK33", "ESDIRK65"])
+def test_library_dirk_tableau_matches_oracle(name):
+    if not os.path.exists(LIB):
+        pytest.skip("libirk.so not built")
+    import paper_1701_07181_amd as irk
+    from oracle import step as ostep
+    A, b, c = irk.dirk_tableau(name)
+    Ao, bo, co = ostep.dirk33() if name == "DIRK33" else ostep.esdirk65()
+    np.testing.assert_allclose(A, Ao, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(b, bo, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(c, co, rtol=0, atol=1e-14)

@@ -50,25 +50,31 @@ def test_cfg1_solve_full(cfg1, pc, dt):
     rel = np.linalg.norm(cfg1.rhs - oracle.matvec(P, oracle.inverse(A), x)) / np.linalg.norm(cfg1.rhs)
     print(f"cfg1 {pc} dt={dt}: iters {info['iters']} true rel res {rel:.2e} "
           f"factor {info['ms_factor']:.2f} ms solve {info['ms_solve']:.2f} ms", flush=True)
-    assert info["converged"] and rel <= 1e-10 * 1.01
+    # the library's FP64 residual and the oracle's recomputation differ only
+    # by rounding (~1e-16 relative to ||B|| ||x||, far below 1e-6 of 1e-10)
+    assert info["converged"] and info["rel_res_true"] <= 1e-10
+    assert rel <= 1e-10 * (1 + 1e-6)
     sol.close()
 
 
 def test_cfg1_matches_oracle_solve(cfg1):
-    """Whole solve at full size against the oracle's (about 10 s of CPU):
-    same preconditioner, same CGS2 Arnoldi, so the same iteration count and
-    solutions that agree to 1e-10."""
+    """Whole solve at full size against the oracle's (about 15 s of CPU):
+    same preconditioner, same CGS2 Arnoldi, both sides solved to rtol 1e-12
+    so that the 1e-10 comparison of the solutions is not limited by the
+    stopping test, and the same iteration count within one."""
     irk = _irk()
-    sol = irk.Solver(cfg1, irk.Options(pc="coupled", rtol=1e-10, restart=30))
+    sol = irk.Solver(cfg1, irk.Options(pc="coupled", rtol=1e-12, restart=30))
     sol.factor()
     x, info = sol.solve(cfg1.rhs)
     x = x.cpu().numpy()
     A, _, _ = oracle.radau_iia(3)
-    xo, io = oracle.solve(oracle.Problem(cfg1), A, cfg1.rhs, pc="coupled", rtol=1e-10,
+    xo, io = oracle.solve(oracle.Problem(cfg1), A, cfg1.rhs, pc="coupled", rtol=1e-12,
                           restart=30, orth="cgs2")
     err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
-    print(f"cfg1 coupled vs oracle: iters {info['iters']} / {io['iters']}, rel err {err:.2e}", flush=True)
-    assert info["iters"] == io["iters"]
+    print(f"cfg1 coupled vs oracle (rtol 1e-12): iters {info['iters']} / {io['iters']}, "
+          f"rel err {err:.2e}", flush=True)
+    assert info["converged"] and io["converged"]
+    assert abs(info["iters"] - io["iters"]) <= 1
     assert err <= 1e-10
     sol.close()
 
@@ -87,7 +93,8 @@ def test_cfg2_mixed_full(prec):
     rel = np.linalg.norm(sy.rhs - oracle.matvec(P, oracle.inverse(A), x)) / np.linalg.norm(sy.rhs)
     print(f"cfg2 {prec}: inner {info['iters']} outer {info['outer_iters']} true rel res {rel:.2e} "
           f"factor {info['ms_factor']:.2f} ms solve {info['ms_solve']:.2f} ms", flush=True)
-    assert info["converged"] and rel <= 1e-8 * 1.01
+    assert info["converged"] and info["rel_res_true"] <= 1e-8
+    assert rel <= 1e-8 * (1 + 1e-6)
     sol.close()
     del sol
     torch.cuda.empty_cache()

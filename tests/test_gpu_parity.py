@@ -252,3 +252,32 @@ def test_deterministic():
     assert i1["iters"] == i2["iters"]
     assert torch.equal(x1, x2)
     sol.close()
+
+
+UNTR_CASES = [(2, 2, 8, 16, 1), (3, 2, 4, 5, 1), (1, 2, 4, 7, 1), (4, 2, 5, 36, 4),
+              (5, 2, 4, 9, 1), (3, 2, 6, 64, 3), (3, 3, 4, 135, 1)]
+
+
+@pytest.mark.parametrize("form", ["blocks", "fused"])
+@pytest.mark.parametrize("case", UNTR_CASES, ids=_ids)
+def test_untransformed_operator_parity(form, case):
+    """The untransformed operator I (x) M - dt [a_kl J_k] (Eq. newton-system-2)
+    against the oracle's, and the transformation identity
+    B x = B_untr (A^{-1} (x) I) x between the library's two operators."""
+    irk = _irk()
+    s, dim, N, m, nJ = case
+    _say("untransformed", form, case)
+    sy = _system(s, dim, N, m, nJ, seed=13)
+    sol = irk.Solver(sy, irk.Options(pc="none"))
+    A, _, _ = oracle.radau_iia(s)
+    P = oracle.Problem(sy)
+    x = np.random.default_rng(6).standard_normal(P.N)
+    y = sol.apply_operator_untransformed(x, form=form).cpu().numpy()
+    yo = oracle.matvec_untransformed(P, A, x)
+    assert _rel(y, yo) < 1e-12
+    Ainv = oracle.inverse(A)
+    n = sy.T * sy.m
+    xt = (Ainv @ x.reshape(s, n)).reshape(-1)
+    yt = sol.apply_operator_untransformed(xt, form=form).cpu().numpy()
+    assert _rel(yt, sol.apply_operator(x).cpu().numpy()) < 1e-12
+    sol.close()
