@@ -13,10 +13,14 @@ factorization, and preconditioned GMRES to tolerance.  The level schedule
 is built once per sparsity pattern (setup) and reused, as within a Newton
 loop.
 
-Prints one JSON line.  Also reports the dominant kernel (the BSR
-multi-stage matvec) against the HBM roofline, from HIP events recorded
-around every matvec launch inside the timed region, and the CPU oracle's
-time on the same workload.
+Prints one JSON line.  It reports every kernel family of the step (BSR
+matvec, preconditioner sweeps, factorization, Arnoldi) against its roofline
+from HIP events recorded around each launch group inside the timed region,
+with `roofline` naming the family that takes the most time; the other five
+cells of the workload (dt in {0.01, 0.1, 1.0} x coupled / shifted
+uncoupled); the untransformed operator beside the transformed one; one
+Newton time step (linear and nonlinear) and the DIRK comparison steps; and
+the CPU oracle on the same workload, single-threaded and on all host cores.
 """
 import argparse
 import json
@@ -28,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+FP64_PEAK_TFS = 78.6    # MI355X dense FP64 matrix-core peak, TFLOP/s
 
 
 def matvec_bytes(s, T, m, nnzb, nJ=1, w=8):
@@ -48,28 +53,71 @@ def sweep_bytes(s, T, m, nnzb, coupled, w=8):
     return r_blocks * m * m * w + 2 * s * T * m * m * w + cross + 4 * s * T * m * 8
 
 
+def factor_flops(s, T, m, row_ptr, col_idx, coupled):
+    """FP64 flops of one block ILU(0) factorization as the kernels run it:
+    per stage and element, two m x m products per lower neighbour
+    (P_j^{-1} J_ji, then J_ij X) and one Gauss-Jordan inversion, each 2 m^3;
+    the coupled form adds, per element, the stage rounds' products (2 for
+    the first stage, (s-1-k)(s-k) for stage k >= 1)."""
+    import numpy as np
+    rows = np.repeat(np.arange(T), np.diff(row_ptr))
+    lower = int(np.sum(np.asarray(col_idx) < rows))
+    m3 = 2.0 * m ** 3
+    fl = s * (2 * lower + T) * m3
+    if coupled and s > 1:
+        fl += T * (2 + sum((s - 1 - k) * (s - k) for k in range(1, s))) * m3
+    return fl
+
+
+def arnoldi_bytes(s, T, m, j):
+    """Algorithmic bytes of Arnoldi step j (CGS2: three basis passes over
+    j + 1 vectors, the work vector read and written, the new basis vector)."""
+    return (3 * (j + 1) + 5) * s * T * m * 8
+
+
+def untransformed_bytes(s, T, m, nnzb, nJ=1, form="blocks", w=8):
+    """Algorithmic bytes of the untransformed operator: block by block, each
+    of the s^2 blocks streams its stage Jacobian (and M on the diagonal) and
+    reads x_l, writes y_k; fused, each Jacobian row and M once."""
+    if form == "blocks":
+        return s * s * nnzb * m * m * w + s * T * m * m * w + 2 * s * s * T * m * 8
+    return matvec_bytes(s, T, m, nnzb, nJ, w)
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_matvec_s3_64x64_m64_hbm_traffic.txt")
 TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_matvec.hip", "paper_1701_07181_amd/csrc/irk_device.h"]
+SWEEP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_s3_64x64_m64_coupled_hbm_traffic.txt")
+SWEEP_TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_sweep.hip", "paper_1701_07181_amd/csrc/irk_device.h"]
 
 
-def measured_traffic():
-    """HBM bytes per k_matvec launch from the committed counter summary
+def _counter_traffic(path, sources):
+    """HBM bytes per launch (group) from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a known-size copy), or None
     when the kernel sources have changed since the counters were taken."""
     import hashlib
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(path).read()
     except OSError:
         return None
     vals = dict(l.split(":", 1) for l in txt.splitlines()
                 if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
     h = hashlib.sha256()
-    for p in TRAFFIC_SOURCES:
+    for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     if vals.get("source_sha256", "").split()[0:1] != [h.hexdigest()]:
         return None
     return int(vals["traffic_bytes_per_launch"])
+
+
+def measured_traffic():
+    """HBM bytes per k_matvec launch (see _counter_traffic)."""
+    return _counter_traffic(TRAFFIC_FILE, TRAFFIC_SOURCES)
+
+
+def sweep_traffic():
+    """HBM bytes per preconditioner application (all sweep levels)."""
+    return _counter_traffic(SWEEP_TRAFFIC_FILE, SWEEP_TRAFFIC_SOURCES)
 
 
 def _log(msg):
@@ -261,6 +309,243 @@ def run_serve(args):
             "points": points}
 
 
+def family_report(prof, elapsed, sy, pc, iters, N):
+    """Per kernel family: time in the timed region, its share, the average
+    launch group, and the fraction of its roofline (HBM for the matvec,
+    sweeps and Arnoldi; FP64 for the factorization).  Returns (families,
+    roofline of the family with the most time)."""
+    fam = {}
+    tot = elapsed * 1e3
+    if prof["matvec_count"]:
+        ms = prof["matvec_ms"] / prof["matvec_count"]
+        by = matvec_bytes(sy.s, sy.T, sy.m, sy.nnzb)
+        ach = by / (ms * 1e-3) / 1e9
+        fam["matvec"] = {"kernel": "k_matvec (BSR multi-stage matvec, FP64)", "bound": "hbm",
+                         "total_ms": round(prof["matvec_ms"], 3), "share": round(prof["matvec_ms"] / tot, 4),
+                         "launches": prof["matvec_count"], "avg_launch_us": round(ms * 1e3, 2),
+                         "bytes_per_launch": by, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic() if N == 64 else None}
+    if prof["pc_count"]:
+        ms = prof["pc_ms"] / prof["pc_count"]
+        by = sweep_bytes(sy.s, sy.T, sy.m, sy.nnzb, pc == "coupled")
+        ach = by / (ms * 1e-3) / 1e9
+        fam["sweeps"] = {"kernel": "k_sweep (block ILU(0) forward + backward sweeps, all levels of "
+                                   "one preconditioner application, FP64)", "bound": "hbm",
+                         "total_ms": round(prof["pc_ms"], 3), "share": round(prof["pc_ms"] / tot, 4),
+                         "launches": prof["pc_count"], "avg_launch_us": round(ms * 1e3, 2),
+                         "bytes_per_launch": by, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": sweep_traffic() if N == 64 and pc == "coupled" else None}
+    if prof["factor_count"]:
+        ms = prof["factor_ms"] / prof["factor_count"]
+        fl = factor_flops(sy.s, sy.T, sy.m, sy.row_ptr, sy.col_idx, pc == "coupled")
+        ach = fl / (ms * 1e-3) / 1e12
+        fam["factor"] = {"kernel": "k_factor_a / k_factor_b (block ILU(0) factorization, all levels, "
+                                   "FP64 matrix-core products and Gauss-Jordan inverses)", "bound": "mfma",
+                         "total_ms": round(prof["factor_ms"], 3), "share": round(prof["factor_ms"] / tot, 4),
+                         "launches": prof["factor_count"], "avg_launch_us": round(ms * 1e3, 2),
+                         "flops_per_launch": fl, "achieved": round(ach, 2), "peak": FP64_PEAK_TFS,
+                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFS, 4), "traffic": None}
+    if prof["orth_count"]:
+        ms = prof["orth_ms"] / prof["orth_count"]
+        # steps j = 0 .. iters-1 of one cycle per solve (GMRES(30) never restarts here)
+        it = max(1, iters[0])
+        by = sum(arnoldi_bytes(sy.s, sy.T, sy.m, j) for j in range(it)) / it
+        ach = by / (ms * 1e-3) / 1e9
+        fam["arnoldi"] = {"kernel": "k_cgs / k_cgs_finish / k_scale (CGS2 Arnoldi step + Givens)",
+                          "bound": "hbm", "total_ms": round(prof["orth_ms"], 3),
+                          "share": round(prof["orth_ms"] / tot, 4), "launches": prof["orth_count"],
+                          "avg_launch_us": round(ms * 1e3, 2), "bytes_per_launch": int(by),
+                          "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    dom = max(fam, key=lambda k: fam[k]["total_ms"])
+    f = fam[dom]
+    roof = {"bound": f["bound"], "achieved": f["achieved"], "peak": f["peak"], "unit": f["unit"],
+            "frac": f["frac"], "traffic": f["traffic"], "kernel": f["kernel"], "family": dom,
+            "share_of_step": f["share"], "avg_launch_us": f["avg_launch_us"], "launches": f["launches"]}
+    roof["bytes_per_launch" if "bytes_per_launch" in f else "flops_per_launch"] = \
+        f.get("bytes_per_launch", f.get("flops_per_launch"))
+    return fam, roof
+
+
+def run_cells(sy, args, skip, irk, torch):
+    """The other cells of the workload (dt x preconditioner), each timed over
+    a few steps of ingest + factor + solve after one warm-up step."""
+    out = []
+    rhs = torch.as_tensor(sy.rhs).cuda()
+    for pc in ("coupled", "uncoupled_shifted"):
+        for dt in (0.01, 0.1, 1.0):
+            if (dt, pc) == skip:
+                continue
+            sol = irk.Solver(sy, irk.Options(pc=pc, rtol=1e-10, restart=30), dt=dt)
+            sol.factor()
+            sol.autotune()
+            Jd, Md = sol.J, sol.M
+
+            def step():
+                sol.update_values(Jd, Md, dt)
+                sol.factor()
+                return sol.solve(rhs)[1]
+            step()
+            torch.cuda.synchronize()
+            n = 4
+            t0 = time.perf_counter()
+            infos = [step() for _ in range(n)]
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / n
+            assert all(i["converged"] for i in infos), (dt, pc)
+            out.append({"dt": dt, "pc": pc, "solves_per_s": round(1.0 / el, 3),
+                        "ms_per_step": round(el * 1e3, 3), "iters": infos[-1]["iters"],
+                        "equiv_mults": infos[-1]["equiv_mults"],
+                        "ms_factor": round(infos[-1]["ms_factor"], 3),
+                        "rel_res_true": infos[-1]["rel_res_true"]})
+            _log(f"cell dt={dt} {pc}: {out[-1]}")
+            sol.close()
+            del sol
+            torch.cuda.empty_cache()
+    return out
+
+
+def run_extras(solver, sy, irk, torch):
+    """The untransformed operator beside the transformed one (Table 2), one
+    Newton time step (linear f; nonlinear f with per-stage Jacobians), and
+    the DIRK comparison steps at equal order, on the same mesh and blocks."""
+    import numpy as np
+    out = {}
+    x = torch.as_tensor(np.random.default_rng(5).standard_normal(sy.s * sy.T * sy.m)).cuda()
+    reps = 10
+    solver.profile(True)
+    for _ in range(reps):
+        solver.apply_operator(x)
+    mv = solver.profile_read()
+    res = {"transformed": {"avg_us": round(mv["matvec_ms"] / mv["matvec_count"] * 1e3, 2),
+                           "bytes": matvec_bytes(sy.s, sy.T, sy.m, sy.nnzb)}}
+    for form in ("blocks", "fused"):
+        solver.profile(True)
+        for _ in range(reps):
+            solver.apply_operator_untransformed(x, form=form)
+        pr = solver.profile_read()
+        us = pr["untr_ms"] / pr["untr_count"] * 1e3
+        by = untransformed_bytes(sy.s, sy.T, sy.m, sy.nnzb, form=form)
+        res[f"untransformed_{form}"] = {"avg_us": round(us, 2), "bytes": by,
+                                        "achieved_GBs": round(by / (us * 1e-6) / 1e9, 1)}
+    res["ratio_blocks_over_transformed"] = round(res["untransformed_blocks"]["avg_us"]
+                                                 / res["transformed"]["avg_us"], 3)
+    solver.profile(False)
+    out["untransformed_operator"] = res
+    _log(f"untransformed: {res}")
+
+    rng = np.random.default_rng(77)
+    n = sy.T * sy.m
+    u0 = torch.as_tensor(rng.standard_normal(n)).cuda()
+    g = torch.as_tensor(rng.standard_normal(n)).cuda()
+    dt = 0.1
+    steps = {}
+    # linear f = J u + cos(2 t) g with the workload's operator; the step
+    # re-factors (a new Jacobian per step, as in a Newton loop)
+    lin = irk.Solver(sy, irk.Options(pc="coupled", rtol=1e-10), dt=dt)
+    lin.step(u0, g=g, omega=2.0, newton_tol=1e-8)
+    lin.update_values(lin.J, lin.M, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, inf = lin.step(u0, g=g, omega=2.0, newton_tol=1e-8)
+    torch.cuda.synchronize()
+    steps["radau35_linear"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), **{
+        k: inf[k] for k in ("newton_iters", "gmres_iters", "equiv_mults", "factorizations")}}
+    lin.close()
+    # nonlinear f = J u + cos(2 t) g - 0.3 u^3: per-stage Jacobians (nJ = s)
+    J3 = np.repeat(np.asarray(sy.J), sy.s, axis=0)
+    sy3 = type(sy)(**{**sy.__dict__, "J": J3, "nJ": sy.s})
+    nl = irk.Solver(sy3, irk.Options(pc="coupled", rtol=1e-10), dt=dt)
+    del J3
+    nl.step(u0, g=g, omega=2.0, eps=0.3, newton_tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, inf = nl.step(u0, g=g, omega=2.0, eps=0.3, newton_tol=1e-8)
+    torch.cuda.synchronize()
+    steps["radau35_nonlinear"] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), **{
+        k: inf[k] for k in ("newton_iters", "gmres_iters", "equiv_mults", "factorizations")}}
+    nl.close()
+    del nl, sy3
+    torch.cuda.empty_cache()
+    # equal-order comparison of one linear step each (factorization included):
+    # RADAU23 vs DIRK33 (order 3), RADAU35 vs ESDIRK65 (order 5)
+    cmp = {}
+    for name, kind, arg in (("RADAU23", "radau", 2), ("DIRK33", "dirk", "DIRK33"),
+                            ("RADAU35", "radau", 3), ("ESDIRK65", "dirk", "ESDIRK65")):
+        if kind == "radau":
+            so = irk.Solver(sy, irk.Options(pc="coupled", rtol=1e-10), s=arg, dt=dt)
+            run = lambda: so.step(u0, g=g, omega=2.0, newton_tol=1e-8)
+        else:
+            A, _, _ = irk.dirk_tableau(arg)
+            so = irk.Solver(sy, irk.Options(pc="coupled", rtol=1e-10), A=np.array([[A[-1, -1]]]),
+                            s=1, dt=dt)
+            run = lambda: so.dirk_step(A, u0, g=g, omega=2.0, newton_tol=1e-8)
+        run()
+        so.update_values(so.J, so.M, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u1, inf = run()
+        torch.cuda.synchronize()
+        cmp[name] = {"ms": round((time.perf_counter() - t0) * 1e3, 2), **{
+            k: inf[k] for k in ("newton_iters", "gmres_iters", "equiv_mults", "factorizations")}}
+        so.close()
+        torch.cuda.empty_cache()
+    steps["equal_order_comparison"] = cmp
+    out["time_step"] = steps
+    _log(f"time steps: {steps}")
+    return out
+
+
+def cpu_baselines(sy, pc):
+    """The oracle on the same workload: one full solve single-threaded and one
+    with the OpenMP build on all host cores (a child process, so the two
+    builds do not meet in one process; it uses no GPU)."""
+    import subprocess
+    import oracle
+    A, _, _ = oracle.radau_iia(sy.s)
+    P = oracle.Problem(sy)
+    tc = time.perf_counter()
+    xo, io = oracle.solve(P, A, sy.rhs, pc=pc, rtol=1e-10, orth="cgs2")
+    t1 = time.perf_counter() - tc
+    single = {"value": round(1.0 / t1, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+              "sample": f"one full solve of the same workload (factor + GMRES, {io['iters']} "
+                        f"iterations), plain FP64 C loops, single thread, {t1:.1f} s"}
+    code = ("import sys, time, os; sys.path.insert(0, %r)\n"
+            "import oracle, dgsynth\n"
+            "oracle.use_openmp(True)\n"
+            "sy = dgsynth.config_system('cfg1', dt=%r, N=%d)\n"
+            "A, _, _ = oracle.radau_iia(sy.s)\n"
+            "P = oracle.Problem(sy)\n"
+            "t = time.perf_counter()\n"
+            "x, i = oracle.solve(P, A, sy.rhs, pc=%r, rtol=1e-10, orth='cgs2')\n"
+            "print(time.perf_counter() - t, i['iters'])\n") % (ROOT, sy.dt, int(round(sy.T ** 0.5)), pc)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    allc = None
+    if r.returncode == 0:
+        tall, its = r.stdout.split()[-2:]
+        tall = float(tall)
+        model = ""
+        try:
+            lines = subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines()
+            info = {l.split(":", 1)[0].strip(): l.split(":", 1)[1].strip() for l in lines if ":" in l}
+            model = f"{info.get('Model name', '?')}, {info.get('Socket(s)', '?')} socket(s), " \
+                    f"{info.get('CPU(s)', '?')} CPUs"
+        except OSError:
+            pass
+        allc = {"value": round(1.0 / tall, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+                "sample": f"one full solve of the same workload ({its} iterations), the oracle's "
+                          f"OpenMP build (matvec rows, per-pivot row updates of the ILU(0), "
+                          f"uncoupled stages, GMRES vector loops) on {threads} threads, {tall:.1f} s; "
+                          f"nproc {os.cpu_count()}; {model}"}
+    else:
+        _log("all-cores oracle run failed: " + r.stderr[-400:])
+    return (allc or single), (single if allc else None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +555,9 @@ def main():
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--N", type=int, default=64, help="mesh side (64 = the full workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cells", action="store_true", help="skip the other dt / preconditioner cells")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the untransformed operator, time-step and DIRK measurements")
     ap.add_argument("--no-profile", action="store_true", help="no HIP events around kernels")
     ap.add_argument("--mode", default="headline", choices=["headline", "mixed", "batched", "serve"],
                     help="headline: the FP64 64x64 workload (default); mixed: the 16^3 hex m=135 "
@@ -352,41 +640,15 @@ def main():
     iters = [i["iters"] for i in infos]
     res = max(i["rel_res_true"] for i in infos)
 
-    mv_bytes = matvec_bytes(sy.s, sy.T, sy.m, sy.nnzb)
-    roof = None
-    extra = {}
-    if prof and prof["matvec_count"]:
-        mv_ms = prof["matvec_ms"] / prof["matvec_count"]
-        ach = mv_bytes / (mv_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic() if args.N == 64 else None,
-                "kernel": "k_matvec (BSR multi-stage matvec, FP64)",
-                "avg_launch_us": round(mv_ms * 1e3, 2), "launches": prof["matvec_count"],
-                "bytes_per_launch": mv_bytes}
-        if prof["pc_count"]:
-            pc_ms = prof["pc_ms"] / prof["pc_count"]
-            sb = sweep_bytes(sy.s, sy.T, sy.m, sy.nnzb, args.pc == "coupled")
-            extra["preconditioner_apply"] = {
-                "avg_us": round(pc_ms * 1e3, 1), "bytes": sb,
-                "achieved_GBs": round(sb / (pc_ms * 1e-3) / 1e9, 1),
-                "frac": round(sb / (pc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        if prof["orth_count"]:
-            extra["arnoldi_avg_us"] = round(prof["orth_ms"] / prof["orth_count"] * 1e3, 1)
-        if prof["factor_count"]:
-            extra["factor_avg_ms"] = round(prof["factor_ms"] / prof["factor_count"], 3)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        A, _, _ = oracle.radau_iia(sy.s)
-        P = oracle.Problem(sy)
-        tc = time.perf_counter()
-        xo, io = oracle.solve(P, A, sy.rhs, pc=args.pc, rtol=1e-10, orth="cgs2")
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": round(1.0 / tcpu, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full solve of the same workload (factor + GMRES, {io['iters']} "
-                         f"iterations), plain FP64 C loops, single thread, {tcpu:.1f} s"}
+    fam, roof = family_report(prof, elapsed, sy, args.pc, iters, args.N) if prof else ({}, None)
+    extra = {"kernels": fam} if fam else {}
+    if not args.no_cells:
+        extra["cells"] = run_cells(sy, args, (args.dt, args.pc), irk, torch)
+    if not args.no_extras:
+        extra.update(run_extras(solver, sy, irk, torch))
+    cpu, cpu1 = (None, None) if args.no_cpu_baseline else cpu_baselines(sy, args.pc)
+    if cpu1:
+        extra["cpu_baseline_single_thread"] = cpu1
 
     out = {
         "metric": "IRK solves/s at 1e-8 rel residual; BSR matvec GB/s vs HBM peak; p99 latency",

@@ -31,11 +31,24 @@ FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
+def _includes(path: str, seen: set) -> set:
+    """Local headers a source includes, transitively (quoted includes found
+    in csrc/ or include/)."""
+    import re
+    for name in re.findall(r'^\s*#\s*include\s+"([^"]+)"', open(path).read(), re.M):
+        for d in (CSRC, os.path.join(ROOT, "include")):
+            f = os.path.join(d, name)
+            if os.path.exists(f) and f not in seen:
+                seen.add(f)
+                _includes(f, seen)
+    return seen
+
+
 def _up_to_date(obj: str, src: str) -> bool:
     if not os.path.exists(obj):
         return False
-    deps = [os.path.join(CSRC, src), os.path.join(ROOT, "include", "irk.h")]
-    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    path = os.path.join(CSRC, src)
+    deps = [path] + sorted(_includes(path, set()))
     return os.path.getmtime(obj) > max(os.path.getmtime(d) for d in deps)
 
 
