@@ -219,6 +219,23 @@ irk_status irk_batch_destroy(irk_batch *b);
 irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
                              double *const *x, int count, irk_solve_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc):
+ * irk_solve_batched without a batch object.  The batch's device scratch
+ * (system table, gathered convergence states, merged work items) is a
+ * library-owned static device array of about 14.8 MB per GPU, taken at the
+ * first call on a device (the current device) and held until the process
+ * ends; the call allocates no device memory.  Limits: count <= 64 and at
+ * most 32768 elements over all handles, else IRK_ERR_ARG before any work.
+ * Handles, rhs, x, info and the result as for irk_solve_batched; all work
+ * goes to `stream`, and the call returns after it has finished.  Every call
+ * on one GPU shares the array: calls from several host threads are
+ * serialized by the library; the array's contents are rewritten by each
+ * call before they are read. */
+irk_status irk_solve_batched_noalloc(irk_handle *const *h, const double *const *rhs,
+                                     double *const *x, int count, hipStream_t stream,
+                                     irk_solve_info *info);
+
 /* Block ILU(0) factorization of `count` handles together (the same
  * factorization as irk_factor_ilu, Sec. 4.2-4.3): level l of every handle
  * runs in the same launches (one per level and kernel class), so many small

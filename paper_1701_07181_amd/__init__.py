@@ -90,6 +90,8 @@ _L.irk_update_values.argtypes = [_vp, _vp, _vp, C.c_double]
 _L.irk_factor_ilu.argtypes = [_vp]
 _L.irk_gmres_solve.argtypes = [_vp, _vp, _vp, C.POINTER(_Info)]
 _L.irk_solve_batched.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.POINTER(_Info)]
+_L.irk_solve_batched_noalloc.argtypes = [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, _vp,
+                                         C.POINTER(_Info)]
 _L.irk_batch_workspace_size.argtypes = [C.c_int, C.c_longlong, C.POINTER(C.c_size_t)]
 _L.irk_batch_create.argtypes = [C.c_int, C.c_longlong, _vp, C.c_size_t, _vp, C.POINTER(_vp)]
 _L.irk_batch_admit.argtypes = [_vp, _vp, _vp, _vp, C.c_longlong]
@@ -128,7 +130,8 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_batch_pending", "irk_batch_destroy", "irk_autotune", "irk_factor_batched",
             "irk_apply_operator_inner", "irk_apply_preconditioner_inner",
             "irk_apply_operator_untransformed", "irk_step_workspace_size", "irk_radau_step",
-            "irk_dirk_workspace_size", "irk_dirk_step", "irk_dirk_tableau"]
+            "irk_dirk_workspace_size", "irk_dirk_step", "irk_dirk_tableau",
+            "irk_solve_batched_noalloc"]
 
 
 def _check(st: int, where: str):
@@ -560,3 +563,20 @@ def solve_batched(batch: Batch, solvers: Sequence[Solver], rhs: Sequence, x0: Op
     infos = (_Info * n)()
     st = _L.irk_solve_batched(batch._b, H, B, X, n, infos)
     return xs, [_info_dict(infos[q], st) for q in range(n)], st
+
+
+def solve_batched_noalloc(solvers: Sequence[Solver], rhs: Sequence, x: Sequence[torch.Tensor],
+                          stream: Optional[torch.cuda.Stream] = None):
+    """irk_solve_batched_noalloc: the batched solve with the library's own
+    static device scratch (no batch object, no device allocation in the
+    call).  rhs and x are device FP64 vectors of each solver's size; x holds
+    the initial guesses and receives the solutions.  Returns (info dicts,
+    status)."""
+    n = len(solvers)
+    st_ = stream or torch.cuda.current_stream()
+    H = (_vp * n)(*[s.handle for s in solvers])
+    B = (_vp * n)(*[int(r.data_ptr()) for r in rhs])
+    X = (_vp * n)(*[int(v.data_ptr()) for v in x])
+    infos = (_Info * n)()
+    st = _L.irk_solve_batched_noalloc(H, B, X, n, _vp(st_.cuda_stream), infos)
+    return [_info_dict(infos[q], st) for q in range(n)], st

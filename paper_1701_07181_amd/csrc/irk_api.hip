@@ -23,7 +23,7 @@ struct Launch { int off, n; };
 // workgroup, prefetching form or not
 struct SwLaunch { int off, n, tps; bool pf; int region; };
 
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------------------
 // small dense helpers (host)
@@ -403,7 +403,9 @@ struct irk_batch {
     Item *ditems;
     size_t max_items;
     std::vector<SysDesc> htab;   // host copy of the table
-    DevState *hgather;           // pinned [capacity]
+    DevState *hgather;           // [capacity]: pinned (own_host) or the caller's host array
+    bool own_host = true;
+    std::vector<hipEvent_t> slot_ev;   // start of the member in each slot
     struct Member {
         irk_handle *h;
         int slot;
@@ -1668,12 +1670,12 @@ irk_status irk_destroy(irk_handle *h)
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------
-static size_t batch_items_bound(int capacity, long long max_elements)
+static constexpr size_t batch_items_bound(int capacity, long long max_elements)
 {
     return (size_t)(24 * max_elements) + (size_t)capacity * (2 * RED_BLOCKS + 8);
 }
 
-static size_t batch_ws_bytes(int capacity, long long max_elements)
+static constexpr size_t batch_ws_bytes(int capacity, long long max_elements)
 {
     size_t off = 0;
     off = align256(off + sizeof(SysDesc) * (size_t)capacity);
@@ -1689,14 +1691,14 @@ irk_status irk_batch_workspace_size(int capacity, long long max_elements, size_t
     return IRK_OK;
 }
 
-irk_status irk_batch_create(int capacity, long long max_elements, void *workspace, size_t ws_bytes,
-                            hipStream_t stream, irk_batch **out)
+}  // extern "C"
+
+// Lay out a batch over `workspace` (device table, gathered states, merged
+// items) and create its events; hgather is the host array the states are
+// read into.
+static irk_status batch_init(irk_batch *b, int capacity, long long max_elements, void *workspace,
+                             size_t ws_bytes, hipStream_t stream, DevState *hgather, bool own_host)
 {
-    if (!out || !workspace || capacity < 1 || max_elements < 1) return IRK_ERR_ARG;
-    *out = nullptr;
-    if (ws_bytes < batch_ws_bytes(capacity, max_elements)) return IRK_ERR_NOMEM;
-    irk_batch *b = new (std::nothrow) irk_batch();
-    if (!b) return IRK_ERR_ARG;
     b->capacity = capacity;
     b->max_elements = max_elements;
     b->stream = stream;
@@ -1710,14 +1712,38 @@ irk_status irk_batch_create(int capacity, long long max_elements, void *workspac
     b->ditems = (Item *)(b->ws + off);
     b->max_items = batch_items_bound(capacity, max_elements);
     b->htab.assign(capacity, SysDesc());
-    if (hipHostMalloc((void **)&b->hgather, sizeof(DevState) * capacity, hipHostMallocDefault) != hipSuccess) {
+    b->hgather = hgather;
+    b->own_host = own_host;
+    b->free_slots.clear();
+    for (int q = capacity - 1; q >= 0; --q) b->free_slots.push_back(q);
+    b->slot_ev.assign(capacity, nullptr);
+    for (auto &e : b->slot_ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventCreate(&b->ev_end));
+    HIPCHK(hipEventCreate(&b->ev_f0));
+    HIPCHK(hipEventCreate(&b->ev_f1));
+    return IRK_OK;
+}
+
+extern "C" {
+
+irk_status irk_batch_create(int capacity, long long max_elements, void *workspace, size_t ws_bytes,
+                            hipStream_t stream, irk_batch **out)
+{
+    if (!out || !workspace || capacity < 1 || max_elements < 1) return IRK_ERR_ARG;
+    *out = nullptr;
+    if (ws_bytes < batch_ws_bytes(capacity, max_elements)) return IRK_ERR_NOMEM;
+    irk_batch *b = new (std::nothrow) irk_batch();
+    if (!b) return IRK_ERR_ARG;
+    DevState *hg = nullptr;
+    if (hipHostMalloc((void **)&hg, sizeof(DevState) * capacity, hipHostMallocDefault) != hipSuccess) {
         delete b;
         return IRK_ERR_DEVICE;
     }
-    for (int q = capacity - 1; q >= 0; --q) b->free_slots.push_back(q);
-    hipEventCreate(&b->ev_end);
-    hipEventCreate(&b->ev_f0);
-    hipEventCreate(&b->ev_f1);
+    const irk_status st = batch_init(b, capacity, max_elements, workspace, ws_bytes, stream, hg, true);
+    if (st != IRK_OK) {
+        irk_batch_destroy(b);
+        return st;
+    }
     *out = b;
     return IRK_OK;
 }
@@ -1755,8 +1781,8 @@ irk_status irk_batch_admit(irk_batch *b, irk_handle *h, const double *rhs, doubl
         HIPCHK(hipEventRecord(h->ev_ready, h->stream));
         HIPCHK(hipStreamWaitEvent(b->stream, h->ev_ready, 0));
     }
-    hipEventCreate(&m.t0);
-    hipEventRecord(m.t0, b->stream);
+    m.t0 = b->slot_ev[m.slot];
+    HIPCHK(hipEventRecord(m.t0, b->stream));
     b->members.push_back(m);
     return IRK_OK;
 }
@@ -1806,7 +1832,6 @@ static void batch_retire_finished(irk_batch *b, std::vector<Solve> &sol, const s
             float ms = 0.0f;
             hipEventElapsedTime(&ms, m.t0, b->ev_end);
             m.info.ms_solve = ms;
-            hipEventDestroy(m.t0);
             b->free_slots.push_back(m.slot);
             b->retired.push_back(m);
         } else {
@@ -2019,11 +2044,78 @@ irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *c
     return worst;
 }
 
+// ---------------------------------------------------------------------------
+// batched solve without device allocation: the batch's device table,
+// gathered states and merged work items live in a library-owned array
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+constexpr int NA_CAPACITY = 64;                 // members per call
+constexpr long long NA_ELEMENTS = 1LL << 15;    // elements of all members together
+constexpr size_t NA_BYTES = batch_ws_bytes(NA_CAPACITY, NA_ELEMENTS);
+constexpr int NA_MAX_DEVICES = 64;
+
+// One batch per device over that device's copy of `scratch`; created at the
+// first call on the device and kept until the process ends.
+struct NoAllocCtx {
+    std::mutex mu;
+    bool ready = false;
+    irk_batch b;
+    DevState hgather[NA_CAPACITY];
+};
+NoAllocCtx g_noalloc[NA_MAX_DEVICES];
+}  // namespace
+
+// Device memory of irk_solve_batched_noalloc (each GPU holds its own copy).
+// Host code reaches it only through the address hipGetSymbolAddress returns.
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+extern "C" irk_status irk_solve_batched_noalloc(irk_handle *const *h, const double *const *rhs,
+                                                double *const *x, int count, hipStream_t stream,
+                                                irk_solve_info *info)
+{
+    if (!h || !rhs || !x || count < 0) return IRK_ERR_ARG;
+    if (count > NA_CAPACITY) return IRK_ERR_ARG;
+    long long elems = 0;
+    for (int q = 0; q < count; ++q) {
+        if (!h[q]) return IRK_ERR_ARG;
+        elems += h[q]->T;
+    }
+    if (elems > NA_ELEMENTS) return IRK_ERR_ARG;
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NA_MAX_DEVICES) return IRK_ERR_ARG;
+    NoAllocCtx &c = g_noalloc[dev];
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (!c.ready) {
+        // once per device, with that device current
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return IRK_ERR_DEVICE;
+        const irk_status st = batch_init(&c.b, NA_CAPACITY, NA_ELEMENTS, ptr, NA_BYTES, stream, c.hgather,
+                                         false);
+        if (st != IRK_OK) return st;
+        c.ready = true;
+    }
+    // a call that failed part-way may have left members behind: every call
+    // starts from an empty batch (the array's contents are rewritten before
+    // any kernel reads them)
+    c.b.members.clear();
+    c.b.retired.clear();
+    c.b.free_slots.clear();
+    for (int q = NA_CAPACITY - 1; q >= 0; --q) c.b.free_slots.push_back(q);
+    c.b.stream = stream;
+    return irk_solve_batched(&c.b, h, rhs, x, count, info);
+}
+
+extern "C" {
+
 irk_status irk_batch_destroy(irk_batch *b)
 {
     if (!b) return IRK_ERR_ARG;
-    for (auto &m : b->members) hipEventDestroy(m.t0);
-    if (b->hgather) hipHostFree(b->hgather);
+    for (auto &e : b->slot_ev)
+        if (e) hipEventDestroy(e);
+    if (b->hgather && b->own_host) hipHostFree(b->hgather);
     if (b->ev_end) hipEventDestroy(b->ev_end);
     if (b->ev_f0) hipEventDestroy(b->ev_f0);
     if (b->ev_f1) hipEventDestroy(b->ev_f1);
