@@ -46,10 +46,12 @@ def matvec_bytes(s, T, m, nnzb, nJ=1, w=8):
 def sweep_bytes(s, T, m, nnzb, coupled, w=8):
     """Algorithmic bytes of one preconditioner application (both sweeps):
     off-diagonal Jacobian blocks once (lower ones forward, upper ones
-    backward), every pivot inverse twice, each cross-stage block once (C_kl
-    with l < k forward, l > k backward), and four stage-vector passes."""
+    backward), every pivot inverse twice, and four stage-vector passes; the
+    coupled form adds each stored cross-stage block once (C_kl with k, l >= 1:
+    the ones in stage row or column 0 are multiples of M) and the mass block
+    once per direction."""
     r_blocks = nnzb - T
-    cross = s * (s - 1) * T * m * m * w if coupled and s > 1 else 0
+    cross = ((s - 1) * (s - 2) + 2) * T * m * m * w if coupled and s > 1 else 0
     return r_blocks * m * m * w + 2 * s * T * m * m * w + cross + 4 * s * T * m * 8
 
 

@@ -220,11 +220,12 @@ int pick_tpw(int ld, int V)
 }
 
 // Register budget of the prefetching sweep: the pivot blocks (and, coupled,
-// the cross blocks one sweep reads) of an element plus the first Jacobian
-// columns, 8 compute-type values per thread and block (VGPRs of 32 bits).
+// the stored cross blocks one sweep reads and the mass block) of an element
+// plus the first Jacobian columns, 8 compute-type values per thread and
+// block (VGPRs of 32 bits).
 bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF)
 {
-    const int blocks = S + (coupled ? S * (S - 1) / 2 : 0);
+    const int blocks = S + (coupled && S > 1 ? (S - 1) * (S - 2) / 2 + 1 : 0);
     const int per_block = (VF == 2) ? 16 : 8;        // FP64: 8 doubles; float: 8 floats
     const int jac = (VJ == 2) ? 64 : 32;             // 16 FP64 or 8 FP32 column loads
     return blocks * per_block + jac <= 176;
@@ -277,7 +278,9 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     const bool coupled = (o->pc == IRK_PC_COUPLED) && s > 1;
     const int ft = factor_type(o);
     const long long N = (long long)s * T * m;
-    const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * s * (s - 1) : 0;
+    // cross blocks C_{lq} with l, q >= 1 (those in stage row or column 0 stay
+    // multiples of M and are not stored)
+    const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * (s - 1) * (s - 2) : 0;
     P.nitems_max = T * (24 + 10 * s) + 2 * RED_BLOCKS + 64;   // sweep records and padded factor tasks
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
@@ -293,15 +296,15 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     }
     if (o->pc != IRK_PC_NONE) {
         P.o_P64 = take(sizeof(double) * (size_t)nblkP * m * P.ld);
-        if (coupled) P.o_C64 = take(sizeof(double) * (size_t)nblkC * m * P.ld);
+        if (nblkC) P.o_C64 = take(sizeof(double) * (size_t)nblkC * m * P.ld);
         P.o_Fscr = take(sizeof(double) * (size_t)nblkP * m * P.ld);
         if (mixed && ft == FT_F32) {
             P.o_P32 = take(sizeof(float) * (size_t)nblkP * m * P.ld32);
-            if (coupled) P.o_C32 = take(sizeof(float) * (size_t)nblkC * m * P.ld32);
+            if (nblkC) P.o_C32 = take(sizeof(float) * (size_t)nblkC * m * P.ld32);
         } else if (mixed) {
             P.o_P16 = take(sizeof(uint16_t) * (size_t)nblkP * m * P.ld16);
             P.o_P16e = take(sizeof(int) * (size_t)nblkP);
-            if (coupled) {
+            if (nblkC) {
                 P.o_C16 = take(sizeof(uint16_t) * (size_t)nblkC * m * P.ld16);
                 P.o_C16e = take(sizeof(int) * (size_t)nblkC);
             }
@@ -375,7 +378,7 @@ struct irk_handle {
     WorkSet W;
     int tpw64, tpw32, nblk;
     SweepShape sw64, sw32;   // sweep launch shapes (FP64, mixed inner)
-    std::vector<Launch> fa, fb;
+    std::vector<Launch> fa;    // factor tasks, one launch per wavefront
     std::vector<Item> fitems;
     size_t shm_fac;
     bool mixed, coupled, sharedJ, factored;
@@ -596,8 +599,6 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         for (int tps : {h->sw64.tps_pf, h->sw64.tps_st})
             M.shm_sw64 = std::max(M.shm_sw64, sizeof(double) * tps * (size_t)sw_region(M.smax, h->m, mr, P, true, h->ftype, tps));
         if (M.mixed) {
-            const int ldF = (h->ftype == FT_F32) ? P.ld32 : P.ld16;
-            const int VF = (h->ftype == FT_F32) ? 4 : 8;
             M.shm_mv32 = std::max(M.shm_mv32, lds_matvec(M.smax, h->m, mr, P.ld32, 4, h->tpw32, sizeof(float)));
             for (int tps : {h->sw32.tps_pf, h->sw32.tps_st})
                 M.shm_sw32 = std::max(M.shm_sw32, sizeof(float) * tps * (size_t)sw_region(M.smax, h->m, mr, P, false, h->ftype, tps));
@@ -964,33 +965,41 @@ static irk_status build_items(irk_handle *h)
             add_level_records(W.items, h->sc, rp, ci, false, b, pb, sb, W.bwd32);
         }
     }
-    // factor tasks per forward level (stored after the work set's items)
-    h->fa.clear(); h->fb.clear();
+    // factor tasks, one launch per wavefront (stored after the work set's
+    // items).  Uncoupled: wavefront = forward level; workgroup w takes stage
+    // k = (w / 8) % s of element 8 (w / (8 s)) + w % 8, so the s tasks of an
+    // element run on one XCD (workgroups go to the XCDs round-robin) and
+    // share its L2 for the blocks common to all stages; first = -1 pads the
+    // last group of eight.  Coupled: task (k, i) belongs to wavefront
+    // level(i) + k (its own earlier stages and the lower neighbours' same
+    // stage are done by then).
+    h->fa.clear();
     h->fitems.clear();
     if (o->pc != IRK_PC_NONE) {
-        for (size_t l = 0; l + 1 < h->sc.off_fwd.size(); ++l) {
-            // phase 0: workgroup w takes stage k = (w / 8) % s of element
-            // 8 (w / (8 s)) + w % 8, so the s tasks of an element run on one
-            // XCD (workgroups go to the XCDs round-robin) and share its L2
-            // for the blocks common to all stages; first = -1 pads the last
-            // group of eight
+        const int L = (int)h->sc.off_fwd.size() - 1;
+        const int nw = h->coupled ? L + s - 1 : L;
+        for (int wf = 0; wf < nw; ++wf) {
             Launch A{(int)(W.items.size() + h->fitems.size()), 0};
-            const int a0 = h->sc.off_fwd[l], ne = h->sc.off_fwd[l + 1] - a0;
-            for (int g = 0; g < (ne + 7) / 8; ++g)
-                for (int k = 0; k < s; ++k)
-                    for (int r = 0; r < 8; ++r) {
-                        const int e = 8 * g + r;
-                        h->fitems.push_back(Item{0, e < ne ? h->sc.lvl_fwd[a0 + e] : -1, 1, k});
+            if (h->coupled) {
+                for (int k = 0; k < s; ++k) {
+                    const int l = wf - k;
+                    if (l < 0 || l >= L) continue;
+                    for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
+                        h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, k});
                         A.n++;
                     }
-            h->fa.push_back(A);
-            Launch B{(int)(W.items.size() + h->fitems.size()), 0};
-            if (h->coupled)
-                for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
-                    h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, 0});
-                    B.n++;
                 }
-            h->fb.push_back(B);
+            } else {
+                const int a0 = h->sc.off_fwd[wf], ne = h->sc.off_fwd[wf + 1] - a0;
+                for (int g = 0; g < (ne + 7) / 8; ++g)
+                    for (int k = 0; k < s; ++k)
+                        for (int r = 0; r < 8; ++r) {
+                            const int e = 8 * g + r;
+                            h->fitems.push_back(Item{0, e < ne ? h->sc.lvl_fwd[a0 + e] : -1, 1, k});
+                            A.n++;
+                        }
+            }
+            h->fa.push_back(A);
         }
     }
     if ((int)(W.items.size() + h->fitems.size()) > P.nitems_max) return IRK_ERR_ARG;
@@ -1115,7 +1124,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     if (o->pc != IRK_PC_NONE) {
         d.P64 = (double *)(ws + P.o_P64);
         d.Fscr = (double *)(ws + P.o_Fscr);
-        if (h->coupled) d.C64 = (double *)(ws + P.o_C64);
+        if (P.o_C64) d.C64 = (double *)(ws + P.o_C64);
         if (P.o_P32) d.P32 = (float *)(ws + P.o_P32);
         if (P.o_C32) d.C32 = (float *)(ws + P.o_C32);
         if (P.o_P16) { d.P16 = (uint16_t *)(ws + P.o_P16); d.P16e = (int *)(ws + P.o_P16e); }
@@ -1198,14 +1207,8 @@ irk_status irk_factor_ilu(irk_handle *h)
     HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
     hipEventRecord(h->ev0, h->stream);
     const int pf = prof_begin(h);
-    for (size_t l = 0; l < h->fa.size(); ++l) {
-        if (h->fa[l].n)
-            launch_factor(0, h->dsys, h->ditems + h->fa[l].off, h->fa[l].n, h->coupled, h->sharedJ,
-                          h->m, h->shm_fac, h->stream);
-        if (h->coupled && h->fb[l].n)
-            launch_factor(1, h->dsys, h->ditems + h->fb[l].off, h->fb[l].n, true, h->sharedJ,
-                          h->m, h->shm_fac, h->stream);
-    }
+    for (const Launch &F : h->fa)
+        launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->stream);
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
     prof_end(h, pf, PK_FACTOR);
     hipEventRecord(h->ev1, h->stream);
@@ -1326,7 +1329,7 @@ irk_status irk_export_factors(irk_handle *h, double *pinv, double *cross)
 {
     if (!h) return IRK_ERR_ARG;
     if (!h->factored || h->opt.pc == IRK_PC_NONE) return IRK_ERR_STATE;
-    launch_export(h->hsys, pinv, cross, h->stream);
+    launch_export(h->dsys, h->hsys, pinv, cross, h->coupled, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
     return IRK_OK;
 }
@@ -1905,10 +1908,11 @@ irk_status irk_batch_retire(irk_batch *b, long long *tags, irk_status *status, i
 namespace {
 
 // One group of handles for irk_factor_batched: the batch's table holds their
-// descriptors; the items are one per handle (flags), then, level by level
-// and for each launch class (coupled, shared J, factor class of m), the
-// level's factor tasks of every handle of that class.  Each handle's phase-0
-// tasks come in whole groups of eight, so every task keeps its XCD.
+// descriptors; the items are one per handle (flags), then, wavefront by
+// wavefront and for each launch class (coupled, shared J, factor class of
+// m), the wavefront's factor tasks of every handle of that class.  Each
+// uncoupled handle's tasks come in whole groups of eight, so every task
+// keeps its XCD.
 irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_status *status)
 {
     const int n = (int)hs.size();
@@ -1918,39 +1922,39 @@ irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_s
             HIPCHK(hipStreamWaitEvent(b->stream, h->ev_ready, 0));
         }
     for (int q = 0; q < n; ++q) b->htab[q] = hs[q]->hsys;
-    struct FL { int off, n, phase; bool coupled, sharedJ; int m; size_t shm; };
+    struct FL { int off, n; bool coupled, sharedJ; int m; size_t shm; };
     std::vector<Item> items;
     std::vector<FL> launches;
     for (int q = 0; q < n; ++q) items.push_back(Item{q, 0, 1, 0});
-    size_t levels = 0;
-    for (irk_handle *h : hs) levels = std::max(levels, h->fa.size());
+    size_t waves = 0;
+    for (irk_handle *h : hs) waves = std::max(waves, h->fa.size());
     std::vector<char> taken(n);
-    for (size_t l = 0; l < levels; ++l)
-        for (int phase = 0; phase < 2; ++phase) {
-            std::fill(taken.begin(), taken.end(), 0);
-            for (int q = 0; q < n; ++q) {
-                const irk_handle *h = hs[q];
-                if (taken[q] || l >= h->fa.size()) continue;
-                FL F{(int)items.size(), 0, phase, h->coupled, h->sharedJ, h->m, h->shm_fac};
-                for (int r = q; r < n; ++r) {
-                    const irk_handle *g = hs[r];
-                    if (taken[r] || l >= g->fa.size() || g->coupled != h->coupled ||
-                        g->sharedJ != h->sharedJ || factor_class(g->m) != factor_class(h->m))
-                        continue;
-                    taken[r] = 1;
-                    const Launch &L = phase == 0 ? g->fa[l] : g->fb[l];
-                    const size_t base = (size_t)L.off - g->W.items.size();
-                    for (int t = 0; t < L.n; ++t) {
-                        Item it = g->fitems[base + t];
-                        it.sys = r;
-                        items.push_back(it);
-                    }
-                    F.n += L.n;
-                    F.shm = std::max(F.shm, g->shm_fac);
+    // wavefront l of every handle, one launch per kernel class
+    for (size_t l = 0; l < waves; ++l) {
+        std::fill(taken.begin(), taken.end(), 0);
+        for (int q = 0; q < n; ++q) {
+            const irk_handle *h = hs[q];
+            if (taken[q] || l >= h->fa.size()) continue;
+            FL F{(int)items.size(), 0, h->coupled, h->sharedJ, h->m, h->shm_fac};
+            for (int r = q; r < n; ++r) {
+                const irk_handle *g = hs[r];
+                if (taken[r] || l >= g->fa.size() || g->coupled != h->coupled ||
+                    g->sharedJ != h->sharedJ || factor_class(g->m) != factor_class(h->m))
+                    continue;
+                taken[r] = 1;
+                const Launch &L = g->fa[l];
+                const size_t base = (size_t)L.off - g->W.items.size();
+                for (int t = 0; t < L.n; ++t) {
+                    Item it = g->fitems[base + t];
+                    it.sys = r;
+                    items.push_back(it);
                 }
-                if (F.n) launches.push_back(F);
+                F.n += L.n;
+                F.shm = std::max(F.shm, g->shm_fac);
             }
+            if (F.n) launches.push_back(F);
         }
+    }
     if (items.size() > b->max_items) return IRK_ERR_NOMEM;
     HIPCHK(hipMemcpyAsync(b->dtab, b->htab.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->ditems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice,
@@ -1958,7 +1962,7 @@ irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_s
     launch_reset_factor_flags(b->dtab, b->ditems, n, b->stream);
     HIPCHK(hipEventRecord(b->ev_f0, b->stream));
     for (const FL &F : launches)
-        launch_factor(F.phase, b->dtab, b->ditems + F.off, F.n, F.coupled, F.sharedJ, F.m, F.shm, b->stream);
+        launch_factor(b->dtab, b->ditems + F.off, F.n, F.coupled, F.sharedJ, F.m, F.shm, b->stream);
     for (irk_handle *h : hs)
         if (h->mixed && h->opt.pc != IRK_PC_NONE) launch_quantize(h->dsys, h->hsys, h->ftype, b->stream);
     HIPCHK(hipEventRecord(b->ev_f1, b->stream));

@@ -75,8 +75,9 @@ struct SysDesc {
     // operator values
     const double *Jc;  const double *Mc;      // col-major blocks, ld
     const float *Jc32; const float *Mc32;     // col-major blocks, ld32
-    // factors: pivots [T][s] blocks, cross [T][s][s-1] blocks ("column k"
-    // group holds C_{lk}, l != k, in ascending l)
+    // factors: pivots [T][s] blocks (inverted); cross blocks C_{lq} with
+    // l, q >= 1, l != q: [T][s-1][s-2] blocks, group q - 1 holding C_{lq} in
+    // ascending l (the ones in stage row or column 0 are A^{-1}_lq M)
     double *P64; double *C64;                 // ld
     float *P32;  float *C32;                  // ld32
     uint16_t *P16; uint16_t *C16;             // ld16
@@ -116,12 +117,13 @@ __host__ __device__ inline int matvec_region(int S, int m, int maxrow, int ld, i
 }
 // sweep: gather of the neighbours' stage vectors [S][maxrow*m], reused for
 // the [G][S][ld] partial sums of the Jacobian and factor products, then the
-// y and u vectors [S][round_up(m, 8)] of one element
+// y and u vectors [S][round_up(m, 8)] of one element and one more vector
+// (the stage-0 combination of the coupled backward sweep)
 __host__ __device__ inline int sweep_region(int S, int m, int maxrow, int team, int ldJ, int VJ,
                                             int ldF, int VF) {
     const int GJ = team / (ldJ / VJ), GF = team / (ldF / VF);
     const int r = imax(S * maxrow * m, imax(GJ * S * ldJ, GF * S * ldF));
-    return r + 2 * S * round_up(m, 8);
+    return r + (2 * S + 1) * round_up(m, 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,14 +183,14 @@ void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nre
                   int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
                   hipStream_t st, bool prefetch);
 
-// Factorization of one level.  phase 0: tasks (stage k = aux, element) build
-// P_{k,i} (and invert it when !coupled; set up cross blocks of column k when
-// coupled).  phase 1 (coupled): tasks = elements, sequential stage rounds.
-// The kernels are chosen by the block order m (all systems of one launch
-// share its class, factor_class(m)): four-wave workgroups for m <= 64,
-// eight-wave ones above.
-void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems,
-                   bool coupled, bool sharedJ, int m, size_t shmem, hipStream_t st);
+// One wavefront of the factorization: tasks (stage k = aux, element =
+// first) build P_{k,i} from the neighbour terms, invert it, and (coupled)
+// run the stage round on the element's later stages (k_factor.hip).  The
+// kernels are chosen by the block order m (all systems of one launch share
+// its class, factor_class(m)): four-wave workgroups for m <= 64, eight-wave
+// ones above.
+void launch_factor(const SysDesc *dsys, const Item *items, int nitems, bool coupled, bool sharedJ, int m,
+                   size_t shmem, hipStream_t st);
 int factor_class(int m);
 
 // Quantize nblk column-major blocks (leading dimensions ld in, ldq out).
@@ -227,7 +229,8 @@ void launch_reset_state(const SysDesc *dsys, const Item *fin, int nfin, hipStrea
 // the factorization's flags (singular pivot, non-finite value) to zero
 void launch_reset_factor_flags(const SysDesc *dsys, const Item *fin, int nfin, hipStream_t st);
 // export FP64 factors to the caller's row-major stage-major layout
-void launch_export(const SysDesc &hsys, double *pinv, double *cross, hipStream_t st);
+void launch_export(const SysDesc *dsys, const SysDesc &hsys, double *pinv, double *cross, bool coupled,
+                   hipStream_t st);
 void factor_set_lds_limit(size_t bytes);
 
 }  // namespace irk

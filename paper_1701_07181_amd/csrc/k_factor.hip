@@ -1,4 +1,5 @@
-// k_factor.hip -- level-scheduled block ILU(0) factorization in FP64
+// k_factor.hip -- block ILU(0) factorization in FP64, stage by stage and
+// level by level
 //
 // Triangle-free meshes (Sec. 4.2.1, Alg. 2): only pivot blocks change.
 // For stage k of element i (all lower neighbours j < i already final):
@@ -12,16 +13,23 @@
 //
 //     L = C_{lk,i} P_{k,i}^{-1};   P_{l,i} -= L C_{kl,i};   C_{lq,i} -= L C_{kq,i} (q > k, q != l)
 //
-// with C_{kl,i} starting at A^{-1}_kl M_i.  Element-major processing (all
-// stages of an element inside one task, elements level by level) reaches
-// every pivot after its dependencies, so both forms use the same level
-// schedule.  Pivots are stored inverted (Gauss-Jordan with partial pivoting)
-// because the sweeps apply them as matrix-vector products.
+// with C_{kl,i} starting at A^{-1}_kl M_i.  Pivot (0, i) is eliminated first,
+// so every cross block in stage row 0 or stage column 0 keeps its starting
+// value A^{-1}_kl M_i: those are never stored (the sweeps apply M_i and the
+// scalar), and the first round collapses to one product X = M_i P_0^{-1} M_i:
 //
-// Tasks: phase 0 -- one workgroup per (stage k, element i): builds P_{k,i}
-// (and inverts it for the uncoupled forms; sets the cross blocks of stage
-// column k for the coupled form).  Phase 1 (coupled only) -- one workgroup
-// per element: the stage rounds above.
+//     P_{l,i} = d_l M_i - dt J_{l,ii} - A^{-1}_l0 A^{-1}_0l X,
+//     C_{lq,i} = A^{-1}_lq M_i - A^{-1}_l0 A^{-1}_0q X        (l, q >= 1).
+//
+// Schedule.  A task is (stage k, element i).  Its pivot needs the same stage
+// of the lower neighbours (earlier levels) and the earlier stages of its own
+// element, so task (k, i) runs in wavefront level(i) + k: L + s - 1 launches
+// for L levels (the uncoupled forms need none of the stage order: wavefront
+// = level).  A task adds the neighbour terms to P_{k,i} (stage 0 and the
+// uncoupled forms start it from d_k M_i - dt J_{k,ii}; later coupled stages
+// from the value the earlier rounds left), inverts it in place (pivots are
+// stored inverted because the sweeps apply them as matrix-vector products),
+// and runs its stage round on the later stages of the element.
 #include "irk_device.h"
 #include "dense64.h"
 
@@ -54,13 +62,14 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
     if (threadIdx.x == 0) atomicCAS(&d.st->singular, 0, elem + 1);
 }
 
-// Phase 0 for m <= 64 with the products fused: the accumulators of P_{k,i}
-// stay in registers from d_k M_i - dt J_ii through every lower neighbour j,
-// and X = -dt^2 P_j^{-1} J_ji passes through LDS (64 x 66 doubles) into
+// Neighbour terms for m <= 64 with the products fused: the accumulators of
+// P_{k,i} stay in registers from their starting value (d_k M_i - dt J_ii, or
+// the stored P_{k,i} when from_p) through every lower neighbour j, and
+// X = -dt^2 P_j^{-1} J_ji passes through LDS (64 x 66 doubles) into
 // P_{k,i} += J_ij X; P_{k,i} is written once.
 template <bool FULL>
-__device__ __forceinline__ void factor_a_small_products(const SysDesc &d, int i, int k, const double *Jk,
-                                                        double *Pk, double *Xs)
+__device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, int k, const double *Jk,
+                                                      double *Pk, bool from_p, double *Xs)
 {
     const int s = d.s, lane = threadIdx.x & 63, w = wave_id();
     int m = d.m, ld = d.ld;
@@ -72,6 +81,7 @@ __device__ __forceinline__ void factor_a_small_products(const SysDesc &d, int i,
     const bool act = nx > 0 && ny > 0;
     const GAS double *Mi = gp(d.Mc + (long long)i * bs);
     const GAS double *Jd = gp(Jk + (long long)diag_pos[i] * bs);
+    const GAS double *Ps = gp(Pk);
     dbl4 acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -81,7 +91,7 @@ __device__ __forceinline__ void factor_a_small_products(const SysDesc &d, int i,
             for (int q = 0; q < 4; ++q) {
                 const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
                 const size_t e = (size_t)min(c, m - 1) * ld + min(r, m - 1);
-                acc[x][y][q] = dk * Mi[e] - dt * Jd[e];
+                acc[x][y][q] = from_p ? Ps[e] : dk * Mi[e] - dt * Jd[e];
             }
     const int p0 = row_ptr[i], pd = diag_pos[i];
     for (int p = p0; p < pd; ++p) {
@@ -110,6 +120,7 @@ __device__ __forceinline__ void factor_a_small_products(const SysDesc &d, int i,
         __syncthreads();
         if (act) d64_accum<FULL, true, 2>(acc, m, ld, gp(Jk + (long long)p * bs), nullptr, Xs, nx, ny);
     }
+    __syncthreads();                              // every wave has read the stored P_{k,i}
     if (act) {
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -126,9 +137,22 @@ __device__ __forceinline__ void factor_a_small_products(const SysDesc &d, int i,
     __syncthreads();
 }
 
+// Stored cross block C_{lq,i} (l, q >= 1, l != q): group q, entry l.
+__device__ __forceinline__ double *cross_blk(const SysDesc &d, long long i, int l, int q)
+{
+    const int s = d.s;
+    const long long bs = (long long)d.m * d.ld;
+    const int e = (q - 1) * (s - 2) + (l < q ? l - 1 : l - 2);
+    return d.C64 + (i * (s - 1) * (s - 2) + e) * bs;
+}
+
+// One task: stage k of element i (see the file comment).  The products of a
+// task are one operation list (the neighbour products for m > 64, then the
+// stage round), so a kernel holds one inlined copy of the product and one of
+// the inverse.
 template <bool COUPLED, bool SHJ, int CLS>
-__device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
-                                              const Item *__restrict__ items, double *lds)
+__device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sysv,
+                                                 const Item *__restrict__ items, double *lds)
 {
     constexpr int TEAM = team_of<CLS>();
     const Item it = items[blockIdx.x];
@@ -137,160 +161,132 @@ __device__ __forceinline__ void factor_a_body(const SysDesc *__restrict__ sysv,
     const int s = d.s, m = d.m, ld = d.ld;
     const int i = it.first, k = it.aux;
     const long long bs = (long long)m * ld;
-    double *Pk = d.P64 + ((long long)i * s + k) * bs;
-    const double *Jk = d.Jc + (SHJ ? 0 : (long long)k * d.nnzb * bs);
+    auto P = [&](int q) { return d.P64 + ((long long)i * s + q) * bs; };
+    auto Jst = [&](int q) { return d.Jc + (SHJ ? 0 : (long long)q * d.nnzb * bs); };
+    double *Pk = P(k);
+    const double *Jk = Jst(k);
     const double *Mi = d.Mc + (long long)i * bs;
     const GAS int *diag_pos = gp(d.diag_pos), *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx),
                   *tpos = gp(d.tpos);
-    const double *Jd = Jk + (long long)diag_pos[i] * bs;
-    const double dk = d.dcoef[k], dt = d.dt;
-    if (CLS != 0)
-        for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
-    if (COUPLED) {
-        // column k of the cross blocks: C_{lk,i} = A^{-1}_lk M_i (l != k)
-        for (int l = 0; l < s; ++l) {
-            if (l == k) continue;
-            const int idx = l < k ? l : l - 1;
-            double *Cl = d.C64 + (((long long)i * s + k) * (s - 1) + idx) * bs;
-            const double al = d.Ainv[l * SMAX + k];
-            for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Cl)[e] = al * gp(Mi)[e];
-        }
-    }
-    if (CLS == 0) {
-        if (m > 56) factor_a_small_products<true>(d, i, k, Jk, Pk, lds);
-        else factor_a_small_products<false>(d, i, k, Jk, Pk, lds);
-        if (!COUPLED) {
-            if (blk_inverse<CLS>(Pk, m, ld, lds)) flag_singular(d, i);
-        }
-        return;
-    }
-    __syncthreads();
-    double *X = d.Fscr + ((long long)i * s + k) * bs;
+    const double dt = d.dt;
+    // later coupled stages start from what the earlier rounds left in P_{k,i}
+    const bool from_p = COUPLED && k > 0;
     const int p0 = row_ptr[i], pd = diag_pos[i];
-    // per lower neighbour j: X = -dt^2 P_j^{-1} J_ji, then P_k += J_ij X
-    for (int t = 2 * p0; t < 2 * pd; ++t) {
-        const int p = t >> 1;
-        const bool second = t & 1;
-        const long long j = col_idx[p];
-        const double *A = second ? Jk + (long long)p * bs : d.P64 + (j * s + k) * bs;
-        const double *B = second ? X : Jk + (long long)tpos[p] * bs;
-        blk_gemm<CLS>(m, ld, second ? 1.0 : -dt * dt, A, B, second, second ? Pk : X, lds);
+    const int nnb = (CLS == 0) ? 0 : 2 * (pd - p0);   // neighbour products (m > 64)
+    if (CLS == 0) {
+        if (m > 56) factor_small_products<true>(d, i, k, Jk, Pk, from_p, lds);
+        else factor_small_products<false>(d, i, k, Jk, Pk, from_p, lds);
+    } else if (!from_p) {
+        const double *Jd = Jk + (long long)diag_pos[i] * bs;
+        const double dk = d.dcoef[k];
+        for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];
+        __syncthreads();
     }
-    if (!COUPLED) {
-        if (blk_inverse<CLS>(Pk, m, ld, lds)) flag_singular(d, i);
+    // stage round: k = 0 -> L = M P_0^{-1}, X = L M; k >= 1 -> for every
+    // later stage l: L = C_lk P_k^{-1}, P_l -= L C_kl, C_lq -= L C_kq
+    const bool round = COUPLED && k + 1 < s;
+    const int w = s - k;
+    const int nround = !round ? 0 : (k == 0 ? 2 : (s - 1 - k) * w);
+    double *L = d.Fscr + ((long long)i * s + k) * bs;
+    double *X = d.Fscr + ((long long)i * s + (k + 1) % s) * bs;
+    const int ntot = nnb + nround;
+    for (int t = 0; t <= ntot; ++t) {
+        // every neighbour term is in: invert the pivot block in place
+        if (t == nnb && blk_inverse<CLS>(Pk, m, ld, lds)) flag_singular(d, i);
+        if (t == ntot) break;
+        const double *A, *B;
+        double *D;
+        double al;
+        bool add;
+        if (t < nnb) {
+            // per lower neighbour j: X = -dt^2 P_j^{-1} J_ji, then P_k += J_ij X
+            const int p = p0 + (t >> 1);
+            const bool second = t & 1;
+            const long long j = col_idx[p];
+            A = second ? Jk + (long long)p * bs : d.P64 + (j * s + k) * bs;
+            B = second ? X : Jk + (long long)tpos[p] * bs;
+            D = second ? Pk : X;
+            al = second ? 1.0 : -dt * dt;
+            add = second;
+        } else if (k == 0) {
+            const int u = t - nnb;
+            A = u ? L : Mi;
+            B = u ? Mi : Pk;
+            D = u ? X : L;
+            al = 1.0;
+            add = false;
+        } else {
+            // w operations per later stage l, q = k .. s-1: q = k -> L = C_lk P_k^{-1};
+            // q = l -> P_l -= L C_kl; other q -> C_lq -= L C_kq
+            const int u = t - nnb;
+            const int l = k + 1 + u / w, q = k + u % w;
+            if (q == k) { A = cross_blk(d, i, l, k); B = Pk; D = L; al = 1.0; add = false; }
+            else if (q == l) { A = L; B = cross_blk(d, i, k, l); D = P(l); al = -1.0; add = true; }
+            else { A = L; B = cross_blk(d, i, k, q); D = cross_blk(d, i, l, q); al = -1.0; add = true; }
+        }
+        blk_gemm<CLS>(m, ld, al, A, B, add, D, lds);
     }
-}
-
-template <bool SHJ, int CLS>
-__device__ __forceinline__ void factor_b_body(const SysDesc *__restrict__ sysv,
-                                              const Item *__restrict__ items, double *lds)
-{
-    constexpr int TEAM = team_of<CLS>();
-    const Item it = items[blockIdx.x];
-    const SysDesc &d = sysv[it.sys];
-    const int s = d.s, m = d.m, ld = d.ld, sm1 = s - 1;
-    const int i = it.first;
-    const long long bs = (long long)m * ld;
-    auto P = [&](int k) { return d.P64 + ((long long)i * s + k) * bs; };
-    // C_{row,col}: column group col, index of row within it
-    auto C = [&](int row, int col) {
-        const int idx = row < col ? row : row - 1;
-        return d.C64 + (((long long)i * s + col) * sm1 + idx) * bs;
-    };
-    double *L = d.Fscr + ((long long)i * s) * bs;
-    double *X = d.Fscr + ((long long)i * s + 1) * bs;
-    const double *Mi = d.Mc + (long long)i * bs;
-    for (int k = 0; k < s; ++k) {
-        if (blk_inverse<CLS>(P(k), m, ld, lds)) flag_singular(d, i);
-        // k = 0: every cross block is still A^{-1}_kl M_i; with
-        //   L = M_i P_0^{-1},  X = L M_i:
-        //   P_l -= A^{-1}_l0 A^{-1}_0l X,   C_lq -= A^{-1}_l0 A^{-1}_0q X.
-        // k > 0, for every later stage l (q runs over k, k+1, .., s-1):
-        //   q = k:  L = C_lk P_k^{-1};  q = l:  P_l -= L C_kl;  else  C_lq -= L C_kq
-        const int w = s - k;
-        const int nops = (k == 0) ? 2 : (s - 1 - k) * w;
-        for (int t = 0; t < nops; ++t) {
-            const double *A, *B;
-            double *D;
-            double al;
-            bool add;
-            if (k == 0) {
-                A = t ? L : Mi;
-                B = t ? Mi : P(0);
-                D = t ? X : L;
-                al = 1.0;
-                add = false;
-            } else {
-                const int l = k + 1 + t / w, q = k + t % w;
-                if (q == k) { A = C(l, k); B = P(k); D = L; al = 1.0; add = false; }
-                else { A = L; B = C(k, q); D = (q == l) ? P(l) : C(l, q); al = -1.0; add = true; }
+    if (round && k == 0) {
+        // later stages' pivots and the stored cross blocks from X = M P_0^{-1} M
+        for (int l = 1; l < s; ++l) {
+            const double *Jd = Jst(l) + (long long)diag_pos[i] * bs;
+            const double dl = d.dcoef[l], fl = d.Ainv[l * SMAX] * d.Ainv[l];
+            double *Pl = P(l);
+            // (padding rows r >= m of a block stay zero: X holds only rows < m)
+            for (long long e = threadIdx.x; e < bs; e += TEAM)
+                gp(Pl)[e] = (e % ld < m) ? dl * gp(Mi)[e] - dt * gp(Jd)[e] - fl * gp(X)[e] : 0.0;
+            for (int q = 1; q < s; ++q) {
+                if (q == l) continue;
+                double *Cq = cross_blk(d, i, l, q);
+                const double a = d.Ainv[l * SMAX + q], f = d.Ainv[l * SMAX] * d.Ainv[q];
+                for (long long e = threadIdx.x; e < bs; e += TEAM)
+                    gp(Cq)[e] = (e % ld < m) ? a * gp(Mi)[e] - f * gp(X)[e] : 0.0;
             }
-            blk_gemm<CLS>(m, ld, al, A, B, add, D, lds);
         }
-        if (k == 0) {
-            for (int l = 1; l < s; ++l)
-                for (int q = 1; q < s; ++q) {
-                    double *D = (q == l) ? P(l) : C(l, q);
-                    const double f = d.Ainv[l * SMAX + 0] * d.Ainv[0 * SMAX + q];
-                    for (long long e = threadIdx.x; e < bs; e += TEAM) gp(D)[e] -= f * gp(X)[e];
-                }
-            __syncthreads();
-        }
+        __syncthreads();
     }
 }
 
 template <bool COUPLED, bool SHJ, int CLS>
-__global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_a(const SysDesc *__restrict__ sysv,
-                                                                          const Item *__restrict__ items)
+__global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_task(const SysDesc *__restrict__ sysv,
+                                                                             const Item *__restrict__ items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_a_body<COUPLED, SHJ, CLS>(sysv, items, reinterpret_cast<double *>(smem_raw));
-}
-template <bool SHJ, int CLS>
-__global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_b(const SysDesc *__restrict__ sysv,
-                                                                          const Item *__restrict__ items)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_b_body<SHJ, CLS>(sysv, items, reinterpret_cast<double *>(smem_raw));
+    factor_task_body<COUPLED, SHJ, CLS>(sysv, items, reinterpret_cast<double *>(smem_raw));
 }
 
 template <int CLS>
-static void launch_factor_t(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
-                            bool sharedJ, size_t shmem, hipStream_t st)
+static void launch_factor_t(const SysDesc *dsys, const Item *items, int nitems, bool coupled, bool sharedJ,
+                            size_t shmem, hipStream_t st)
 {
     dim3 grid(nitems), block(team_of<CLS>());
-    if (phase == 0) {
-        if (coupled) {
-            if (sharedJ) hipLaunchKernelGGL((k_factor_a<true, true, CLS>), grid, block, shmem, st, dsys, items);
-            else hipLaunchKernelGGL((k_factor_a<true, false, CLS>), grid, block, shmem, st, dsys, items);
-        } else {
-            if (sharedJ) hipLaunchKernelGGL((k_factor_a<false, true, CLS>), grid, block, shmem, st, dsys, items);
-            else hipLaunchKernelGGL((k_factor_a<false, false, CLS>), grid, block, shmem, st, dsys, items);
-        }
+    if (coupled) {
+        if (sharedJ) hipLaunchKernelGGL((k_factor_task<true, true, CLS>), grid, block, shmem, st, dsys, items);
+        else hipLaunchKernelGGL((k_factor_task<true, false, CLS>), grid, block, shmem, st, dsys, items);
     } else {
-        if (sharedJ) hipLaunchKernelGGL((k_factor_b<true, CLS>), grid, block, shmem, st, dsys, items);
-        else hipLaunchKernelGGL((k_factor_b<false, CLS>), grid, block, shmem, st, dsys, items);
+        if (sharedJ) hipLaunchKernelGGL((k_factor_task<false, true, CLS>), grid, block, shmem, st, dsys, items);
+        else hipLaunchKernelGGL((k_factor_task<false, false, CLS>), grid, block, shmem, st, dsys, items);
     }
 }
 
 int factor_class(int m) { return m <= 64 ? 0 : (m <= 128 ? 2 : 3); }
 
-void launch_factor(int phase, const SysDesc *dsys, const Item *items, int nitems, bool coupled,
-                   bool sharedJ, int m, size_t shmem, hipStream_t st)
+void launch_factor(const SysDesc *dsys, const Item *items, int nitems, bool coupled, bool sharedJ, int m,
+                   size_t shmem, hipStream_t st)
 {
+    if (nitems <= 0) return;
     switch (factor_class(m)) {
-    case 0: launch_factor_t<0>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st); break;
-    case 2: launch_factor_t<2>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st); break;
-    default: launch_factor_t<3>(phase, dsys, items, nitems, coupled, sharedJ, shmem, st); break;
+    case 0: launch_factor_t<0>(dsys, items, nitems, coupled, sharedJ, shmem, st); break;
+    case 2: launch_factor_t<2>(dsys, items, nitems, coupled, sharedJ, shmem, st); break;
+    default: launch_factor_t<3>(dsys, items, nitems, coupled, sharedJ, shmem, st); break;
     }
 }
 
 template <int CLS>
 static void set_lds_limit_t(int b)
 {
-    const void *k[] = {(const void *)k_factor_a<true, true, CLS>, (const void *)k_factor_a<true, false, CLS>,
-                       (const void *)k_factor_a<false, true, CLS>, (const void *)k_factor_a<false, false, CLS>,
-                       (const void *)k_factor_b<true, CLS>, (const void *)k_factor_b<false, CLS>};
+    const void *k[] = {(const void *)k_factor_task<true, true, CLS>, (const void *)k_factor_task<true, false, CLS>,
+                       (const void *)k_factor_task<false, true, CLS>, (const void *)k_factor_task<false, false, CLS>};
     for (const void *f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
 }
 
@@ -401,7 +397,7 @@ void launch_quantize(const SysDesc *dsys, const SysDesc &h, int ftype, hipStream
 {
     (void)dsys;
     const long long np = (long long)h.T * h.s;
-    const long long nc = (h.C64 != nullptr) ? (long long)h.T * h.s * (h.s - 1) : 0;
+    const long long nc = (h.C64 != nullptr) ? (long long)h.T * (h.s - 1) * (h.s - 2) : 0;
     if (ftype == FT_F32) {
         quantize_blocks(h.P64, h.P32, nullptr, np, h.m, h.ld, h.ld32, ftype, st);
         if (nc) quantize_blocks(h.C64, h.C32, nullptr, nc, h.m, h.ld, h.ld32, ftype, st);
@@ -413,25 +409,15 @@ void launch_quantize(const SysDesc *dsys, const SysDesc &h, int ftype, hipStream
 
 // ---------------------------------------------------------------------------
 // export of the FP64 factors to the caller's layout (row-major blocks):
-// pinv [s][T][m][m], cross [s][s][T][m][m] (C_{kl,i} at (k, l, i)).
+// pinv [s][T][m][m], cross [s][s][T][m][m] (C_{kl,i} at (k, l, i); those in
+// stage row or column 0 are A^{-1}_kl M_i, the others the stored blocks).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHREADS) void k_export(const double *__restrict__ src, double *dst,
-                                                     int s, int T, int m, int ld, int cross)
+__global__ __launch_bounds__(NTHREADS) void k_export_pivots(const double *__restrict__ src, double *dst,
+                                                            int s, int T, int m, int ld)
 {
-    const long long b = blockIdx.x;   // source block index
-    long long o;
-    if (!cross) {
-        const long long i = b / s, k = b - i * s;
-        o = (k * T + i) * (long long)m * m;
-    } else {
-        const int sm1 = s - 1;
-        const long long ik = b / sm1;
-        const int idx = (int)(b - ik * sm1);
-        const long long i = ik / s;
-        const int col = (int)(ik - i * s);
-        const int row = idx < col ? idx : idx + 1;
-        o = (((long long)row * s + col) * T + i) * (long long)m * m;
-    }
+    const long long b = blockIdx.x;   // source block (element i, stage k)
+    const long long i = b / s, k = b - i * s;
+    const long long o = (k * T + i) * (long long)m * m;
     const double *S = src + b * (long long)m * ld;
     for (int e = threadIdx.x; e < m * m; e += NTHREADS) {
         const int r = e / m, c = e - r * m;
@@ -439,14 +425,37 @@ __global__ __launch_bounds__(NTHREADS) void k_export(const double *__restrict__ 
     }
 }
 
-void launch_export(const SysDesc &h, double *pinv, double *cross, hipStream_t st)
+// one workgroup per (element i, stage pair k != l)
+__global__ __launch_bounds__(NTHREADS) void k_export_cross(const SysDesc *__restrict__ dsys, double *dst)
+{
+    const SysDesc &d = *dsys;
+    const int s = d.s, T = d.T, m = d.m, ld = d.ld;
+    const long long b = blockIdx.x;
+    const long long i = b / (s * (s - 1));
+    const int pr = (int)(b - i * s * (s - 1));
+    const int k = pr / (s - 1), lr = pr - k * (s - 1), l = lr < k ? lr : lr + 1;
+    const long long o = (((long long)k * s + l) * T + i) * (long long)m * m;
+    const long long bs = (long long)m * ld;
+    const bool mass = (k == 0 || l == 0);
+    const double a = d.Ainv[k * SMAX + l];
+    const double *S = mass ? d.Mc + i * bs
+                           : d.C64 + (i * (s - 1) * (s - 2) + (l - 1) * (s - 2) + (k < l ? k - 1 : k - 2)) * bs;
+    for (int e = threadIdx.x; e < m * m; e += NTHREADS) {
+        const int r = e / m, c = e - r * m;
+        const double v = S[(long long)c * ld + r];
+        dst[o + e] = mass ? a * v : v;
+    }
+}
+
+void launch_export(const SysDesc *dsys, const SysDesc &h, double *pinv, double *cross, bool coupled,
+                   hipStream_t st)
 {
     if (pinv)
-        hipLaunchKernelGGL(k_export, dim3((unsigned)((long long)h.T * h.s)), dim3(NTHREADS), 0, st,
-                           (const double *)h.P64, pinv, h.s, h.T, h.m, h.ld, 0);
-    if (cross && h.C64 && h.s > 1)
-        hipLaunchKernelGGL(k_export, dim3((unsigned)((long long)h.T * h.s * (h.s - 1))), dim3(NTHREADS),
-                           0, st, (const double *)h.C64, cross, h.s, h.T, h.m, h.ld, 1);
+        hipLaunchKernelGGL(k_export_pivots, dim3((unsigned)((long long)h.T * h.s)), dim3(NTHREADS), 0, st,
+                           (const double *)h.P64, pinv, h.s, h.T, h.m, h.ld);
+    if (cross && coupled && h.s > 1)
+        hipLaunchKernelGGL(k_export_cross, dim3((unsigned)((long long)h.T * h.s * (h.s - 1))), dim3(NTHREADS),
+                           0, st, dsys, cross);
 }
 
 }  // namespace irk

@@ -14,6 +14,13 @@
 //       z_{k,i} = y^_{k,i} + P_{k,i}^{-1} ( dt sum_{j>i} J_ij z_{k,j}
 //                                           - sum_{l>k} C_{kl,i} z_{l,i} )
 //
+// Pivot (0, i) is eliminated first, so the cross blocks in stage row or
+// column 0 keep their starting value A^{-1}_kl M_i and are not stored: the
+// forward round of stage 0 applies M_i once (t = M_i y^_0, y_l -= A^{-1}_l0 t
+// for every l >= 1), and the backward sweep gathers the stage-0 couplings
+// into a = sum_{l>=1} A^{-1}_0l z_l and applies M_i once before the stage-0
+// pivot.  The stored cross blocks are the C_{lk,i} with l, k >= 1.
+//
 // Elements of one level are independent; a team of threads handles one
 // element and all s stages of it: the shared Jacobian blocks of the
 // element's row are streamed once and applied to the s stage vectors, then
@@ -151,8 +158,9 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     const int maxg = d.maxrow * m;
     TC *base_lds = reinterpret_cast<TC *>(smem_raw) + (size_t)tm * region;
     TC *xg = base_lds;                       // gather, then partials
-    TC *yv = base_lds + (region - 2 * S * ldv);   // [S][ldv]
+    TC *yv = base_lds + (region - (2 * S + 1) * ldv);   // [S][ldv]
     TC *uv = yv + S * ldv;                   // [S][ldv]
+    TC *av = uv + S * ldv;                   // [ldv]: backward stage-0 combination
 
     const long long n = (long long)T * m;
     const int i = rec.i;
@@ -162,7 +170,6 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     const auto Pb = piv_of<TF>(d);
     const auto Cb = cross_of<TF>(d);
     const long long bsF = (long long)m * ldF;
-    const int sm1 = s - 1;
     const bool fact = has && gF < GF;
 
     const int pa = rec.pa, ncol = rec.nb * m;
@@ -197,7 +204,14 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     // ---- prefetch: Jacobian row (first QJ column loads), pivots, cross blocks ----
     TC rJ[QJ][VJ];
     TC rP[S][NQ][VF];
-    TC rC[S][S][NQ][VF];   // [k][l]: block C_{lk} used by round k
+    TC rC[S][S][NQ][VF];   // [k][l]: stored block C_{lk} (l, k >= 1) used by round k
+    constexpr int NQJ = 8 / VJ;                     // prefetched column pieces of M_i
+    TC rM[NQJ][VJ];
+    const auto Mb = mass_of<TJ>(d) + (size_t)ic * m * ldJ + sJ * VJ;
+    // stored cross block C_{lk,i} (l, k >= 1): group k - 1, entry l
+    auto cross_idx = [&](long long e, int l, int k) {
+        return e * (s - 1) * (s - 2) + (long long)(k - 1) * (s - 2) + (l < k ? l - 1 : l - 2);
+    };
     if (PF) {
         if (SHJ) {
             const auto jrow_c = Jb + (size_t)min(pa, d.nnzb - 1) * m * ldJ + sJ * VJ;
@@ -211,17 +225,18 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
         for (int k = 0; k < S; ++k) {
             const int kc = min(k, s - 1);
             prefetch_block<TF, TC, NQ>(Pb + (ic * s + kc) * bsF + sF * VF, ldF, m, gF, GF, rP[k]);
-            if (COUPLED) {
+            if (COUPLED && S > 2 && s > 2) {
 #pragma unroll
-                for (int l = 0; l < S; ++l) {
-                    if (l == k || (FWD ? (l < k) : (l > k))) continue;
-                    const int lc = min(l, s - 1);
-                    const int idx = max(0, min(lc < kc ? lc : lc - 1, sm1 - 1));
-                    prefetch_block<TF, TC, NQ>(Cb + ((ic * s + kc) * sm1 + idx) * bsF + sF * VF,
-                                               ldF, m, gF, GF, rC[k][l]);
+                for (int l = 1; l < S; ++l) {
+                    if (l == k || k == 0 || (FWD ? (l < k) : (l > k))) continue;
+                    // clamped into this system's stored blocks (s may be below S)
+                    const int lc = min(l, s - 1), kk2 = max(1, min(k, s - 1));
+                    const long long ci = (s > 2 && lc != kk2) ? cross_idx(ic, lc, kk2) : 0;
+                    prefetch_block<TF, TC, NQ>(Cb + ci * bsF + sF * VF, ldF, m, gF, GF, rC[k][l]);
                 }
             }
         }
+        if (COUPLED) prefetch_block<TJ, TC, NQJ>(Mb, ldJ, m, gJ, GJ, rM);
     }
 
     // ---- gather: first pass stores, entries beyond it (more than a team's
@@ -374,10 +389,38 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     }
 
     // ---- coupled: stage rounds inside the element ----
+    // mass step (Jacobian-block layout): t = M_i vin; forward: y_l -= A^{-1}_l0 t
+    // for every later stage; backward: u_0 -= t
+    auto mass_step = [&](const TC *vin, bool act) {
+        TC am[VJ];
+#pragma unroll
+        for (int v = 0; v < VJ; ++v) am[v] = 0;
+        if (act && gJ < GJ) {
+            col_product<TJ, TC, NQJ, PF>(Mb, ldJ, m, gJ, GJ, rM, vin, am);
+#pragma unroll
+            for (int v = 0; v < VJ; ++v) red[gJ * ldJ + sJ * VJ + v] = am[v];
+        }
+        __syncthreads();
+        if (act) {
+            for (int r = tid; r < m; r += team) {
+                const TC t = sum_strided(red + r, GJ, ldJ);
+                if (FWD) {
+#pragma unroll
+                    for (int l = 1; l < S; ++l)
+                        if (l < s) yv[l * ldv + r] -= (TC)d.Ainv[l * SMAX] * t;
+                } else {
+                    uv[r] -= t;
+                }
+            }
+        }
+        __syncthreads();
+    };
 #pragma unroll
     for (int kk = 0; kk < S; ++kk) {
         const int k = FWD ? kk : (S - 1 - kk);
         const bool act = has && k < s;
+        // backward, stage 0: the stage-0 couplings u_0 -= M_i sum_{l>=1} A^{-1}_0l z_l
+        if (!FWD && k == 0 && S > 1) mass_step(av, has && s > 1);
         // (a) pivot product of stage k
         {
             const TC *in = FWD ? yv : uv;
@@ -393,6 +436,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
             __syncthreads();
             if (act) {
                 const TC sc = block_scale<TF, TC>(d.P16e, (long long)i * s + k);
+                const TC a0k = (TC)d.Ainv[k];
                 for (int r = tid; r < m; r += team) {
                     TC o = sum_strided(red + r, GF, ldF);
                     o *= sc;
@@ -401,34 +445,37 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
                     yh[gi] = o;
                     if (!FWD && acc) acc[gi] += (double)o;
                     yv[k * ldv + r] = o;   // y^_k (forward) or z_k (backward) for the cross terms
+                    // backward: a = sum over the stages done so far of A^{-1}_0k z_k
+                    if (!FWD && k > 0) av[r] = (k == s - 1) ? a0k * o : av[r] + a0k * o;
                 }
             }
             __syncthreads();
         }
         // (b) cross-stage update of the stages not yet done:
-        //     forward: y_l -= C_{lk} y^_k (l > k);  backward: u_l -= C_{lk} z_k (l < k)
-        if (kk + 1 < S) {
-            if (act && gF < GF) {
+        //     forward: y_l -= C_{lk} y^_k (l > k);  backward: u_l -= C_{lk} z_k (1 <= l < k)
+        if (FWD && k == 0 && S > 1) {
+            mass_step(yv, has && s > 1);
+        } else if (S > 2 && k >= 1 && (FWD ? k + 1 < S : k > 1)) {
+            const bool cact = act && s > 2;
+            if (cact && gF < GF) {
 #pragma unroll
-                for (int l = 0; l < S; ++l) {
+                for (int l = 1; l < S; ++l) {
                     if (l >= s || l == k || (FWD ? (l < k) : (l > k))) continue;
-                    const int idx = l < k ? l : l - 1;
                     TC ac[VF];
 #pragma unroll
                     for (int v = 0; v < VF; ++v) ac[v] = 0;
-                    col_product<TF, TC, NQ, PF>(Cb + (((long long)i * s + k) * sm1 + idx) * bsF + sF * VF,
+                    col_product<TF, TC, NQ, PF>(Cb + cross_idx(i, l, k) * bsF + sF * VF,
                                                 ldF, m, gF, GF, rC[k][l], yv + k * ldv, ac);
 #pragma unroll
                     for (int v = 0; v < VF; ++v) red[(gF * S + l) * ldF + sF * VF + v] = ac[v];
                 }
             }
             __syncthreads();
-            if (act) {
+            if (cact) {
                 for (int q = tid; q < s * m; q += team) {
                     const int l = q / m, r = q - l * m;
-                    if (l == k || (FWD ? (l < k) : (l > k))) continue;
-                    const int idx = l < k ? l : l - 1;
-                    const TC sc = block_scale<TF, TC>(d.C16e, ((long long)i * s + k) * sm1 + idx);
+                    if (l == 0 || l == k || (FWD ? (l < k) : (l > k))) continue;
+                    const TC sc = block_scale<TF, TC>(d.C16e, cross_idx(i, l, k));
                     const TC cv = sc * sum_groups<TC, S>(red, GF, l, ldF, r);
                     if (FWD) yv[l * ldv + r] -= cv;
                     else uv[l * ldv + r] -= cv;
@@ -464,7 +511,7 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep(const SysDesc *__restrict_
 // never selected and are not instantiated.
 constexpr bool pf_fits(int S, bool coupled, bool fp64)
 {
-    return (S + (coupled ? S * (S - 1) / 2 : 0)) * (fp64 ? 16 : 8) + (fp64 ? 64 : 32) <= 176;
+    return (S + (coupled && S > 1 ? (S - 1) * (S - 2) / 2 + 1 : 0)) * (fp64 ? 16 : 8) + (fp64 ? 64 : 32) <= 176;
 }
 
 template <int S, typename TJ, typename TF, typename TC, bool PF>
