@@ -309,12 +309,14 @@ irk_status irk_profile_read(irk_handle *h, irk_profile_stats *out);
 /* Launch shapes chosen by irk_autotune. */
 typedef struct {
     int matvec_teams;    /* block rows per 256-thread workgroup of the inner-precision matvec */
-    int sweep_big_min;   /* levels of at least this many elements use the streaming sweep form
+    int sweep_big_min;   /* levels of at least this many elements use the large-level sweep form
                             (the smaller ones the prefetching form) */
     int sweep_teams;     /* elements per 512-thread workgroup in the streaming form */
     int from_cache;      /* 1: shapes taken from the process-wide table, nothing timed */
     float matvec_us;     /* timed cost of one matvec / one preconditioner application with */
     float sweep_us;      /* the chosen shapes (0 when from_cache)                          */
+    int sweep_big_form;  /* large-level form: 0 streaming, 2 prefetching without the first
+                            Jacobian columns (one element per workgroup) */
 } irk_tune_info;
 
 /* Choose the launch shapes of a handle's matvec and preconditioner sweeps
@@ -322,14 +324,15 @@ typedef struct {
  * product and the level-scheduled sweeps of Sec. 4.3; the shapes change
  * only how the work is spread over workgroups).  Candidates: 1, 2, 4 or 8
  * block rows per matvec workgroup; for the sweeps, the level size from which
- * the streaming form replaces the prefetching one (1, 64, 128, 256, 512,
- * never) and half, the default or twice the default elements per streaming
- * workgroup.  Each candidate is run once and timed over three runs on the
+ * the large-level form replaces the prefetching one (1, 64, 128, 256, 512,
+ * never) and that form: streaming with half, the default or twice the
+ * default elements per workgroup, or prefetching without the Jacobian
+ * columns.  Each candidate is run once and timed over three runs on the
  * handle's stream; the fastest is kept.  The result is stored in a
  * process-wide table keyed by (m, s, preconditioner, precision, shared J,
  * row length, log2 T), and later calls for the same key (from any handle)
  * apply it without timing unless retime != 0.  The sweep results are
- * unchanged by the choice (both forms accumulate in the same order); the
+ * unchanged by the choice (every form accumulates in the same order); the
  * matvec's partial sums are combined in a different order, so results may
  * differ in the last bits.
  * h must be factored (IRK_ERR_STATE otherwise; any handle with pc NONE).

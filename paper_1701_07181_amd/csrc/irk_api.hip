@@ -20,8 +20,9 @@ namespace {
 
 struct Launch { int off, n; };
 // sweep launch: n SwItem records starting at item `off`, tps elements per
-// workgroup, prefetching form or not
-struct SwLaunch { int off, n, tps; bool pf; int region; };
+// workgroup, form (0 streaming, 1 prefetching, 2 prefetching without the
+// Jacobian columns)
+struct SwLaunch { int off, n, tps; int form; int region; };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -223,11 +224,11 @@ int pick_tpw(int ld, int V)
 // the stored cross blocks one sweep reads and the mass block) of an element
 // plus the first Jacobian columns, 8 compute-type values per thread and
 // block (VGPRs of 32 bits).
-bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF)
+bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF, bool jac_cols = true)
 {
     const int blocks = S + (coupled && S > 1 ? (S - 1) * (S - 2) / 2 + 1 : 0);
     const int per_block = (VF == 2) ? 16 : 8;        // FP64: 8 doubles; float: 8 floats
-    const int jac = (VJ == 2) ? 64 : 32;             // 16 FP64 or 8 FP32 column loads
+    const int jac = !jac_cols ? 0 : (VJ == 2) ? 64 : 32;   // 16 FP64 or 8 FP32 column loads
     return blocks * per_block + jac <= 176;
 }
 
@@ -235,14 +236,15 @@ bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF)
 // bound: one element per workgroup of SW_THREADS threads in the prefetching
 // form when its register budget allows (the most elements per workgroup,
 // up to 16, for which each thread covers at most 8 / VF columns of a factor
-// block).  Levels of at least big_min elements are bandwidth bound and use
-// the streaming form with teams of at least 8 column groups, which keeps
-// several elements in flight per compute unit.
-struct SweepShape { int tps_pf; bool pf; int tps_st; int big_min; };
+// block).  Levels of at least big_min elements use big_form: the streaming
+// form (0) with teams of at least 8 column groups, which keeps several
+// elements in flight per compute unit, or the prefetching form without the
+// Jacobian columns (2), which holds fewer registers than the full one.
+struct SweepShape { int tps_pf; bool pf; int tps_st; int big_min; int big_form; bool pf_lite; };
 
 SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupled)
 {
-    SweepShape sh{0, false, 1, 0};
+    SweepShape sh{0, false, 1, 0, 0, false};
     const int RF = ldF / VF, RJ = ldJ / VJ, NQ = 8 / VF;
     for (int tpw = 1; tpw <= 16; tpw *= 2) {
         const int team = SW_THREADS / tpw;
@@ -251,10 +253,12 @@ SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupl
         if ((m + G - 1) / G <= NQ) sh.tps_pf = tpw;
     }
     sh.pf = sh.tps_pf > 0 && sweep_prefetch_fits(s, coupled, VJ, VF);
+    sh.pf_lite = sh.tps_pf > 0 && sweep_prefetch_fits(s, coupled, VJ, VF, false);
     const int R = std::max(RF, RJ);
     while (sh.tps_st < 8 && SW_THREADS / (sh.tps_st * 2) >= R * 8) sh.tps_st *= 2;
     sh.big_min = 256;
     if (const char *e = std::getenv("IRK_SWEEP_BIG")) sh.big_min = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("IRK_SWEEP_BIG_FORM")) sh.big_form = (std::atoi(e) == 2) ? 2 : 0;
     if (!sh.pf) { sh.tps_pf = sh.tps_st; sh.big_min = 1; }
     return sh;
 }
@@ -465,8 +469,9 @@ void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32
     const std::vector<int> &lst = fwd ? sc.lvl_fwd : sc.lvl_bwd;
     for (size_t l = 0; l + 1 < off.size(); ++l) {
         const bool big = off[l + 1] - off[l] >= sh.big_min;
-        SwLaunch L{(int)items.size(), 0, big ? sh.tps_st : sh.tps_pf, sh.pf && !big,
-                   big ? region_st : region_pf};
+        const bool lite = big && sh.big_form == 2 && sh.pf_lite;
+        SwLaunch L{(int)items.size(), 0, (big && !lite) ? sh.tps_st : sh.tps_pf,
+                   lite ? 2 : (sh.pf && !big ? 1 : 0), (big && !lite) ? region_st : region_pf};
         for (int a = off[l]; a < off[l + 1]; ++a) {
             const int i = lst[a];
             SwItem r;
@@ -547,7 +552,7 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
                 const int tps = lv0[l].tps;
                 if (std::find(seen.begin(), seen.end(), tps) != seen.end()) continue;
                 seen.push_back(tps);
-                SwLaunch o{(int)M.items.size(), 0, tps, true, 0};
+                SwLaunch o{(int)M.items.size(), 0, tps, -1, 0};
                 for (auto &pr : mem) {
                     const irk_handle *h = pr.first;
                     const auto &lv = h->W.*f;
@@ -569,7 +574,11 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
                     }
                     o.n += padded;
                     const int VF = fp64 ? 2 : ((h->ftype == FT_F32) ? 4 : 8);
-                    o.pf = o.pf && src.pf && sweep_prefetch_fits(M.smax, M.coupled, fp64 ? 2 : 4, VF);
+                    // one form per launch: the members' common one if it fits
+                    // every member at S = smax, else the streaming form
+                    const bool fits = src.form == 0 ||
+                                      sweep_prefetch_fits(M.smax, M.coupled, fp64 ? 2 : 4, VF, src.form == 1);
+                    o.form = (o.form == -1 || o.form == src.form) && fits ? src.form : 0;
                     o.region = std::max(o.region, sw_region(M.smax, h->m, h->sc.maxrow, h->plan, fp64,
                                                             h->ftype, tps));
                 }
@@ -618,11 +627,11 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
     for (const SwLaunch &L : F)
         launch_sweep(true, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + L.off), L.n, L.tps,
                      L.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, -1, skip_done,
-                     w * L.tps * L.region, C.st, L.pf);
+                     w * L.tps * L.region, C.st, L.form);
     for (const SwLaunch &L : B)
         launch_sweep(false, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + L.off), L.n, L.tps,
                      L.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, acc_slot,
-                     skip_done, w * L.tps * L.region, C.st, L.pf);
+                     skip_done, w * L.tps * L.region, C.st, L.form);
     prof_end(C.prof, pi, PK_PC);
 }
 
@@ -2224,12 +2233,20 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
             const int bigs[] = {1, 64, 128, 256, 512, 1 << 30};
             float tbest = 0.0f;
             SweepShape cbest = base;
-            for (int tps : {base.tps_st / 2, base.tps_st, base.tps_st * 2}) {
-                if (tps < 1 || tps > 16 || SW_THREADS / tps < 4 * R) continue;
+            // candidates: the level size from which the large-level form
+            // replaces the prefetching one, that form (streaming with half,
+            // the default or twice the default elements per workgroup, or
+            // prefetching without the Jacobian columns)
+            for (int tps : {base.tps_st / 2, base.tps_st, base.tps_st * 2, 0}) {
+                const bool lite = tps == 0;
+                if (lite && !base.pf_lite) continue;
+                if (!lite && (tps < 1 || tps > 16 || SW_THREADS / tps < 4 * R)) continue;
                 for (int bm : bigs) {
                     if (!base.pf && bm != 1) continue;
+                    if (lite && bm == (1 << 30)) continue;     // no large levels: same as above
                     sh = base;
-                    sh.tps_st = tps;
+                    sh.tps_st = lite ? base.tps_st : tps;
+                    sh.big_form = lite ? 2 : 0;
                     sh.big_min = bm;
                     if (build_items(h) != IRK_OK) continue;
                     irk_status st = upload_items(h);
@@ -2257,6 +2274,7 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
         info->matvec_teams = h->mixed ? h->tpw32 : h->tpw64;
         info->sweep_big_min = sh.big_min;
         info->sweep_teams = sh.tps_st;
+        info->sweep_big_form = sh.big_form;
         info->from_cache = cached ? 1 : 0;
         info->matvec_us = best.matvec_us;
         info->sweep_us = best.sweep_us;

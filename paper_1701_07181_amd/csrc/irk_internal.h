@@ -177,11 +177,13 @@ void launch_step_finish(int s, long long n, const double *u0, const double *W, d
 //   and factors of type ftype with float vectors.
 //   v_slot/v_index: input of the forward sweep (FP64); result in SL_YH;
 //   acc_slot >= 0 adds the backward result to that FP64 slot (x += z).
-//   prefetch: every record's blocks fit the prefetching form (k_sweep.hip).
+//   form: 0 streaming; 1 prefetching (factor blocks, mass block, first
+//   Jacobian columns); 2 prefetching without the Jacobian columns (k_sweep.hip);
+//   a prefetching form whose blocks exceed the register budget runs streaming.
 void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
                   int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                   int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
-                  hipStream_t st, bool prefetch);
+                  hipStream_t st, int form);
 
 // One wavefront of the factorization: tasks (stage k = aux, element =
 // first) build P_{k,i} from the neighbour terms, invert it, and (coupled)

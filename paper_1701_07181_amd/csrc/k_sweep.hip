@@ -138,15 +138,19 @@ struct RecCols {
 };
 static_assert(SW_NB == 8, "RecCols holds eight columns");
 
-template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
+// PFM: 0 streaming form; 1 prefetching form (factor blocks, the mass block
+// and the first Jacobian columns); 2 prefetching form without the Jacobian
+// columns (fewer registers: more elements in flight on the large levels).
+template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, int PFM>
 __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, bool has, int tps,
                                            int region, int v_slot, int v_index, int acc_slot,
                                            unsigned char *smem_raw)
 {
+    constexpr bool PF = PFM > 0;
     const int s = d.s, m = d.m, T = d.T;
     constexpr int VJ = Vec16<TJ>::V, VF = Vec16<TF>::V;
     constexpr int NQ = 8 / VF;        // prefetched loads per thread and factor block
-    constexpr int QJ = 32 / VJ;       // prefetched loads per thread of the Jacobian row
+    constexpr int QJ = (PFM == 1) ? 32 / VJ : 0;   // prefetched loads per thread of the Jacobian row
     const int ldJ = ld_of<TJ>(d), ldF = ld_of<TF>(d);
     const int ldv = round_up(m, 8);
     const int team = SW_THREADS / tps;
@@ -202,7 +206,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
     __builtin_amdgcn_sched_barrier(0);   // keep these loads ahead of the prefetch
 
     // ---- prefetch: Jacobian row (first QJ column loads), pivots, cross blocks ----
-    TC rJ[QJ][VJ];
+    TC rJ[QJ > 0 ? QJ : 1][VJ];
     TC rP[S][NQ][VF];
     TC rC[S][S][NQ][VF];   // [k][l]: stored block C_{lk} (l, k >= 1) used by round k
     constexpr int NQJ = 8 / VJ;                     // prefetched column pieces of M_i
@@ -487,7 +491,7 @@ __device__ __forceinline__ void sweep_item(const SysDesc &d, const SwItem &rec, 
 }
 
 // One level per launch: workgroup b handles records b*tps .. b*tps+tps-1.
-template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, bool PF>
+template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, int PFM>
 __global__ __launch_bounds__(SW_THREADS) void k_sweep(const SysDesc *__restrict__ sysv,
                                                       const SwItem *__restrict__ recs, int nrec,
                                                       int tps, int region, int v_slot, int v_index,
@@ -503,25 +507,27 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep(const SysDesc *__restrict_
     const int idx = blockIdx.x * tps + threadIdx.x / team;
     const SwItem rec = recs[min(idx, nrec - 1)];
     const bool has = idx < nrec && rec.i >= 0;
-    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PF>(d, rec, has, tps, region, v_slot, v_index,
+    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PFM>(d, rec, has, tps, region, v_slot, v_index,
                                                      acc_slot, smem_raw);
 }
 
 // Same register budget as the host's choice of form: variants beyond it are
 // never selected and are not instantiated.
-constexpr bool pf_fits(int S, bool coupled, bool fp64)
+constexpr int pf_form(int PFM, int S, bool coupled, bool fp64)
 {
-    return (S + (coupled && S > 1 ? (S - 1) * (S - 2) / 2 + 1 : 0)) * (fp64 ? 16 : 8) + (fp64 ? 64 : 32) <= 176;
+    return (PFM == 0) ? 0 :
+           ((S + (coupled && S > 1 ? (S - 1) * (S - 2) / 2 + 1 : 0)) * (fp64 ? 16 : 8) +
+            (PFM == 1 ? (fp64 ? 64 : 32) : 0) <= 176) ? PFM : 0;
 }
 
-template <int S, typename TJ, typename TF, typename TC, bool PF>
+template <int S, typename TJ, typename TF, typename TC, int PFM>
 static void launch_sweep_t(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
                            int region, bool coupled, bool sharedJ, int v_slot, int v_index,
                            int acc_slot, int skip_done, size_t shmem, hipStream_t st)
 {
     dim3 grid((nrec + tps - 1) / tps), block(SW_THREADS);
 #define SW(C, SH, F)                                                                                   \
-    hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F, PF && pf_fits(S, C, sizeof(TC) == 8)>), grid, \
+    hipLaunchKernelGGL((k_sweep<S, TJ, TF, TC, C, SH, F, pf_form(PFM, S, C, sizeof(TC) == 8)>), grid, \
                        block, shmem, st, dsys, recs, nrec, tps, region, v_slot, v_index, acc_slot,   \
                        skip_done)
     if (forward) {
@@ -534,13 +540,13 @@ static void launch_sweep_t(bool forward, const SysDesc *dsys, const SwItem *recs
 #undef SW
 }
 
-template <int S, bool PF>
+template <int S, int PFM>
 static void launch_sweep_p(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
                            int region, bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
                            int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st)
 {
 #define SWP(TJ, TF, TC)                                                                             \
-    launch_sweep_t<S, TJ, TF, TC, PF>(forward, dsys, recs, nrec, tps, region, coupled, sharedJ, v_slot, \
+    launch_sweep_t<S, TJ, TF, TC, PFM>(forward, dsys, recs, nrec, tps, region, coupled, sharedJ, v_slot, \
                                       v_index, acc_slot, skip_done, shmem, st)
     if (fp64) SWP(double, double, double);
     else if (ftype == FT_F32) SWP(float, float, float);
@@ -552,17 +558,17 @@ static void launch_sweep_p(bool forward, const SysDesc *dsys, const SwItem *recs
 void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
                   int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                   int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st,
-                  bool prefetch)
+                  int form)
 {
     if (nrec <= 0) return;
+#define SWF(SS, FM)                                                                                 \
+    launch_sweep_p<SS, FM>(forward, dsys, recs, nrec, tps, region, fp64, ftype, coupled, sharedJ,   \
+                           v_slot, v_index, acc_slot, skip_done, shmem, st)
 #define SWS(SS)                                                                                      \
     do {                                                                                             \
-        if (prefetch)                                                                                \
-            launch_sweep_p<SS, true>(forward, dsys, recs, nrec, tps, region, fp64, ftype, coupled,   \
-                                     sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st);      \
-        else                                                                                         \
-            launch_sweep_p<SS, false>(forward, dsys, recs, nrec, tps, region, fp64, ftype, coupled,  \
-                                      sharedJ, v_slot, v_index, acc_slot, skip_done, shmem, st);     \
+        if (form == 1) SWF(SS, 1);                                                                   \
+        else if (form == 2) SWF(SS, 2);                                                              \
+        else SWF(SS, 0);                                                                             \
     } while (0)
     switch (s_max) {
     case 1: SWS(1); break;
@@ -572,6 +578,7 @@ void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nre
     default: SWS(5); break;
     }
 #undef SWS
+#undef SWF
 }
 
 }  // namespace irk

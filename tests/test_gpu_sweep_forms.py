@@ -1,10 +1,11 @@
 """Element-wise parity of every form of the preconditioner sweeps, and the
 method's exact-preconditioner cases, on the GPU.
 
-* The streaming sweep form (the one the large levels of the full-size
-  workloads run) is forced for every level (IRK_SWEEP_BIG=1, read at
-  set-up) and compared with the oracle's preconditioner apply element by
-  element, for all three FP64 forms, block sizes 9 to 135 and 2D/3D meshes.
+* The large-level sweep forms (streaming, and prefetching without the
+  Jacobian columns) are forced for every level (IRK_SWEEP_BIG=1 and
+  IRK_SWEEP_BIG_FORM, read at set-up) and compared with the oracle's
+  preconditioner apply element by element, for all three FP64
+  preconditioners, block sizes 6 to 135 and 2D/3D meshes.
 * Rows with more than 8 lower or upper neighbours (the records keep the
   first 8 columns; the rest are read from the column index) on a complete
   bipartite mesh, which is triangle-free.
@@ -57,12 +58,16 @@ STREAM_CASES = [(2, 2, 8, 16, 1), (3, 2, 5, 9, 1), (4, 2, 4, 6, 4), (3, 3, 4, 20
                 (3, 2, 6, 64, 1), (3, 3, 4, 135, 1), (2, 2, 5, 100, 2)]
 
 
+@pytest.mark.parametrize("form", ["streaming", "prefetch_lite"])
 @pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted", "uncoupled"])
 @pytest.mark.parametrize("case", STREAM_CASES, ids=_ids)
-def test_streaming_form_parity(pc, case, monkeypatch):
-    """Every level in the streaming form, element-wise against the oracle."""
+def test_streaming_form_parity(pc, case, form, monkeypatch):
+    """Every level in the large-level form (streaming, or prefetching without
+    the Jacobian columns), element-wise against the oracle."""
     irk = _irk()
     monkeypatch.setenv("IRK_SWEEP_BIG", "1")
+    if form == "prefetch_lite":
+        monkeypatch.setenv("IRK_SWEEP_BIG_FORM", "2")
     s, dim, N, m, nJ = case
     _say("streaming sweep", pc, case)
     sy = _system(s, dim, N, m, nJ)
@@ -127,7 +132,7 @@ def test_rows_longer_than_record(form, pc, s, m, monkeypatch):
 INNER_BOUND = {"fp32": 2.0 ** -17, "bf16": 16 * 2.0 ** -8, "fp16s": 16 * 2.0 ** -11}
 
 
-@pytest.mark.parametrize("form", ["default", "streaming"])
+@pytest.mark.parametrize("form", ["default", "streaming", "prefetch_lite"])
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16s"])
 @pytest.mark.parametrize("pc,case", [("uncoupled_shifted", (3, 3, 4, 135, 1)),
                                      ("coupled", (3, 2, 6, 64, 1)),
@@ -135,8 +140,10 @@ INNER_BOUND = {"fp32": 2.0 ** -17, "bf16": 16 * 2.0 ** -8, "fp16s": 16 * 2.0 ** 
                          ids=lambda v: v if isinstance(v, str) else _ids(v))
 def test_inner_preconditioner_parity(form, prec, pc, case, monkeypatch):
     irk = _irk()
-    if form == "streaming":
+    if form != "default":
         monkeypatch.setenv("IRK_SWEEP_BIG", "1")
+    if form == "prefetch_lite":
+        monkeypatch.setenv("IRK_SWEEP_BIG_FORM", "2")
     s, dim, N, m, nJ = case
     sy = _system(s, dim, N, m, nJ, seed=53)
     sol = irk.Solver(sy, irk.Options(pc=pc, matvec_prec="fp32", factor_prec=prec, rtol=1e-8))
