@@ -672,7 +672,8 @@ def main():
                    "dt": args.dt, "rtol": 1e-10, "restart": 30},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "autotune": {k: tune[k] for k in ("matvec_teams", "sweep_big_min", "sweep_teams", "sweep_big_form")},
+        "autotune": {k: tune[k] for k in ("matvec_teams", "sweep_big_min", "sweep_teams", "sweep_big_form",
+                                              "sweep_flow", "sweep_chain_max")},
         "iters": {"min": min(iters), "max": max(iters)},
         "equiv_mults": iters[0] * sy.s,
         "rel_res_true_max": res,

@@ -187,9 +187,11 @@ irk_status irk_batch_create(int capacity, long long max_elements, void *workspac
 /* Queue a factored handle with its right-hand side and its initial guess /
  * solution vector (DEVICE [s][T][m] each; both must stay valid until the
  * member is retired).  It starts at the next irk_batch_advance.  The batch's
- * stream first waits for the work already enqueued on the handle's stream,
- * so a new system can be set up and factored on another stream while the
- * batch iterates.  IRK_ERR_NOMEM: no free slot or element budget. */
+ * stream first waits for the end of the handle's last set-up, value update
+ * or factorization (not for other work enqueued on the handle's stream
+ * since), so new systems can be set up and factored on another stream while
+ * the batch iterates; rhs and x must be ready in the batch stream's order.
+ * IRK_ERR_NOMEM: no free slot or element budget. */
 irk_status irk_batch_admit(irk_batch *b, irk_handle *h, const double *rhs, double *x,
                            long long tag);
 
@@ -213,9 +215,10 @@ irk_status irk_batch_destroy(irk_batch *b);
  * big-irk, each with its own factored block ILU(0), Sec. 4.2-4.3) in the
  * batch: admit the handles (tags 0..count-1), advance until all have left,
  * retire them.  rhs[q], x[q]: DEVICE [s_q][T_q][m_q] (x[q] is the initial
- * guess on entry and the solution on return).  info (HOST, may be NULL)
- * receives one entry per handle.  The batch must be empty (IRK_ERR_STATE
- * otherwise).  Returns the first non-OK member status. */
+ * guess on entry and the solution on return; both ready in the order of the
+ * batch's stream).  info (HOST, may be NULL) receives one entry per handle.
+ * The batch must be empty (IRK_ERR_STATE otherwise).  Returns the first
+ * non-OK member status. */
 irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *const *rhs,
                              double *const *x, int count, irk_solve_info *info);
 
@@ -317,6 +320,12 @@ typedef struct {
     float sweep_us;      /* the chosen shapes (0 when from_cache)                          */
     int sweep_big_form;  /* large-level form: 0 streaming, 2 prefetching without the first
                             Jacobian columns (one element per workgroup) */
+    int sweep_flow;      /* 0: one launch per level; 1 + form: every level of a sweep in one
+                            launch, each element waiting only for the neighbours it reads
+                            (form 0 streaming, 1 prefetching, 2 prefetching without the
+                            Jacobian columns) */
+    int sweep_chain_max; /* (sweep_flow 0) levels of fewer elements run chained: each run of
+                            consecutive such levels of one form in one launch; 0 none */
 } irk_tune_info;
 
 /* Choose the launch shapes of a handle's matvec and preconditioner sweeps
@@ -327,7 +336,12 @@ typedef struct {
  * the large-level form replaces the prefetching one (1, 64, 128, 256, 512,
  * never) and that form: streaming with half, the default or twice the
  * default elements per workgroup, or prefetching without the Jacobian
- * columns.  Each candidate is run once and timed over three runs on the
+ * columns; then, on top of the best of these, the level size below which
+ * consecutive levels run chained in one launch (32 to 1024, or every level),
+ * each element waiting only for the neighbours it reads (variable
+ * IRK_SWEEP_CHAIN fixes it); or every level of a direction in one launch in
+ * one form (variable IRK_SWEEP_FLOW: 0 never, 1 always, 10 + form that form;
+ * any value fixes this choice).  Each candidate is run once and timed over three runs on the
  * handle's stream; the fastest is kept.  The result is stored in a
  * process-wide table keyed by (m, s, preconditioner, precision, shared J,
  * row length, log2 T), and later calls for the same key (from any handle)

@@ -78,7 +78,8 @@ class _StepInfo(C.Structure):
 class _Tune(C.Structure):
     _fields_ = [("matvec_teams", C.c_int), ("sweep_big_min", C.c_int), ("sweep_teams", C.c_int),
                 ("from_cache", C.c_int), ("matvec_us", C.c_float), ("sweep_us", C.c_float),
-                ("sweep_big_form", C.c_int)]
+                ("sweep_big_form", C.c_int), ("sweep_flow", C.c_int),
+                ("sweep_chain_max", C.c_int)]
 
 
 _vp = C.c_void_p
@@ -492,11 +493,15 @@ class Batch:
             pass
 
     def admit(self, solver: "Solver", rhs, tag: int, x0=None) -> int:
-        """Queue a factored solver; returns the status (OK, or ERR_NOMEM when full)."""
-        b = solver._vec(rhs)
-        with torch.cuda.stream(solver.stream):
+        """Queue a factored solver; returns the status (OK, or ERR_NOMEM when full).
+        The right-hand side and the initial guess are staged on the batch's
+        stream, so admission never waits for other work on the solver's."""
+        with torch.cuda.stream(self.stream):
+            b = torch.as_tensor(rhs, dtype=torch.float64).to(solver.device).contiguous().view(-1)
+            if b.numel() != solver.N:
+                raise ValueError(f"vector of {b.numel()} entries, expected {solver.N}")
             x = torch.zeros(solver.N, dtype=torch.float64, device=solver.device) if x0 is None \
-                else solver._vec(x0).clone()
+                else torch.as_tensor(x0, dtype=torch.float64).to(solver.device).contiguous().view(-1).clone()
         st = _L.irk_batch_admit(self._b, solver.handle, b.data_ptr(), x.data_ptr(), int(tag))
         if st == OK:
             self._keep[int(tag)] = (solver, b, x)
@@ -552,12 +557,17 @@ def solve_batched(batch: Batch, solvers: Sequence[Solver], rhs: Sequence, x0: Op
     """Solve several systems together through irk_solve_batched.  Returns
     (list of x, list of info dicts, status)."""
     n = len(solvers)
-    bs = [s._vec(r) for s, r in zip(solvers, rhs)]
-    xs = []
-    for q, s in enumerate(solvers):
-        with torch.cuda.stream(s.stream):
+    bs, xs = [], []
+    # staged on the batch's stream, which the solve runs on
+    with torch.cuda.stream(batch.stream):
+        for q, s in enumerate(solvers):
+            b = torch.as_tensor(rhs[q], dtype=torch.float64).to(s.device).contiguous().view(-1)
+            if b.numel() != s.N:
+                raise ValueError(f"vector of {b.numel()} entries, expected {s.N}")
+            bs.append(b)
             xs.append(torch.zeros(s.N, dtype=torch.float64, device=s.device) if x0 is None
-                      else s._vec(x0[q]).clone())
+                      else torch.as_tensor(x0[q], dtype=torch.float64).to(s.device).contiguous()
+                      .view(-1).clone())
     H = (_vp * n)(*[s.handle for s in solvers])
     B = (_vp * n)(*[b.data_ptr() for b in bs])
     X = (_vp * n)(*[x.data_ptr() for x in xs])

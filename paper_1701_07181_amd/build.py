@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libirk.so")
-SOURCES = ["irk_api.hip", "k_matvec.hip", "k_sweep.hip", "k_factor.hip", "k_krylov.hip",
+SOURCES = ["irk_api.hip", "k_matvec.hip", "k_sweep.hip", "k_sweep_flow.hip", "k_factor.hip", "k_krylov.hip",
            "k_untransformed.hip", "k_step.hip"]
 ARCH = os.environ.get("IRK_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -5,6 +5,7 @@
 #include "dense64.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -22,7 +23,7 @@ struct Launch { int off, n; };
 // sweep launch: n SwItem records starting at item `off`, tps elements per
 // workgroup, form (0 streaming, 1 prefetching, 2 prefetching without the
 // Jacobian columns)
-struct SwLaunch { int off, n, tps; int form; int region; };
+struct SwLaunch { int off, n, tps; int form; int region; int chain; };   // chain: see enqueue_pc
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -240,11 +241,17 @@ bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF, bool jac_cols = tr
 // form (0) with teams of at least 8 column groups, which keeps several
 // elements in flight per compute unit, or the prefetching form without the
 // Jacobian columns (2), which holds fewer registers than the full one.
-struct SweepShape { int tps_pf; bool pf; int tps_st; int big_min; int big_form; bool pf_lite; };
+struct SweepShape {
+    int tps_pf; bool pf; int tps_st; int big_min; int big_form; bool pf_lite;
+    bool flow;       // every level in one launch per direction (k_sweep_flow.hip)
+    int flow_form;   // its form: 0 streaming (tps_st), 1 prefetching, 2 prefetching
+                     // without the Jacobian columns (tps_pf)
+    int chain_max;   // otherwise: levels of fewer elements run chained (0: none)
+};
 
 SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupled)
 {
-    SweepShape sh{0, false, 1, 0, 0, false};
+    SweepShape sh{0, false, 1, 0, 0, false, false, 0, 0};
     const int RF = ldF / VF, RJ = ldJ / VJ, NQ = 8 / VF;
     for (int tpw = 1; tpw <= 16; tpw *= 2) {
         const int team = SW_THREADS / tpw;
@@ -260,13 +267,20 @@ SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupl
     if (const char *e = std::getenv("IRK_SWEEP_BIG")) sh.big_min = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("IRK_SWEEP_BIG_FORM")) sh.big_form = (std::atoi(e) == 2) ? 2 : 0;
     if (!sh.pf) { sh.tps_pf = sh.tps_st; sh.big_min = 1; }
+    sh.flow_form = sh.pf ? 1 : 0;
+    if (const char *e = std::getenv("IRK_SWEEP_FLOW")) {
+        const int f = std::atoi(e);            // 1: single launch, default form; 10 + form: that form
+        sh.flow = f > 0;
+        if (f >= 10) sh.flow_form = (f - 10 == 1 && sh.pf) ? 1 : (f - 10 == 2 && sh.pf_lite) ? 2 : 0;
+    }
+    if (const char *e = std::getenv("IRK_SWEEP_CHAIN")) sh.chain_max = std::max(0, std::atoi(e));
     return sh;
 }
 
 struct Plan {
     size_t o_dsys, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
         o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
-        o_hbuf, o_part, o_gather, total;
+        o_hbuf, o_part, o_gather, o_flow, o_ticket, total;
     int ld, ld32, ld16, nitems_max;
 };
 
@@ -328,6 +342,10 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     P.o_hbuf = take(sizeof(double) * 2 * (RESTART_MAX + 1));
     P.o_part = take(sizeof(double) * (size_t)RED_BLOCKS * (RESTART_MAX + 2));
     P.o_gather = take(sizeof(DevState));
+    if (o->pc != IRK_PC_NONE) {
+        P.o_flow = take(sizeof(unsigned long long) * (size_t)T);   // single-launch sweep flags
+        P.o_ticket = take(sizeof(unsigned));                        // its ticket counter
+    }
     P.total = off;
     return P;
 }
@@ -354,6 +372,8 @@ struct WorkSet {
     bool mixed = false, coupled = false, sharedJ = true, has_pc = true;
     int ftype = FT_F64;
     size_t shm_mv64 = 0, shm_mv32 = 0, shm_sw64 = 0, shm_sw32 = 0;
+    // ticket counter of the launches that chain levels
+    unsigned *dticket = nullptr;
 };
 
 }  // namespace
@@ -390,6 +410,7 @@ struct irk_handle {
     int bad_element;
     float ms_factor;
     hipEvent_t ev0, ev1, ev_ready;
+    hipEvent_t ev_done = nullptr;   // end of the last set-up, value update or factorization
     hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr;   // span of a time step
     SysDesc solve_desc;  // descriptor with the caller's rhs / x (staging for the copy)
     // profiling: event pool and recorded intervals (kind, event index)
@@ -408,6 +429,7 @@ struct irk_batch {
     SysDesc *dtab;               // device table [capacity]
     DevState *dgather;           // [capacity]
     Item *ditems;
+    unsigned *dticket;           // ticket counter of the single-launch sweeps
     size_t max_items;
     std::vector<SysDesc> htab;   // host copy of the table
     DevState *hgather;           // [capacity]: pinned (own_host) or the caller's host array
@@ -472,6 +494,14 @@ void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32
         const bool lite = big && sh.big_form == 2 && sh.pf_lite;
         SwLaunch L{(int)items.size(), 0, (big && !lite) ? sh.tps_st : sh.tps_pf,
                    lite ? 2 : (sh.pf && !big ? 1 : 0), (big && !lite) ? region_st : region_pf};
+        if (sh.flow) {
+            // one form for every level
+            L.tps = sh.flow_form == 0 ? sh.tps_st : sh.tps_pf;
+            L.form = sh.flow_form;
+            L.region = sh.flow_form == 0 ? region_st : region_pf;
+        }
+        // chained levels hold whole workgroups
+        L.chain = (sh.flow || off[l + 1] - off[l] < sh.chain_max) ? 1 : 0;
         for (int a = off[l]; a < off[l + 1]; ++a) {
             const int i = lst[a];
             SwItem r;
@@ -486,9 +516,22 @@ void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32
             items.insert(items.end(), it, it + 3);
             L.n++;
         }
+        while (L.chain && L.n % L.tps) {
+            SwItem r;
+            std::memset(&r, 0, sizeof(r));
+            r.i = -1;
+            Item it[3];
+            std::memcpy(it, &r, sizeof(r));
+            items.insert(items.end(), it, it + 3);
+            L.n++;
+        }
         if (L.n) out.push_back(L);
     }
 }
+
+// Epochs of the sweeps that chain levels: one per sweep, increasing over
+// the process, so a flag from an earlier sweep never equals the current one.
+std::atomic<unsigned long long> g_flow_epoch{0};
 
 int reduction_chunks(long long N)
 {
@@ -546,13 +589,14 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         for (auto &pr : mem) L = std::max(L, (pr.first->W.*f).size());
         for (size_t l = 0; l < L; ++l) {
             std::vector<int> seen;
+            const int first_item = (int)M.items.size();
             for (auto &pr0 : mem) {
                 const auto &lv0 = pr0.first->W.*f;
                 if (l >= lv0.size()) continue;
                 const int tps = lv0[l].tps;
                 if (std::find(seen.begin(), seen.end(), tps) != seen.end()) continue;
                 seen.push_back(tps);
-                SwLaunch o{(int)M.items.size(), 0, tps, -1, 0};
+                SwLaunch o{(int)M.items.size(), 0, tps, -1, 0, 1};
                 for (auto &pr : mem) {
                     const irk_handle *h = pr.first;
                     const auto &lv = h->W.*f;
@@ -581,9 +625,13 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
                     o.form = (o.form == -1 || o.form == src.form) && fits ? src.form : 0;
                     o.region = std::max(o.region, sw_region(M.smax, h->m, h->sc.maxrow, h->plan, fp64,
                                                             h->ftype, tps));
+                    o.chain = o.chain && src.chain;
                 }
                 if (o.n) out.push_back(o);
             }
+            // a level split over several launches is not chained
+            if (seen.size() > 1)
+                for (size_t q = out.size(); q-- > 0 && out[q].off >= first_item;) out[q].chain = 0;
         }
     };
     merge(&WorkSet::mv64, M.mv64);
@@ -598,6 +646,7 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
             merge_sweeps(&WorkSet::bwd32, false, M.bwd32);
         }
     }
+
     // LDS for the merged launches (template S = smax for every member)
     M.shm_mv64 = M.shm_mv32 = M.shm_sw64 = M.shm_sw32 = 0;
     for (auto &pr : mem) {
@@ -624,14 +673,44 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
     const std::vector<SwLaunch> &B = fp64 ? W.bwd64 : W.bwd32;
     const int ft = fp64 ? FT_F64 : W.ftype;
     const size_t w = fp64 ? sizeof(double) : sizeof(float);
-    for (const SwLaunch &L : F)
-        launch_sweep(true, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + L.off), L.n, L.tps,
-                     L.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, -1, skip_done,
-                     w * L.tps * L.region, C.st, L.form);
-    for (const SwLaunch &L : B)
-        launch_sweep(false, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + L.off), L.n, L.tps,
-                     L.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, acc_slot,
-                     skip_done, w * L.tps * L.region, C.st, L.form);
+    // Runs of consecutive chained levels (same form and elements per
+    // workgroup, whole workgroups) go in one launch each (k_sweep_flow.hip);
+    // every launch of such a sweep publishes its elements' flags with the
+    // sweep's epoch, which the chained launches wait for.
+    auto run = [&](const std::vector<SwLaunch> &L, bool fwd, int acc) {
+        bool any = false;
+        for (const SwLaunch &x : L) any = any || x.chain;
+        const unsigned long long ep = (any && W.dticket) ? ++g_flow_epoch : 0;
+        size_t a = 0;
+        while (a < L.size()) {
+            const SwLaunch &A = L[a];
+            if (ep && A.chain && A.n % A.tps == 0) {
+                int region = A.region;
+                size_t b = a + 1;
+                while (b < L.size() && L[b].chain && L[b].tps == A.tps && L[b].form == A.form &&
+                       L[b].n % A.tps == 0 && L[b].off == L[b - 1].off + 3 * L[b - 1].n &&
+                       w * A.tps * (size_t)std::max(region, L[b].region) + 64 <= 160 * 1024) {
+                    region = std::max(region, L[b].region);
+                    ++b;
+                }
+                if (b > a + 1) {
+                    const int nrec = (L[b - 1].off + 3 * L[b - 1].n - A.off) / 3;
+                    launch_sweep_flow(fwd, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + A.off),
+                                      nrec / A.tps, A.tps, region, W.smax, fp64, ft, W.coupled, W.sharedJ,
+                                      v_slot, v_index, acc, skip_done, w * A.tps * region, C.st, A.form,
+                                      W.dticket, ep);
+                    a = b;
+                    continue;
+                }
+            }
+            launch_sweep(fwd, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + A.off), A.n, A.tps,
+                         A.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, acc, skip_done,
+                         w * A.tps * A.region, C.st, A.form, ep);
+            ++a;
+        }
+    };
+    run(F, true, -1);
+    run(B, false, acc_slot);
     prof_end(C.prof, pi, PK_PC);
 }
 
@@ -1152,6 +1231,10 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     h->ditems = (Item *)(ws + P.o_items);
     h->dst = d.st;
     h->dgather = (DevState *)(ws + P.o_gather);
+    if (o->pc != IRK_PC_NONE) {
+        d.flow = (unsigned long long *)(ws + P.o_flow);
+        W.dticket = (unsigned *)(ws + P.o_ticket);
+    }
     W.dsys = h->dsys;
     W.ditems = h->ditems;
 
@@ -1169,6 +1252,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     hipEventCreate(&h->ev0);
     hipEventCreate(&h->ev1);
     hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming);
+    hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming);
     hipEventCreate(&h->ev_s0);
     hipEventCreate(&h->ev_s1);
     std::vector<Item> all(W.items);
@@ -1178,6 +1262,11 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     ok &= hipMemcpyAsync(h->ditems, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, stream) == hipSuccess;
     ok &= hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, stream) == hipSuccess;
+    if (o->pc != IRK_PC_NONE) {
+        // sweep flags at epoch 0 (every sweep uses a larger one), ticket counter at 0
+        ok &= hipMemsetAsync(d.flow, 0, sizeof(unsigned long long) * (size_t)T, stream) == hipSuccess;
+        ok &= hipMemsetAsync(W.dticket, 0, sizeof(unsigned), stream) == hipSuccess;
+    }
     if (!ok) { irk_destroy(h); return IRK_ERR_DEVICE; }
     *out = h;
     st = irk_update_values(h, p->J, p->M, p->dt);
@@ -1204,6 +1293,7 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
         HIPCHK(hipStreamSynchronize(h->stream));
     }
     h->factored = false;
+    if (h->ev_done) HIPCHK(hipEventRecord(h->ev_done, h->stream));
     return hipGetLastError() == hipSuccess ? IRK_OK : IRK_ERR_DEVICE;
 }
 
@@ -1225,6 +1315,7 @@ irk_status irk_factor_ilu(irk_handle *h)
     HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     hipEventElapsedTime(&h->ms_factor, h->ev0, h->ev1);
+    HIPCHK(hipEventRecord(h->ev_done, h->stream));
     if (h->hst->singular) {
         h->bad_element = h->hst->singular - 1;
         h->factored = false;
@@ -1673,6 +1764,7 @@ irk_status irk_destroy(irk_handle *h)
     if (h->ev0) hipEventDestroy(h->ev0);
     if (h->ev1) hipEventDestroy(h->ev1);
     if (h->ev_ready) hipEventDestroy(h->ev_ready);
+    if (h->ev_done) hipEventDestroy(h->ev_done);
     if (h->ev_s0) hipEventDestroy(h->ev_s0);
     if (h->ev_s1) hipEventDestroy(h->ev_s1);
     delete h;
@@ -1693,6 +1785,7 @@ static constexpr size_t batch_ws_bytes(int capacity, long long max_elements)
     off = align256(off + sizeof(SysDesc) * (size_t)capacity);
     off = align256(off + sizeof(DevState) * (size_t)capacity);
     off = align256(off + sizeof(Item) * batch_items_bound(capacity, max_elements));
+    off = align256(off + sizeof(unsigned));   // ticket counter of the single-launch sweeps
     return off;
 }
 
@@ -1722,6 +1815,9 @@ static irk_status batch_init(irk_batch *b, int capacity, long long max_elements,
     b->dgather = (DevState *)(b->ws + off);
     off = align256(off + sizeof(DevState) * (size_t)capacity);
     b->ditems = (Item *)(b->ws + off);
+    off = align256(off + sizeof(Item) * batch_items_bound(capacity, max_elements));
+    b->dticket = (unsigned *)(b->ws + off);
+    HIPCHK(hipMemsetAsync(b->dticket, 0, sizeof(unsigned), stream));
     b->max_items = batch_items_bound(capacity, max_elements);
     b->htab.assign(capacity, SysDesc());
     b->hgather = hgather;
@@ -1788,11 +1884,10 @@ irk_status irk_batch_admit(irk_batch *b, irk_handle *h, const double *rhs, doubl
     d.vec[SL_B] = const_cast<double *>(rhs);
     d.vec[SL_X] = x;
     b->htab[m.slot] = d;
-    // the batch stream waits for work already enqueued on the handle's stream
-    if (h->stream != b->stream) {
-        HIPCHK(hipEventRecord(h->ev_ready, h->stream));
-        HIPCHK(hipStreamWaitEvent(b->stream, h->ev_ready, 0));
-    }
+    // the batch stream waits for the handle's own last set-up, value update
+    // or factorization only, not for later work on the handle's stream (a
+    // server prepares other systems there meanwhile)
+    if (h->ev_done) HIPCHK(hipStreamWaitEvent(b->stream, h->ev_done, 0));
     m.t0 = b->slot_ev[m.slot];
     HIPCHK(hipEventRecord(m.t0, b->stream));
     b->members.push_back(m);
@@ -1816,6 +1911,7 @@ static irk_status batch_workset(irk_batch *b, int phase, WorkSet &W, std::vector
     if (W.shm_sw64 > 160 * 1024 || W.shm_sw32 > 160 * 1024) return IRK_ERR_ARG;
     W.dsys = b->dtab;
     W.ditems = b->ditems;
+    W.dticket = b->dticket;
     if (!W.items.empty())
         HIPCHK(hipMemcpyAsync(b->ditems, W.items.data(), sizeof(Item) * W.items.size(),
                               hipMemcpyHostToDevice, b->stream));
@@ -1975,6 +2071,7 @@ irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_s
     for (irk_handle *h : hs)
         if (h->mixed && h->opt.pc != IRK_PC_NONE) launch_quantize(h->dsys, h->hsys, h->ftype, b->stream);
     HIPCHK(hipEventRecord(b->ev_f1, b->stream));
+    for (irk_handle *h : hs) HIPCHK(hipEventRecord(h->ev_done, b->stream));
     HIPCHK(hipGetLastError());
     launch_gather_state(b->dtab, b->ditems, n, b->dgather, b->stream);
     HIPCHK(hipMemcpyAsync(b->hgather, b->dgather, sizeof(DevState) * n, hipMemcpyDeviceToHost, b->stream));
@@ -2237,22 +2334,58 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
             // replaces the prefetching one, that form (streaming with half,
             // the default or twice the default elements per workgroup, or
             // prefetching without the Jacobian columns)
-            for (int tps : {base.tps_st / 2, base.tps_st, base.tps_st * 2, 0}) {
-                const bool lite = tps == 0;
-                if (lite && !base.pf_lite) continue;
-                if (!lite && (tps < 1 || tps > 16 || SW_THREADS / tps < 4 * R)) continue;
-                for (int bm : bigs) {
-                    if (!base.pf && bm != 1) continue;
-                    if (lite && bm == (1 << 30)) continue;     // no large levels: same as above
-                    sh = base;
-                    sh.tps_st = lite ? base.tps_st : tps;
-                    sh.big_form = lite ? 2 : 0;
-                    sh.big_min = bm;
-                    if (build_items(h) != IRK_OK) continue;
-                    irk_status st = upload_items(h);
+            // (IRK_SWEEP_FLOW / IRK_SWEEP_CHAIN in the environment fix the
+            // single-launch / chaining choice)
+            const bool flow_fixed = std::getenv("IRK_SWEEP_FLOW") != nullptr;
+            const bool chain_fixed = std::getenv("IRK_SWEEP_CHAIN") != nullptr;
+            auto time_shape = [&](const SweepShape &cand) -> irk_status {
+                sh = cand;
+                if (build_items(h) != IRK_OK) return IRK_OK;
+                irk_status st = upload_items(h);
+                if (st != IRK_OK) return st;
+                const float t = time_us(h, [&] { enqueue_pc(C, fp64, SL_EXT0, 0, -1, 0); }, 3);
+                if (tbest == 0.0f || t < tbest) { tbest = t; cbest = sh; }
+                return IRK_OK;
+            };
+            if (flow_fixed && base.flow) {
+                irk_status st = time_shape(base);
+                if (st != IRK_OK) return st;
+            } else {
+                for (int tps : {base.tps_st / 2, base.tps_st, base.tps_st * 2, 0}) {
+                    const bool lite = tps == 0;
+                    if (lite && !base.pf_lite) continue;
+                    if (!lite && (tps < 1 || tps > 16 || SW_THREADS / tps < 4 * R)) continue;
+                    for (int bm : bigs) {
+                        if (!base.pf && bm != 1) continue;
+                        if (lite && bm == (1 << 30)) continue;     // no large levels: same as above
+                        SweepShape c = base;
+                        c.flow = false;
+                        if (!chain_fixed) c.chain_max = 0;
+                        c.tps_st = lite ? base.tps_st : tps;
+                        c.big_form = lite ? 2 : 0;
+                        c.big_min = bm;
+                        irk_status st = time_shape(c);
+                        if (st != IRK_OK) return st;
+                    }
+                }
+                // the best shape with its levels below a size chained into one
+                // launch per run of equal forms
+                const SweepShape per_level = cbest;
+                for (int cm : {32, 64, 128, 256, 512, 1024, 1 << 30}) {
+                    if (chain_fixed) break;
+                    SweepShape c = per_level;
+                    c.chain_max = cm;
+                    irk_status st = time_shape(c);
                     if (st != IRK_OK) return st;
-                    const float t = time_us(h, [&] { enqueue_pc(C, fp64, SL_EXT0, 0, -1, 0); }, 3);
-                    if (tbest == 0.0f || t < tbest) { tbest = t; cbest = sh; }
+                }
+                // every level of a direction in one launch, in each form that fits
+                for (int ff = 0; ff < 3 && !flow_fixed; ++ff) {
+                    if ((ff == 1 && !base.pf) || (ff == 2 && !base.pf_lite)) continue;
+                    SweepShape c = base;
+                    c.flow = true;
+                    c.flow_form = ff;
+                    irk_status st = time_shape(c);
+                    if (st != IRK_OK) return st;
                 }
             }
             sh = cbest;
@@ -2275,6 +2408,8 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
         info->sweep_big_min = sh.big_min;
         info->sweep_teams = sh.tps_st;
         info->sweep_big_form = sh.big_form;
+        info->sweep_flow = sh.flow ? 1 + sh.flow_form : 0;
+        info->sweep_chain_max = sh.flow ? 0 : sh.chain_max;
         info->from_cache = cached ? 1 : 0;
         info->matvec_us = best.matvec_us;
         info->sweep_us = best.sweep_us;

@@ -83,6 +83,8 @@ struct SysDesc {
     uint16_t *P16; uint16_t *C16;             // ld16
     int *P16e; int *C16e;                     // per-block exponents (FP16S)
     double *Fscr;                             // per-element factor scratch [T][s] blocks (ld)
+    unsigned long long *flow;                 // [T] epoch of the last single-launch sweep that
+                                              // published the element's result
     // vectors
     void *vec[NSLOT];
     // Krylov state
@@ -180,10 +182,24 @@ void launch_step_finish(int s, long long n, const double *u0, const double *W, d
 //   form: 0 streaming; 1 prefetching (factor blocks, mass block, first
 //   Jacobian columns); 2 prefetching without the Jacobian columns (k_sweep.hip);
 //   a prefetching form whose blocks exceed the register budget runs streaming.
+//   epoch != 0: publish each element's flag (a later launch of the same
+//   sweep chains levels, see launch_sweep_flow).
 void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nrec, int tps,
                   int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                   int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
-                  hipStream_t st, int form);
+                  hipStream_t st, int form, unsigned long long epoch = 0);
+
+// Consecutive levels of one sweep in a single launch (k_sweep_flow.hip):
+// workgroups take consecutive blocks of tps records in claim order (ticket
+// counter, back at zero when the launch ends), each element waits for the
+// flags of the neighbours it reads, then publishes its own flag = epoch.
+// recs: nblk * tps records, every level padded to whole workgroups
+// (i = -1), levels in sweep order.  epoch: the same for every launch of one
+// sweep, larger than any epoch an earlier sweep used on these flags.
+void launch_sweep_flow(bool forward, const SysDesc *dsys, const SwItem *recs, int nblk, int tps,
+                       int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
+                       int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
+                       hipStream_t st, int form, unsigned *ticket, unsigned long long epoch);
 
 // One wavefront of the factorization: tasks (stage k = aux, element =
 // first) build P_{k,i} from the neighbour terms, invert it, and (coupled)
