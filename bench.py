@@ -89,7 +89,11 @@ def untransformed_bytes(s, T, m, nnzb, nJ=1, form="blocks", w=8):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_matvec_s3_64x64_m64_hbm_traffic.txt")
 TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_matvec.hip", "paper_1701_07181_amd/csrc/irk_device.h"]
 SWEEP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_s3_64x64_m64_coupled_hbm_traffic.txt")
-SWEEP_TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_sweep.hip", "paper_1701_07181_amd/csrc/irk_device.h"]
+SWEEP_TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_sweep.hip", "paper_1701_07181_amd/csrc/k_sweep_flow.hip",
+                         "paper_1701_07181_amd/csrc/sweep_item.h", "paper_1701_07181_amd/csrc/irk_device.h"]
+FACTOR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_factor_task_s3_64x64_m64_coupled_counters.txt")
+FACTOR_TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_factor.hip", "paper_1701_07181_amd/csrc/dense64.h",
+                          "paper_1701_07181_amd/csrc/irk_device.h"]
 
 
 def _counter_traffic(path, sources):
@@ -103,6 +107,8 @@ def _counter_traffic(path, sources):
         return None
     vals = dict(l.split(":", 1) for l in txt.splitlines()
                 if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    vals.update({l.split(":", 1)[0][len("factor "):]: l.split(":", 1)[1] for l in txt.splitlines()
+                 if l.startswith(("factor traffic_bytes_per_launch:", "factor source_sha256:"))})
     h = hashlib.sha256()
     for p in sources:
         with open(os.path.join(ROOT, p), "rb") as f:
@@ -120,6 +126,11 @@ def measured_traffic():
 def sweep_traffic():
     """HBM bytes per preconditioner application (all sweep levels)."""
     return _counter_traffic(SWEEP_TRAFFIC_FILE, SWEEP_TRAFFIC_SOURCES)
+
+
+def factor_traffic():
+    """HBM bytes per factorization (all wavefronts of k_factor_task)."""
+    return _counter_traffic(FACTOR_TRAFFIC_FILE, FACTOR_TRAFFIC_SOURCES)
 
 
 def _log(msg):
@@ -207,7 +218,13 @@ def run_batched(args):
                         restart=30)
     plain = irk.Options(pc="uncoupled_shifted", rtol=1e-8, restart=30)
     res = {}
+    xs = None
+    xs_by_label = {}
+    legs = set(args.legs.split(",")) if args.legs else {f"{a}_{b}" for a in ("mixed", "fp64")
+                                                          for b in ("batched", "one_by_one")}
     for label, opts in [("mixed", mixed), ("fp64", plain)]:
+        if not any(l.startswith(label) for l in legs):
+            continue
         solvers = [irk.Solver(sy, opts) for sy in systems]
         # launch shapes per problem class: timed on the first system of each
         # class, then taken from the process-wide table
@@ -216,10 +233,11 @@ def run_batched(args):
             so.factor()
             tuned += 1 - so.autotune()["from_cache"]
         _log(f"batched {label}: {tuned} problem classes timed by the autotuner")
-        batch = irk.Batch(count, elems) if label == "mixed" else None
-        modes = ["batched", "one_by_one"] if batch else ["one_by_one"]
+        batch = irk.Batch(count, elems)
+        modes = [md for md in ("batched", "one_by_one") if f"{label}_{md}" in legs]
         for mode in modes:
             def step():
+                nonlocal xs
                 if mode == "batched":
                     irk.factor_batched(batch, solvers)
                     xs, infos, st = irk.solve_batched(batch, solvers, [sy.rhs for sy in systems])
@@ -239,12 +257,24 @@ def run_batched(args):
                                       "converged": sum(bool(i["converged"]) for i in infos),
                                       "mean_iters": round(sum(i["iters"] for i in infos) / count, 2),
                                       "max_rel_res": max(i["rel_res_true"] for i in infos)}
+            if mode == "batched":
+                xs_by_label[label] = [x.clone() for x in xs]
             _log(f"batched {label} {mode}: {res[f'{label}_{mode}']}")
         for s in solvers:
             s.close()
         if batch:
             batch.close()
         torch.cuda.empty_cache()
+    # like for like: mixed against FP64, both batched and both one by one;
+    # the mixed solutions against the FP64 ones (both at a true residual of 1e-8)
+    for mode in ("batched", "one_by_one"):
+        if f"mixed_{mode}" in res and f"fp64_{mode}" in res:
+            res[f"mixed_over_fp64_{mode}"] = round(res[f"mixed_{mode}"]["solves_per_s"] /
+                                                   res[f"fp64_{mode}"]["solves_per_s"], 3)
+    if "mixed" in xs_by_label and "fp64" in xs_by_label:
+        diffs = [float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                 for a, b in zip(xs_by_label["mixed"], xs_by_label["fp64"])]
+        res["mixed_vs_fp64_rel_diff_max"] = max(diffs)
     return {"metric": "IRK solves/s at 1e-8 rel residual", "mode": "batched", "unit": "solves/s",
             "data": "synthetic",
             "config": {"workload": f"{count} systems: 2D periodic NxN, N in 4..32, DG p in 1..4 "
@@ -255,20 +285,25 @@ def run_batched(args):
 
 
 def run_serve(args):
-    """Poisson arrivals of solve requests (75 % 2D up to 48x48 p 1..4, 25 % 3D
-    up to 12^3 p 2; s 2..4; 30 % re-use a resident operator), served by the
-    continuous-batching loop with FP32 inner / FP64 outer to 1e-8.  The
-    stream replays 200 generated (operator, right-hand side) specifications
-    with fresh right-hand sides; each replay's operators count as new (set up
-    and factored again), which keeps input generation within a minute."""
+    """Poisson arrivals of solve requests (75 % 2D periodic N x N, N up to 64,
+    p 1..4; 25 % 3D N^3, N up to 16, p 2; s 2..4; 30 % re-use a resident
+    operator), served by the continuous-batching loop to a true residual of
+    1e-8.  Legs: FP32 inner / FP64 outer, plain FP64, BF16-factor inner.
+    Each leg first measures its saturation rate (every request present at
+    t = 0), then serves Poisson arrivals at fixed fractions of that rate.
+    The stream replays 200 generated (operator, right-hand side)
+    specifications with fresh right-hand sides; each replay's operators
+    count as new (set up and factored again), which keeps input generation
+    within two minutes."""
     import numpy as np
     import torch
     import dgsynth
     import paper_1701_07181_amd as irk
     from paper_1701_07181_amd.serve import Request, Server, latency_stats
-    count = args.count or 1000
+    count = args.count or 600
     NB = 200
-    stream = dgsynth.serve_requests(min(count, NB), N2max=48, N3max=12)
+    N2max, N3max = 64, 16
+    stream = dgsynth.serve_requests(min(count, NB), N2max=N2max, N3max=N3max)
     systems, reqs_base = {}, []
     t0 = time.time()
     for rid in range(count):
@@ -284,31 +319,55 @@ def run_serve(args):
         rhs = torch.from_numpy(dgsynth.fresh_rhs((*rhs_seed, rep), sy.s, sy.T, sy.m)).cuda()
         reqs_base.append((rid, base + NB * rep, sy, rhs))
     torch.cuda.synchronize()
-    _log(f"built {len(systems)} operators for {count} requests in {time.time() - t0:.1f}s")
-    opts = irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="fp32", rtol=1e-8,
-                       restart=30)
-    points = []
+    elems = [sy.T for sy in systems.values()]
+    _log(f"built {len(systems)} operators for {count} requests in {time.time() - t0:.1f}s "
+         f"(elements per operator {min(elems)}..{max(elems)})")
+    legs = [("fp32_inner", irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="fp32",
+                                       rtol=1e-8, restart=30), (0.25, 0.5, 0.75, 0.9)),
+            ("fp64", irk.Options(pc="uncoupled_shifted", rtol=1e-8, restart=30), (0.25, 0.5, 0.75, 0.9)),
+            ("bf16_inner", irk.Options(pc="uncoupled_shifted", matvec_prec="fp32", factor_prec="bf16",
+                                       rtol=1e-8, restart=30), (0.5,))]
+    out = {}
     rng = np.random.default_rng(4242)
-    for qps in (50.0, 100.0, 200.0, 400.0):
-        arr = np.cumsum(rng.exponential(1.0 / qps, size=count))
-        reqs = [Request(rid, op, sy, rhs, float(a)) for (rid, op, sy, rhs), a in zip(reqs_base, arr)]
+
+    def serve(opts, arrivals, tag):
+        reqs = [Request(rid, op, sy, rhs, float(a)) for (rid, op, sy, rhs), a in zip(reqs_base, arrivals)]
         srv = Server(opts, capacity=64, max_elements=1 << 20, budget_bytes=120 << 30)
-        results = srv.run(reqs, progress=lambda d, n: _log(f"serve qps={qps}: {d}/{n} done"))
+        results = srv.run(reqs, progress=lambda d, n: _log(f"serve {tag}: {d}/{n} done"))
         st = latency_stats(results)
         st["stalls"], st["evictions"] = srv.stalls, srv.evictions
         srv.close()
-        st["offered_qps"] = qps
-        points.append(st)
-        _log(f"serve qps={qps}: {st}")
         torch.cuda.empty_cache()
+        return st
+
+    for label, opts, fracs in legs:
+        sat = serve(opts, np.zeros(count), f"{label} saturation")
+        sat_rate = sat["solves_per_s"]
+        _log(f"serve {label} saturation: {sat}")
+        points = []
+        for fr in fracs:
+            qps = fr * sat_rate
+            arr = np.cumsum(rng.exponential(1.0 / qps, size=count))
+            st = serve(opts, arr, f"{label} {fr:.2f} x saturation")
+            st["offered_qps"] = round(qps, 2)
+            st["fraction_of_saturation"] = fr
+            points.append(st)
+            _log(f"serve {label} {fr:.2f} x saturation: {st}")
+        out[label] = {"saturation": sat, "points": points}
+    out["fp32_inner_over_fp64_saturation"] = round(out["fp32_inner"]["saturation"]["solves_per_s"] /
+                                                   out["fp64"]["saturation"]["solves_per_s"], 3)
+    out["bf16_inner_over_fp64_saturation"] = round(out["bf16_inner"]["saturation"]["solves_per_s"] /
+                                                   out["fp64"]["saturation"]["solves_per_s"], 3)
     return {"metric": "IRK solves/s at 1e-8 rel residual; p99 latency", "mode": "serve",
             "unit": "solves/s", "data": "synthetic",
-            "config": {"workload": f"{count} requests per arrival rate (Poisson), 75% 2D N<=48 p 1..4, "
-                                   "25% 3D N<=12 p=2, s 2..4, 30% operator re-use, FP32 inner / FP64 "
-                                   f"outer, rtol 1e-8, capacity 64, {NB} generated specifications "
-                                   "replayed with fresh right-hand sides (replayed operators set up "
-                                   "and factored again), 120 GiB workspace pool"},
-            "points": points}
+            "config": {"workload": f"{count} requests per point, 75% 2D N<={N2max} p 1..4, 25% 3D "
+                                   f"N<={N3max} p=2, s 2..4, 30% operator re-use, shifted uncoupled "
+                                   "block ILU(0), rtol 1e-8, capacity 64, Poisson arrivals at 0.25 / "
+                                   "0.5 / 0.75 / 0.9 of each leg's measured saturation rate, "
+                                   f"{NB} generated specifications replayed with fresh right-hand "
+                                   "sides (replayed operators set up and factored again), 120 GiB "
+                                   "workspace pool"},
+            "legs": out}
 
 
 def family_report(prof, elapsed, sy, pc, iters, N):
@@ -332,8 +391,8 @@ def family_report(prof, elapsed, sy, pc, iters, N):
         ms = prof["pc_ms"] / prof["pc_count"]
         by = sweep_bytes(sy.s, sy.T, sy.m, sy.nnzb, pc == "coupled")
         ach = by / (ms * 1e-3) / 1e9
-        fam["sweeps"] = {"kernel": "k_sweep (block ILU(0) forward + backward sweeps, all levels of "
-                                   "one preconditioner application, FP64)", "bound": "hbm",
+        fam["sweeps"] = {"kernel": "k_sweep / k_sweep_flow (block ILU(0) forward + backward sweeps, "
+                                   "all levels of one preconditioner application, FP64)", "bound": "hbm",
                          "total_ms": round(prof["pc_ms"], 3), "share": round(prof["pc_ms"] / tot, 4),
                          "launches": prof["pc_count"], "avg_launch_us": round(ms * 1e3, 2),
                          "bytes_per_launch": by, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
@@ -343,12 +402,14 @@ def family_report(prof, elapsed, sy, pc, iters, N):
         ms = prof["factor_ms"] / prof["factor_count"]
         fl = factor_flops(sy.s, sy.T, sy.m, sy.row_ptr, sy.col_idx, pc == "coupled")
         ach = fl / (ms * 1e-3) / 1e12
-        fam["factor"] = {"kernel": "k_factor_a / k_factor_b (block ILU(0) factorization, all levels, "
-                                   "FP64 matrix-core products and Gauss-Jordan inverses)", "bound": "mfma",
+        fam["factor"] = {"kernel": "k_factor_task (block ILU(0) factorization, all stage/level "
+                                   "wavefronts, FP64 matrix-core products and Gauss-Jordan inverses)",
+                         "bound": "mfma",
                          "total_ms": round(prof["factor_ms"], 3), "share": round(prof["factor_ms"] / tot, 4),
                          "launches": prof["factor_count"], "avg_launch_us": round(ms * 1e3, 2),
                          "flops_per_launch": fl, "achieved": round(ach, 2), "peak": FP64_PEAK_TFS,
-                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFS, 4), "traffic": None}
+                         "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFS, 4),
+                         "traffic": factor_traffic() if N == 64 and pc == "coupled" else None}
     if prof["orth_count"]:
         ms = prof["orth_ms"] / prof["orth_count"]
         # steps j = 0 .. iters-1 of one cycle per solve (GMRES(30) never restarts here)
@@ -567,6 +628,8 @@ def main():
                          "256 uneven systems solved together vs one by one; serve: a request "
                          "stream at several arrival rates")
     ap.add_argument("--count", type=int, default=0, help="systems / requests for batched and serve")
+    ap.add_argument("--legs", default="", help="batched mode: comma list of legs to run "
+                    "(mixed_batched, mixed_one_by_one, fp64_batched, fp64_one_by_one; default all)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the "
                          "known-size kernel that scales the HBM byte counters)")

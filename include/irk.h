@@ -226,7 +226,7 @@ irk_status irk_solve_batched(irk_batch *b, irk_handle *const *h, const double *c
  * capture, serving loops or harnesses that forbid hipMalloc):
  * irk_solve_batched without a batch object.  The batch's device scratch
  * (system table, gathered convergence states, merged work items) is a
- * library-owned static device array of about 14.8 MB per GPU, taken at the
+ * library-owned static device array of about 19 MB per GPU, taken at the
  * first call on a device (the current device) and held until the process
  * ends; the call allocates no device memory.  Limits: count <= 64 and at
  * most 32768 elements over all handles, else IRK_ERR_ARG before any work.

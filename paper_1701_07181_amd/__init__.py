@@ -565,9 +565,13 @@ def solve_batched(batch: Batch, solvers: Sequence[Solver], rhs: Sequence, x0: Op
             if b.numel() != s.N:
                 raise ValueError(f"vector of {b.numel()} entries, expected {s.N}")
             bs.append(b)
-            xs.append(torch.zeros(s.N, dtype=torch.float64, device=s.device) if x0 is None
-                      else torch.as_tensor(x0[q], dtype=torch.float64).to(s.device).contiguous()
-                      .view(-1).clone())
+        if x0 is None:
+            # one zero-filled allocation, one view per member
+            flat = torch.zeros(sum(s.N for s in solvers), dtype=torch.float64, device=batch.device)
+            xs = list(torch.split(flat, [s.N for s in solvers]))
+        else:
+            xs = [torch.as_tensor(x0[q], dtype=torch.float64).to(s.device).contiguous().view(-1).clone()
+                  for q, s in enumerate(solvers)]
     H = (_vp * n)(*[s.handle for s in solvers])
     B = (_vp * n)(*[b.data_ptr() for b in bs])
     X = (_vp * n)(*[x.data_ptr() for x in xs])

@@ -23,7 +23,15 @@ struct Launch { int off, n; };
 // sweep launch: n SwItem records starting at item `off`, tps elements per
 // workgroup, form (0 streaming, 1 prefetching, 2 prefetching without the
 // Jacobian columns)
-struct SwLaunch { int off, n, tps; int form; int region; int chain; };   // chain: see enqueue_pc
+// One sweep level (or, in a merged work set, the members of a level that
+// share a launch shape): records at item offset off, n records, tps per
+// workgroup.  chain: the level may run chained with its neighbours; group:
+// the chain (SwChain) it runs in, -1 for a launch of its own.
+struct SwLaunch { int off, n, tps; int form; int region; int chain; int group = -1; };
+// A run of consecutive chained levels of one form in one launch
+// (k_sweep_flow.hip): workgroup table at item offset tab (one Item per
+// workgroup: first record's item offset, records), nblk workgroups.
+struct SwChain { int tab, nblk, form, region, tps_max; };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -299,7 +307,9 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     // cross blocks C_{lq} with l, q >= 1 (those in stage row or column 0 stay
     // multiples of M and are not stored)
     const long long nblkP = (long long)T * s, nblkC = coupled ? (long long)T * (s - 1) * (s - 2) : 0;
-    P.nitems_max = T * (24 + 10 * s) + 2 * RED_BLOCKS + 64;   // sweep records and padded factor tasks
+    // sweep records (four lists; chained levels padded to whole workgroups of
+    // up to 16), chain workgroup tables, padded factor tasks
+    P.nitems_max = T * (24 + 10 * s + 4 * 3 * 15 + 8) + 2 * RED_BLOCKS + 64;
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
     P.o_dsys = take(sizeof(SysDesc));
@@ -372,7 +382,9 @@ struct WorkSet {
     bool mixed = false, coupled = false, sharedJ = true, has_pc = true;
     int ftype = FT_F64;
     size_t shm_mv64 = 0, shm_mv32 = 0, shm_sw64 = 0, shm_sw32 = 0;
-    // ticket counter of the launches that chain levels
+    // runs of chained levels of each sweep, and the ticket counter their
+    // launches claim workgroups from
+    std::vector<SwChain> cf64, cb64, cf32, cb32;
     unsigned *dticket = nullptr;
 };
 
@@ -529,6 +541,42 @@ void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32
     }
 }
 
+// Runs of consecutive chained levels of one form (whole workgroups, within
+// the LDS limit) become chains: their workgroup tables are appended to
+// items and the levels point at their chain.  A run of one level stays a
+// launch of its own.
+void make_chains(std::vector<Item> &items, std::vector<SwLaunch> &L, size_t w, std::vector<SwChain> &out)
+{
+    out.clear();
+    for (SwLaunch &x : L) x.group = -1;
+    auto fits = [&](const SwLaunch &x) { return x.chain && x.n % x.tps == 0; };
+    size_t a = 0;
+    while (a < L.size()) {
+        if (!fits(L[a])) { ++a; continue; }
+        int region = L[a].region, tps_max = L[a].tps;
+        size_t b = a + 1;
+        while (b < L.size() && fits(L[b]) && L[b].form == L[a].form) {
+            const int r2 = std::max(region, L[b].region), t2 = std::max(tps_max, L[b].tps);
+            if (w * (size_t)t2 * r2 + 64 > 160 * 1024) break;
+            region = r2;
+            tps_max = t2;
+            ++b;
+        }
+        if (b - a >= 2 && w * (size_t)tps_max * region + 64 <= 160 * 1024) {
+            SwChain c{(int)items.size(), 0, L[a].form, region, tps_max};
+            for (size_t q = a; q < b; ++q) {
+                for (int r = 0; r < L[q].n; r += L[q].tps) {
+                    items.push_back(Item{0, L[q].off + 3 * r, L[q].tps, 0});
+                    c.nblk++;
+                }
+                L[q].group = (int)out.size();
+            }
+            out.push_back(c);
+        }
+        a = b;
+    }
+}
+
 // Epochs of the sweeps that chain levels: one per sweep, increasing over
 // the process, so a flag from an earlier sweep never equals the current one.
 std::atomic<unsigned long long> g_flow_epoch{0};
@@ -559,6 +607,7 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
 {
     M.items.clear();
     M.fwd64.clear(); M.bwd64.clear(); M.fwd32.clear(); M.bwd32.clear();
+    M.cf64.clear(); M.cb64.clear(); M.cf32.clear(); M.cb32.clear();
     M.nsys = (int)mem.size();
     if (mem.empty()) return;
     const irk_handle *h0 = mem[0].first;
@@ -589,7 +638,6 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         for (auto &pr : mem) L = std::max(L, (pr.first->W.*f).size());
         for (size_t l = 0; l < L; ++l) {
             std::vector<int> seen;
-            const int first_item = (int)M.items.size();
             for (auto &pr0 : mem) {
                 const auto &lv0 = pr0.first->W.*f;
                 if (l >= lv0.size()) continue;
@@ -629,9 +677,6 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
                 }
                 if (o.n) out.push_back(o);
             }
-            // a level split over several launches is not chained
-            if (seen.size() > 1)
-                for (size_t q = out.size(); q-- > 0 && out[q].off >= first_item;) out[q].chain = 0;
         }
     };
     merge(&WorkSet::mv64, M.mv64);
@@ -645,6 +690,10 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
             merge_sweeps(&WorkSet::fwd32, false, M.fwd32);
             merge_sweeps(&WorkSet::bwd32, false, M.bwd32);
         }
+        make_chains(M.items, M.fwd64, sizeof(double), M.cf64);
+        make_chains(M.items, M.bwd64, sizeof(double), M.cb64);
+        make_chains(M.items, M.fwd32, sizeof(float), M.cf32);
+        make_chains(M.items, M.bwd32, sizeof(float), M.cb32);
     }
 
     // LDS for the merged launches (template S = smax for every member)
@@ -673,35 +722,23 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
     const std::vector<SwLaunch> &B = fp64 ? W.bwd64 : W.bwd32;
     const int ft = fp64 ? FT_F64 : W.ftype;
     const size_t w = fp64 ? sizeof(double) : sizeof(float);
-    // Runs of consecutive chained levels (same form and elements per
-    // workgroup, whole workgroups) go in one launch each (k_sweep_flow.hip);
-    // every launch of such a sweep publishes its elements' flags with the
+    // Levels in a chain run in its one launch (k_sweep_flow.hip); every
+    // launch of a sweep with chains publishes its elements' flags with the
     // sweep's epoch, which the chained launches wait for.
-    auto run = [&](const std::vector<SwLaunch> &L, bool fwd, int acc) {
-        bool any = false;
-        for (const SwLaunch &x : L) any = any || x.chain;
-        const unsigned long long ep = (any && W.dticket) ? ++g_flow_epoch : 0;
+    const std::vector<SwChain> &CF = fp64 ? W.cf64 : W.cf32;
+    const std::vector<SwChain> &CB = fp64 ? W.cb64 : W.cb32;
+    auto run = [&](const std::vector<SwLaunch> &L, const std::vector<SwChain> &CH, bool fwd, int acc) {
+        const unsigned long long ep = (!CH.empty() && W.dticket) ? ++g_flow_epoch : 0;
         size_t a = 0;
         while (a < L.size()) {
             const SwLaunch &A = L[a];
-            if (ep && A.chain && A.n % A.tps == 0) {
-                int region = A.region;
-                size_t b = a + 1;
-                while (b < L.size() && L[b].chain && L[b].tps == A.tps && L[b].form == A.form &&
-                       L[b].n % A.tps == 0 && L[b].off == L[b - 1].off + 3 * L[b - 1].n &&
-                       w * A.tps * (size_t)std::max(region, L[b].region) + 64 <= 160 * 1024) {
-                    region = std::max(region, L[b].region);
-                    ++b;
-                }
-                if (b > a + 1) {
-                    const int nrec = (L[b - 1].off + 3 * L[b - 1].n - A.off) / 3;
-                    launch_sweep_flow(fwd, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + A.off),
-                                      nrec / A.tps, A.tps, region, W.smax, fp64, ft, W.coupled, W.sharedJ,
-                                      v_slot, v_index, acc, skip_done, w * A.tps * region, C.st, A.form,
-                                      W.dticket, ep);
-                    a = b;
-                    continue;
-                }
+            if (ep && A.group >= 0) {
+                const SwChain &c = CH[A.group];
+                launch_sweep_flow(fwd, W.dsys, W.ditems, c.tab, c.nblk, c.region, W.smax, fp64, ft, W.coupled,
+                                  W.sharedJ, v_slot, v_index, acc, skip_done, w * c.tps_max * c.region, C.st,
+                                  c.form, W.dticket, ep);
+                while (a < L.size() && L[a].group == A.group) ++a;
+                continue;
             }
             launch_sweep(fwd, W.dsys, reinterpret_cast<const SwItem *>(W.ditems + A.off), A.n, A.tps,
                          A.region, W.smax, fp64, ft, W.coupled, W.sharedJ, v_slot, v_index, acc, skip_done,
@@ -709,8 +746,8 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
             ++a;
         }
     };
-    run(F, true, -1);
-    run(B, false, acc_slot);
+    run(F, CF, true, -1);
+    run(B, CB, false, acc_slot);
     prof_end(C.prof, pi, PK_PC);
 }
 
@@ -1025,6 +1062,7 @@ static irk_status build_items(irk_handle *h)
     WorkSet &W = h->W;
     W.items.clear();
     W.fwd64.clear(); W.bwd64.clear(); W.fwd32.clear(); W.bwd32.clear();
+    W.cf64.clear(); W.cb64.clear(); W.cf32.clear(); W.cb32.clear();
     auto row_items = [&](int tpw, Launch &L) {
         L.off = (int)W.items.size();
         L.n = 0;
@@ -1052,6 +1090,10 @@ static irk_status build_items(irk_handle *h)
             add_level_records(W.items, h->sc, rp, ci, true, b, pb, sb, W.fwd32);
             add_level_records(W.items, h->sc, rp, ci, false, b, pb, sb, W.bwd32);
         }
+        make_chains(W.items, W.fwd64, sizeof(double), W.cf64);
+        make_chains(W.items, W.bwd64, sizeof(double), W.cb64);
+        make_chains(W.items, W.fwd32, sizeof(float), W.cf32);
+        make_chains(W.items, W.bwd32, sizeof(float), W.cb32);
     }
     // factor tasks, one launch per wavefront (stored after the work set's
     // items).  Uncoupled: wavefront = forward level; workgroup w takes stage
@@ -1776,7 +1818,7 @@ irk_status irk_destroy(irk_handle *h)
 // ---------------------------------------------------------------------------
 static constexpr size_t batch_items_bound(int capacity, long long max_elements)
 {
-    return (size_t)(24 * max_elements) + (size_t)capacity * (2 * RED_BLOCKS + 8);
+    return (size_t)(32 * max_elements) + (size_t)capacity * (2 * RED_BLOCKS + 8);
 }
 
 static constexpr size_t batch_ws_bytes(int capacity, long long max_elements)
@@ -2060,6 +2102,22 @@ irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_s
             if (F.n) launches.push_back(F);
         }
     }
+    // quantization of the mixed members' factors: one launch per factor
+    // type, chunks of 16 blocks
+    int q_off[4] = {0, 0, 0, 0}, q_n[4] = {0, 0, 0, 0};
+    for (int ft = FT_F32; ft <= FT_F16S; ++ft) {
+        q_off[ft] = (int)items.size();
+        for (int q = 0; q < n; ++q) {
+            const irk_handle *h = hs[q];
+            if (!h->mixed || h->opt.pc == IRK_PC_NONE || h->ftype != ft) continue;
+            const long long np = (long long)h->T * h->s;
+            const long long nc = h->coupled ? (long long)h->T * (h->s - 1) * (h->s - 2) : 0;
+            for (int kind = 0; kind < 2; ++kind)
+                for (long long b0 = 0; b0 < (kind ? nc : np); b0 += 16)
+                    items.push_back(Item{q, (int)b0, (int)std::min<long long>(16, (kind ? nc : np) - b0), kind});
+        }
+        q_n[ft] = (int)items.size() - q_off[ft];
+    }
     if (items.size() > b->max_items) return IRK_ERR_NOMEM;
     HIPCHK(hipMemcpyAsync(b->dtab, b->htab.data(), sizeof(SysDesc) * n, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->ditems, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice,
@@ -2068,8 +2126,8 @@ irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_s
     HIPCHK(hipEventRecord(b->ev_f0, b->stream));
     for (const FL &F : launches)
         launch_factor(b->dtab, b->ditems + F.off, F.n, F.coupled, F.sharedJ, F.m, F.shm, b->stream);
-    for (irk_handle *h : hs)
-        if (h->mixed && h->opt.pc != IRK_PC_NONE) launch_quantize(h->dsys, h->hsys, h->ftype, b->stream);
+    for (int ft = FT_F32; ft <= FT_F16S; ++ft)
+        if (q_n[ft] > 0) launch_quantize_sys(b->dtab, b->ditems + q_off[ft], q_n[ft], ft, b->stream);
     HIPCHK(hipEventRecord(b->ev_f1, b->stream));
     for (irk_handle *h : hs) HIPCHK(hipEventRecord(h->ev_done, b->stream));
     HIPCHK(hipGetLastError());

@@ -190,13 +190,15 @@ void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nre
                   hipStream_t st, int form, unsigned long long epoch = 0);
 
 // Consecutive levels of one sweep in a single launch (k_sweep_flow.hip):
-// workgroups take consecutive blocks of tps records in claim order (ticket
-// counter, back at zero when the launch ends), each element waits for the
-// flags of the neighbours it reads, then publishes its own flag = epoch.
-// recs: nblk * tps records, every level padded to whole workgroups
-// (i = -1), levels in sweep order.  epoch: the same for every launch of one
-// sweep, larger than any epoch an earlier sweep used on these flags.
-void launch_sweep_flow(bool forward, const SysDesc *dsys, const SwItem *recs, int nblk, int tps,
+// workgroups take the entries of the table items[tab .. tab + nblk) (first
+// record's item offset, records per workgroup; levels in sweep order) in
+// claim order (ticket counter, back at zero when the launch ends); each
+// element waits for the flags of the neighbours it reads, then publishes
+// its own flag = epoch.  A workgroup's records belong to one system and one
+// level (i = -1 pads).  region: LDS elements per team (the largest any
+// entry needs).  epoch: the same for every launch of one sweep, larger than
+// any epoch an earlier sweep used on these flags.
+void launch_sweep_flow(bool forward, const SysDesc *dsys, const Item *items, int tab, int nblk,
                        int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                        int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
                        hipStream_t st, int form, unsigned *ticket, unsigned long long epoch);
@@ -216,6 +218,9 @@ void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int 
                      int ldq, int ftype, hipStream_t st);
 // Quantize the FP64 factors to ftype (FP32 / BF16 / FP16 scaled).
 void launch_quantize(const SysDesc *dsys, const SysDesc &hsys, int ftype, hipStream_t st);
+// The same for several systems of one factor type in one launch: item =
+// (system, first block, block count, 0 pivots / 1 cross blocks).
+void launch_quantize_sys(const SysDesc *dsys, const Item *items, int nitems, int ftype, hipStream_t st);
 
 // ---- Krylov (FP64; vec items: (sys, chunk, chunks); fin items: one per system) ----
 // one Arnoldi step j: CGS2 passes, Givens update, v_{j+1} = w / ||w||

@@ -345,12 +345,10 @@ void launch_relayout(const double *src, void *dst, int dst_type, long long nblk,
 // e = 14 - E (clamped to [-100, 100]); stored value fp16(fp32(x * 2^e)).
 // ---------------------------------------------------------------------------
 template <int FT>
-__global__ __launch_bounds__(NTHREADS) void k_quantize(const double *__restrict__ src,
-                                                       void *__restrict__ dst, int *__restrict__ ex,
-                                                       int m, int ld, int ldq)
+__device__ __forceinline__ void quantize_block(const double *__restrict__ src, void *__restrict__ dst,
+                                               int *__restrict__ ex, int m, int ld, int ldq,
+                                               long long b, double *red)
 {
-    __shared__ double red[NTHREADS / 64];
-    const long long b = blockIdx.x;
     const double *S = src + b * (long long)m * ld;
     int e = 0;
     if (FT == FT_F16S) {
@@ -381,6 +379,44 @@ __global__ __launch_bounds__(NTHREADS) void k_quantize(const double *__restrict_
         else if (FT == FT_BF16) reinterpret_cast<uint16_t *>(dst)[o] = f32_to_bf16_rne((float)x);
         else reinterpret_cast<uint16_t *>(dst)[o] = f32_to_f16_rne((float)ldexp(x, e));
     }
+}
+
+template <int FT>
+__global__ __launch_bounds__(NTHREADS) void k_quantize(const double *__restrict__ src,
+                                                       void *__restrict__ dst, int *__restrict__ ex,
+                                                       int m, int ld, int ldq)
+{
+    __shared__ double red[NTHREADS / 64];
+    quantize_block<FT>(src, dst, ex, m, ld, ldq, blockIdx.x, red);
+}
+
+// The factors of several systems in one launch: item = (system, first
+// block, block count, 0 pivots / 1 cross blocks).
+template <int FT>
+__global__ __launch_bounds__(NTHREADS) void k_quantize_sys(const SysDesc *__restrict__ sysv,
+                                                           const Item *__restrict__ items)
+{
+    __shared__ double red[NTHREADS / 64];
+    const Item it = items[blockIdx.x];
+    const SysDesc &d = sysv[it.sys];
+    const bool cross = it.aux != 0;
+    const double *src = cross ? d.C64 : d.P64;
+    void *dst = (FT == FT_F32) ? (void *)(cross ? d.C32 : d.P32) : (void *)(cross ? d.C16 : d.P16);
+    int *ex = cross ? d.C16e : d.P16e;
+    const int ldq = (FT == FT_F32) ? d.ld32 : d.ld16;
+    for (int b = it.first; b < it.first + it.count; ++b) {
+        quantize_block<FT>(src, dst, ex, d.m, d.ld, ldq, b, red);
+        __syncthreads();   // red is reused by the next block
+    }
+}
+
+void launch_quantize_sys(const SysDesc *dsys, const Item *items, int nitems, int ftype, hipStream_t st)
+{
+    if (nitems <= 0) return;
+    dim3 grid((unsigned)nitems), block(NTHREADS);
+    if (ftype == FT_F32) hipLaunchKernelGGL(k_quantize_sys<FT_F32>, grid, block, 0, st, dsys, items);
+    else if (ftype == FT_BF16) hipLaunchKernelGGL(k_quantize_sys<FT_BF16>, grid, block, 0, st, dsys, items);
+    else hipLaunchKernelGGL(k_quantize_sys<FT_F16S>, grid, block, 0, st, dsys, items);
 }
 
 void quantize_blocks(const double *src, void *dst, int *ex, long long nblk, int m, int ld,

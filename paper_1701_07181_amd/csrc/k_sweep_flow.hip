@@ -13,11 +13,13 @@
 // chain of the current one, and a sweep costs one launch instead of one per
 // level.
 //
-// Progress without co-residency assumptions: workgroups take blocks of
-// records in the order they claim a ticket (one atomic increment), and the
-// records are in level order, so a task only waits for tasks with smaller
-// tickets, which belong to workgroups that are already running.  The last
-// claimant sets the counter back to zero, so every launch finds it at zero.
+// Progress without co-residency assumptions: workgroups take entries of a
+// workgroup table (first record, records per workgroup) in the order they
+// claim a ticket (one atomic increment), and the table is in level order,
+// so a task only waits for tasks with smaller tickets, which belong to
+// workgroups that are already running.  The last claimant sets the counter
+// back to zero, so every launch finds it at zero.  Entries may differ in
+// their records per workgroup (the members of a batch do), not in form.
 //
 // Flags hold the epoch of the sweep that published them (a 64-bit number
 // that grows with every sweep of the process that chains levels), so they
@@ -41,8 +43,8 @@ namespace irk {
 
 template <int S, typename TJ, typename TF, typename TC, bool COUPLED, bool SHJ, bool FWD, int PFM>
 __global__ __launch_bounds__(SW_THREADS) void k_sweep_flow(const SysDesc *__restrict__ sysv,
-                                                           const SwItem *__restrict__ recs, int nblk,
-                                                           int tps, int region, int v_slot,
+                                                           const Item *__restrict__ items, int tab,
+                                                           int nblk, int region, int v_slot,
                                                            int v_index, int acc_slot, int skip_done,
                                                            unsigned *ticket, unsigned long long epoch)
 {
@@ -57,15 +59,18 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep_flow(const SysDesc *__rest
     __syncthreads();
     const int blk = s_blk;
     if (blk >= nblk) return;   // (the counter was not at zero: no record to read)
+    const Item wg = items[tab + blk];
+    const int tps = __builtin_amdgcn_readfirstlane(wg.count);
+    const SwItem *recs = reinterpret_cast<const SwItem *>(items + __builtin_amdgcn_readfirstlane(wg.first));
     // every record of a workgroup belongs to one system and one level
-    const int sys = __builtin_amdgcn_readfirstlane(recs[(size_t)blk * tps].sys);
+    const int sys = __builtin_amdgcn_readfirstlane(recs[0].sys);
     const SysDesc &d = sysv[sys];
     // a finished system: none of its tasks runs, and no task of another
     // system waits for them
     if (skip_done && d.st->done) return;
     const int team = SW_THREADS / tps;
     const int tid = threadIdx.x % team;
-    const SwItem rec = recs[(size_t)blk * tps + threadIdx.x / team];
+    const SwItem rec = recs[threadIdx.x / team];
     const bool has = rec.i >= 0;
     sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PFM, true>(d, rec, has, tps, region, v_slot, v_index,
                                                            acc_slot, smem_raw, epoch, &s_late);
@@ -88,7 +93,7 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep_flow(const SysDesc *__rest
 }
 
 template <int S, typename TJ, typename TF, typename TC, int PFM>
-static void launch_flow_t(bool forward, const SysDesc *dsys, const SwItem *recs, int nblk, int tps,
+static void launch_flow_t(bool forward, const SysDesc *dsys, const Item *items, int tab, int nblk,
                           int region, bool coupled, bool sharedJ, int v_slot, int v_index,
                           int acc_slot, int skip_done, size_t shmem, hipStream_t st, unsigned *ticket,
                           unsigned long long epoch)
@@ -96,7 +101,7 @@ static void launch_flow_t(bool forward, const SysDesc *dsys, const SwItem *recs,
     dim3 grid(nblk), block(SW_THREADS);
 #define SWF(C, SH, F)                                                                                   \
     hipLaunchKernelGGL((k_sweep_flow<S, TJ, TF, TC, C, SH, F, pf_form(PFM, S, C, sizeof(TC) == 8)>),   \
-                       grid, block, shmem, st, dsys, recs, nblk, tps, region, v_slot, v_index,         \
+                       grid, block, shmem, st, dsys, items, tab, nblk, region, v_slot, v_index,        \
                        acc_slot, skip_done, ticket, epoch)
     if (forward) {
         if (coupled) { if (sharedJ) SWF(true, true, true); else SWF(true, false, true); }
@@ -109,13 +114,13 @@ static void launch_flow_t(bool forward, const SysDesc *dsys, const SwItem *recs,
 }
 
 template <int S, int PFM>
-static void launch_flow_p(bool forward, const SysDesc *dsys, const SwItem *recs, int nblk, int tps,
+static void launch_flow_p(bool forward, const SysDesc *dsys, const Item *items, int tab, int nblk,
                           int region, bool fp64, int ftype, bool coupled, bool sharedJ, int v_slot,
                           int v_index, int acc_slot, int skip_done, size_t shmem, hipStream_t st,
                           unsigned *ticket, unsigned long long epoch)
 {
 #define SWP(TJ, TF, TC)                                                                                \
-    launch_flow_t<S, TJ, TF, TC, PFM>(forward, dsys, recs, nblk, tps, region, coupled, sharedJ, v_slot, \
+    launch_flow_t<S, TJ, TF, TC, PFM>(forward, dsys, items, tab, nblk, region, coupled, sharedJ, v_slot, \
                                      v_index, acc_slot, skip_done, shmem, st, ticket, epoch)
     if (fp64) SWP(double, double, double);
     else if (ftype == FT_F32) SWP(float, float, float);
@@ -124,14 +129,14 @@ static void launch_flow_p(bool forward, const SysDesc *dsys, const SwItem *recs,
 #undef SWP
 }
 
-void launch_sweep_flow(bool forward, const SysDesc *dsys, const SwItem *recs, int nblk, int tps,
+void launch_sweep_flow(bool forward, const SysDesc *dsys, const Item *items, int tab, int nblk,
                        int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,
                        int v_slot, int v_index, int acc_slot, int skip_done, size_t shmem,
                        hipStream_t st, int form, unsigned *ticket, unsigned long long epoch)
 {
     if (nblk <= 0) return;
 #define SWF(SS, FM)                                                                                  \
-    launch_flow_p<SS, FM>(forward, dsys, recs, nblk, tps, region, fp64, ftype, coupled, sharedJ,      \
+    launch_flow_p<SS, FM>(forward, dsys, items, tab, nblk, region, fp64, ftype, coupled, sharedJ,     \
                           v_slot, v_index, acc_slot, skip_done, shmem, st, ticket, epoch)
 #define SWS(SS)                                                                                      \
     do {                                                                                             \

@@ -195,12 +195,20 @@ def test_flow_solve_equals_level_solve(pc, monkeypatch):
     ref.close()
 
 
+@pytest.mark.parametrize("mode", ["flow", "chain"])
 @pytest.mark.parametrize("pc,prec", [("coupled", "fp64"), ("uncoupled_shifted", "fp32")])
-def test_flow_batch_equals_solo(pc, prec, monkeypatch):
-    """Uneven members merged into one single-launch sweep per direction;
-    every member equals its solo solve bitwise."""
+def test_flow_batch_equals_solo(pc, prec, mode, monkeypatch):
+    """Uneven members (different block sizes, so different records per
+    workgroup) merged into chained launches (flow: one form for every level;
+    chain: every level chained in its own form); every member equals its
+    solo solve bitwise."""
     irk = _irk()
-    monkeypatch.setenv("IRK_SWEEP_FLOW", "1")
+    if mode == "flow":
+        monkeypatch.setenv("IRK_SWEEP_FLOW", "1")
+        monkeypatch.setenv("IRK_SWEEP_CHAIN", "0")
+    else:
+        monkeypatch.setenv("IRK_SWEEP_FLOW", "0")
+        monkeypatch.setenv("IRK_SWEEP_CHAIN", str(1 << 30))
     specs = dgsynth.batch_specs(count=10, seed=3300, Nmin=4, Nmax=8, pmax=2)
     systems = [sp.build() for sp in specs]
     mixed = prec != "fp64"
