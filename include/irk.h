@@ -53,7 +53,8 @@ typedef enum {
     IRK_ERR_BREAKDOWN = 5,   /* Arnoldi breakdown without convergence            */
     IRK_ERR_NONFINITE = 6,   /* NaN or Inf in the input or the iteration         */
     IRK_ERR_DEVICE = 7,      /* a HIP runtime call failed                        */
-    IRK_ERR_STATE = 8        /* call out of order (e.g. solve before factor)     */
+    IRK_ERR_STATE = 8,       /* call out of order (e.g. solve before factor)     */
+    IRK_ERR_INTERNAL = 9     /* an internal consistency check failed (a bug)     */
 } irk_status;
 
 typedef enum {
@@ -122,6 +123,25 @@ irk_status irk_default_options(irk_options *o);
 /* Device bytes the caller must provide to irk_setup for this problem and
  * these options.  Pure host computation. */
 irk_status irk_workspace_size(const irk_problem *p, const irk_options *o, size_t *bytes);
+
+/* The level schedule that the factorization and both sweeps follow (Sec.
+ * 4.2.1, Alg. 2: on a triangle-free mesh an element's pivot and sweep
+ * values need only its lower neighbours in the forward direction and its
+ * upper neighbours in the backward one).  Forward level of element i:
+ * 1 + the largest forward level of its lower neighbours (0 without any);
+ * backward level: the same over its upper neighbours.  lvl_fwd, lvl_bwd
+ * (HOST, T): the elements by ascending level, ascending element number
+ * within a level; off_fwd, off_bwd (HOST, T + 1): level l is
+ * lvl[off[l] .. off[l+1]); *nlev_fwd, *nlev_bwd: the level counts.  The
+ * pattern (row_ptr[T+1], col_idx[nnzb], HOST) is checked as irk_setup
+ * checks it: IRK_ERR_ARG for a malformed row pointer, a column out of
+ * range or out of order, a missing diagonal, an asymmetric pattern or a
+ * triangle; IRK_ERR_INTERNAL if the schedule fails its own check (every
+ * element listed once, after the neighbours it reads).  Host only; the
+ * caller owns every array. */
+irk_status irk_level_schedule(int T, int nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                              int *lvl_fwd, int *off_fwd, int *nlev_fwd, int *lvl_bwd, int *off_bwd,
+                              int *nlev_bwd);
 
 /* Set up the solver of the transformed Newton system B W = R (Sec. 4.1,
  * Eq. modified-IRK, written as Eq. big-irk in Sec. 4.3; the tableau A of Sec. 3, the block Jacobians of Sec. 2.1 and

@@ -20,7 +20,8 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libirk.so")
 
-OK, ERR_ARG, ERR_NOMEM, ERR_SINGULAR, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE, ERR_DEVICE, ERR_STATE = range(9)
+(OK, ERR_ARG, ERR_NOMEM, ERR_SINGULAR, ERR_NOCONV, ERR_BREAKDOWN, ERR_NONFINITE, ERR_DEVICE, ERR_STATE,
+ ERR_INTERNAL) = range(10)
 PC = {"coupled": 0, "uncoupled_shifted": 1, "uncoupled": 2, "none": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16s": 3}
 
@@ -120,6 +121,8 @@ _L.irk_radau_step.argtypes = [_vp, C.POINTER(_Rhs), _vp, C.c_double, _vp, _vp, C
                               _vp, C.c_size_t, C.POINTER(_StepInfo)]
 _L.irk_dirk_tableau.argtypes = [C.c_int, C.POINTER(C.c_int), _vp, _vp, _vp]
 _L.irk_dirk_workspace_size.argtypes = [_vp, C.c_int, C.POINTER(C.c_size_t)]
+_ip = C.POINTER(C.c_int)
+_L.irk_level_schedule.argtypes = [C.c_int, C.c_int, _vp, _vp, _vp, _vp, _ip, _vp, _vp, _ip]
 _L.irk_dirk_step.argtypes = [_vp, C.POINTER(_Rhs), C.c_int, _vp, C.c_double, _vp, _vp, C.c_double,
                              C.c_int, _vp, C.c_size_t, C.POINTER(_StepInfo)]
 
@@ -133,7 +136,7 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_apply_operator_inner", "irk_apply_preconditioner_inner",
             "irk_apply_operator_untransformed", "irk_step_workspace_size", "irk_radau_step",
             "irk_dirk_workspace_size", "irk_dirk_step", "irk_dirk_tableau",
-            "irk_solve_batched_noalloc"]
+            "irk_solve_batched_noalloc", "irk_level_schedule"]
 
 
 def _check(st: int, where: str):
@@ -150,6 +153,23 @@ def radau_iia(s: int):
     A = np.zeros((s, s)); b = np.zeros(s); c = np.zeros(s)
     _check(_L.irk_radau_iia(s, A.ctypes.data, b.ctypes.data, c.ctypes.data), "irk_radau_iia")
     return A, b, c
+
+
+def level_schedule(row_ptr, col_idx):
+    """The factorization's and sweeps' level schedule of a BSR pattern, from
+    the library: (lvl_fwd, off_fwd, lvl_bwd, off_bwd) as int32 arrays, level
+    l of a direction being lvl[off[l]:off[l + 1]].  Raises IrkError for a
+    pattern irk_setup would reject."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    T = len(rp) - 1
+    lf = np.zeros(T, np.int32); lb = np.zeros(T, np.int32)
+    of = np.zeros(T + 1, np.int32); ob = np.zeros(T + 1, np.int32)
+    nf = C.c_int(); nb = C.c_int()
+    _check(_L.irk_level_schedule(T, len(ci), rp.ctypes.data, ci.ctypes.data, lf.ctypes.data, of.ctypes.data,
+                                 C.byref(nf), lb.ctypes.data, ob.ctypes.data, C.byref(nb)),
+           "irk_level_schedule")
+    return lf, of[:nf.value + 1], lb, ob[:nb.value + 1]
 
 
 def dirk_tableau(name: str):

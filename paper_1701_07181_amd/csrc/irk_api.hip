@@ -3,6 +3,7 @@
 #include "irk.h"
 #include "irk_internal.h"
 #include "dense64.h"
+#include "schedule.h"
 
 #include <algorithm>
 #include <atomic>
@@ -109,79 +110,12 @@ void legendre_pd(int n, double t, double &p, double &dp)
 }
 
 // ---------------------------------------------------------------------------
-// problem checks and the level schedule
+// problem checks and the level schedule (schedule.h)
 // ---------------------------------------------------------------------------
-struct Schedule {
-    std::vector<int> diag, tpos, lvl_fwd, lvl_bwd, off_fwd, off_bwd;
-    int maxrow = 0;
-};
-
 irk_status analyze(const irk_problem *p, Schedule &sc)
 {
-    const int T = p->T;
-    const int32_t *rp = p->row_ptr, *ci = p->col_idx;
-    // the whole row pointer first: every later read of col_idx stays inside
-    // [0, nnzb) only if rp starts at 0, never decreases and ends at nnzb
-    if (rp[0] != 0 || rp[T] != p->nnzb) return IRK_ERR_ARG;
-    for (int i = 0; i < T; ++i)
-        if (rp[i + 1] < rp[i] || rp[i + 1] > p->nnzb) return IRK_ERR_ARG;
-    sc.diag.assign(T, -1);
-    sc.tpos.assign(p->nnzb, -1);
-    sc.maxrow = 0;
-    for (int i = 0; i < T; ++i) {
-        sc.maxrow = std::max(sc.maxrow, rp[i + 1] - rp[i]);
-        for (int q = rp[i]; q < rp[i + 1]; ++q) {
-            if (ci[q] < 0 || ci[q] >= T) return IRK_ERR_ARG;
-            if (q > rp[i] && ci[q] <= ci[q - 1]) return IRK_ERR_ARG;   // ascending, no repeats
-            if (ci[q] == i) sc.diag[i] = q;
-        }
-        if (sc.diag[i] < 0) return IRK_ERR_ARG;
-    }
-    auto find = [&](int row, int col) -> int {
-        const int32_t *b = ci + rp[row], *e = ci + rp[row + 1];
-        const int32_t *f = std::lower_bound(b, e, col);
-        return (f != e && *f == col) ? int(f - ci) : -1;
-    };
-    // structural symmetry, transpose positions, triangle-freeness
-    for (int i = 0; i < T; ++i)
-        for (int q = rp[i]; q < rp[i + 1]; ++q) {
-            const int j = ci[q];
-            const int t = find(j, i);
-            if (t < 0) return IRK_ERR_ARG;
-            sc.tpos[q] = t;
-            if (j == i) continue;
-            for (int q2 = q + 1; q2 < rp[i + 1]; ++q2) {
-                const int k = ci[q2];
-                if (k == i) continue;
-                if (find(j, k) >= 0) return IRK_ERR_ARG;   // j, k both neighbours of i and of each other
-            }
-        }
-    // forward levels: lev(i) = 1 + max over lower neighbours
-    std::vector<int> lf(T, 0), lb(T, 0);
-    int Lf = 0, Lb = 0;
-    for (int i = 0; i < T; ++i) {
-        int l = 0;
-        for (int q = rp[i]; q < sc.diag[i]; ++q) l = std::max(l, lf[ci[q]] + 1);
-        lf[i] = l;
-        Lf = std::max(Lf, l + 1);
-    }
-    for (int i = T - 1; i >= 0; --i) {
-        int l = 0;
-        for (int q = sc.diag[i] + 1; q < rp[i + 1]; ++q) l = std::max(l, lb[ci[q]] + 1);
-        lb[i] = l;
-        Lb = std::max(Lb, l + 1);
-    }
-    auto bucket = [&](const std::vector<int> &lev, int L, std::vector<int> &list, std::vector<int> &off) {
-        off.assign(L + 1, 0);
-        for (int i = 0; i < T; ++i) off[lev[i] + 1]++;
-        for (int l = 0; l < L; ++l) off[l + 1] += off[l];
-        list.assign(T, 0);
-        std::vector<int> pos(off.begin(), off.end() - 1);
-        for (int i = 0; i < T; ++i) list[pos[lev[i]]++] = i;
-    };
-    bucket(lf, Lf, sc.lvl_fwd, sc.off_fwd);
-    bucket(lb, Lb, sc.lvl_bwd, sc.off_bwd);
-    return IRK_OK;
+    const int st = analyze_pattern(p->T, p->nnzb, p->row_ptr, p->col_idx, sc);
+    return st == SCHED_OK ? IRK_OK : st == SCHED_BAD_PATTERN ? IRK_ERR_ARG : IRK_ERR_INTERNAL;
 }
 
 bool is_mixed(const irk_options *o) { return o->factor_prec != IRK_FP64 || o->matvec_prec != IRK_FP64; }
@@ -929,6 +863,7 @@ const char *irk_status_str(irk_status st)
     case IRK_ERR_NONFINITE: return "non-finite value";
     case IRK_ERR_DEVICE: return "HIP runtime error";
     case IRK_ERR_STATE: return "call out of order";
+    case IRK_ERR_INTERNAL: return "internal consistency check failed";
     }
     return "unknown status";
 }
@@ -946,6 +881,23 @@ irk_status irk_default_options(irk_options *o)
     o->max_outer = 20;
     o->rtol = 1e-10;
     o->inner_rtol = 1e-4;
+    return IRK_OK;
+}
+
+irk_status irk_level_schedule(int T, int nnzb, const int32_t *row_ptr, const int32_t *col_idx,
+                              int *lvl_fwd, int *off_fwd, int *nlev_fwd, int *lvl_bwd, int *off_bwd,
+                              int *nlev_bwd)
+{
+    if (!lvl_fwd || !off_fwd || !nlev_fwd || !lvl_bwd || !off_bwd || !nlev_bwd) return IRK_ERR_ARG;
+    Schedule sc;
+    const int st = analyze_pattern(T, nnzb, row_ptr, col_idx, sc);
+    if (st != SCHED_OK) return st == SCHED_BAD_PATTERN ? IRK_ERR_ARG : IRK_ERR_INTERNAL;
+    std::copy(sc.lvl_fwd.begin(), sc.lvl_fwd.end(), lvl_fwd);
+    std::copy(sc.off_fwd.begin(), sc.off_fwd.end(), off_fwd);
+    std::copy(sc.lvl_bwd.begin(), sc.lvl_bwd.end(), lvl_bwd);
+    std::copy(sc.off_bwd.begin(), sc.off_bwd.end(), off_bwd);
+    *nlev_fwd = (int)sc.off_fwd.size() - 1;
+    *nlev_bwd = (int)sc.off_bwd.size() - 1;
     return IRK_OK;
 }
 
