@@ -161,9 +161,10 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
 /* Replace J, M and dt (same pattern, same nJ): a new Newton iteration or
  * time step re-evaluates the Jacobians (Sec. 4.1) and must refactor
  * (Sec. 4.4: the preconditioner is computed once per linear solve).  J, M:
- * DEVICE, same layout as in irk_problem; read before the call returns (the
- * caller may free them afterwards).  The factors are stale until the next
- * irk_factor_ilu.  IRK_ERR_ARG for null pointers or dt <= 0. */
+ * DEVICE, same layout as in irk_problem; read by kernels on the handle's
+ * stream (the caller keeps them valid until that stream has passed this
+ * call, e.g. until the next solve returns).  The factors are stale until the
+ * next factorization.  IRK_ERR_ARG for null pointers or dt <= 0. */
 irk_status irk_update_values(irk_handle *h, const double *J, const double *M, double dt);
 
 /* Block ILU(0) factorization chosen by the options (Sec. 4.2.1 Alg. 2,
@@ -171,6 +172,16 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
  * in FP64 level by level; then quantized when factor_prec is not FP64.
  * Synchronizes; IRK_ERR_SINGULAR names the element in irk_last_bad_element. */
 irk_status irk_factor_ilu(irk_handle *h);
+
+/* The same factorization without waiting for it: returns once its launches
+ * are enqueued on the handle's stream, so the host prepares the next calls
+ * while it runs.  A singular pivot is reported by the next call that uses
+ * the factors: irk_gmres_solve (which reads the flag with the state it
+ * reads anyway after the initial residual), irk_apply_preconditioner(_inner),
+ * irk_export_factors, irk_autotune and irk_batch_admit (which wait for the
+ * stream first) return IRK_ERR_SINGULAR, irk_last_bad_element names the
+ * element, and the handle is not factored. */
+irk_status irk_factor_ilu_async(irk_handle *h);
 
 /* Solve B x = rhs (Sec. 4.3, Eq. big-irk) by restarted GMRES, right-
  * preconditioned with the factored block ILU(0) (Sec. 4.2-4.3), to

@@ -91,6 +91,7 @@ _L.irk_workspace_size.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), C.PO
 _L.irk_setup.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
 _L.irk_update_values.argtypes = [_vp, _vp, _vp, C.c_double]
 _L.irk_factor_ilu.argtypes = [_vp]
+_L.irk_factor_ilu_async.argtypes = [_vp]
 _L.irk_gmres_solve.argtypes = [_vp, _vp, _vp, C.POINTER(_Info)]
 _L.irk_solve_batched.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, C.POINTER(_Info)]
 _L.irk_solve_batched_noalloc.argtypes = [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.c_int, _vp,
@@ -136,7 +137,7 @@ EXPORTED = ["irk_default_options", "irk_workspace_size", "irk_setup", "irk_updat
             "irk_apply_operator_inner", "irk_apply_preconditioner_inner",
             "irk_apply_operator_untransformed", "irk_step_workspace_size", "irk_radau_step",
             "irk_dirk_workspace_size", "irk_dirk_step", "irk_dirk_tableau",
-            "irk_solve_batched_noalloc", "irk_level_schedule"]
+            "irk_solve_batched_noalloc", "irk_level_schedule", "irk_factor_ilu_async"]
 
 
 def _check(st: int, where: str):
@@ -319,8 +320,14 @@ class Solver:
                "irk_update_values")
         self.factored = False
 
-    def factor(self):
-        """Block ILU(0) factorization (raises IrkError on a singular pivot)."""
+    def factor(self, wait: bool = True):
+        """Block ILU(0) factorization (raises IrkError on a singular pivot).
+        wait=False: irk_factor_ilu_async (returns at once; a singular pivot
+        is raised by the next call that uses the factors)."""
+        if not wait:
+            _check(_L.irk_factor_ilu_async(self._h), "irk_factor_ilu_async")
+            self.factored = True
+            return
         st = _L.irk_factor_ilu(self._h)
         if st == ERR_SINGULAR:
             raise IrkError(st, f"irk_factor_ilu (element {_L.irk_last_bad_element(self._h)})")

@@ -352,12 +352,14 @@ struct irk_handle {
     std::vector<Item> fitems;
     size_t shm_fac;
     bool mixed, coupled, sharedJ, factored;
+    bool factor_pending = false;   // an asynchronous factorization's flags not read yet
     int ftype;
     int bad_element;
     float ms_factor;
     hipEvent_t ev0, ev1, ev_ready;
     hipEvent_t ev_done = nullptr;   // end of the last set-up, value update or factorization
     hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr;   // span of a time step
+    hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr;   // span of the last factorization
     SysDesc solve_desc;  // descriptor with the caller's rhs / x (staging for the copy)
     // profiling: event pool and recorded intervals (kind, event index)
     bool prof;
@@ -775,12 +777,14 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
     const bool fp64 = !W.mixed;
     // The host reads the systems' state only at some steps (the device ends
     // a system's cycle by itself: steps after its convergence do nothing).
-    // Several systems: every second step.  One system: the next read is
-    // placed one step before the step at which the estimate, shrinking at
-    // its last observed rate, would meet the tolerance.
+    // Several systems: every second step.  One system: first after two
+    // steps, then one step before the step at which the estimate, shrinking
+    // at the rate observed since the previous read (the cycle's starting
+    // residual for the first), would meet the tolerance.
     const int check_every = (W.nsys == 1) ? 1 : 2;
-    int next_check = check_every - 1;
-    double prev_est = -1.0;
+    int next_check = (W.nsys == 1) ? std::min(1, W.restart - 1) : check_every - 1;
+    double prev_est = (W.nsys == 1) ? hg[0].beta : -1.0;
+    int prev_j = -1;
     for (int j = 0; j < W.restart; ++j) {
         if (W.has_pc) {
             enqueue_pc(C, fp64, SL_V, j, -1, 1);
@@ -802,10 +806,12 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
             if (W.nsys == 1) {
                 const double est = hg[0].est, tol = hg[0].tol_abs;
                 if (prev_est > 0.0 && est > 0.0 && est < prev_est && tol > 0.0 && tol < est) {
-                    const double steps = std::log(tol / est) / std::log(est / prev_est);
+                    // steps still needed at the per-step rate since the last read
+                    const double steps = std::log(tol / est) * (j - prev_j) / std::log(est / prev_est);
                     if (steps > 2.0 && steps < 1e6) next_check = j + (int)steps - 1;
                 }
                 prev_est = est;
+                prev_j = j;
             }
         }
     }
@@ -813,29 +819,23 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
     // one more preconditioner application)
     launch_cycle_end(W.dsys, vec, W.vec.n, W.restart, W.has_pc ? SL_ZB : SL_V, C.st);
     launch_axpy(W.dsys, vec, W.vec.n, SL_X, SL_U, C.st);
-    // FP64 true residual and the next cycle
+    // FP64 true residual and the next cycle (whose start keeps the finished
+    // cycle's breakdown flag and estimate: one read for both)
     enqueue_matvec(C, true, SL_X, SL_R, SL_B, 1, 0);
-    // the last step's flags (breakdown, non-finite) are read before the reset
-    irk_status st = sync_states(C, dg, hg);
-    if (st != IRK_OK) return st;
-    std::vector<int> brk(W.nsys), nonf(W.nsys);
-    for (int q = 0; q < W.nsys; ++q) {
-        brk[q] = hg[q].breakdown; nonf[q] = hg[q].nonfinite;
-        sv[q]->est = hg[q].est / std::max(sv[q]->bn, 1e-300);
-    }
     launch_start_cycle(W.dsys, vec, W.vec.n, fin, W.fin.n, SL_R, C.st);
     HIPCHK(hipGetLastError());
-    st = sync_states(C, dg, hg);
+    irk_status st = sync_states(C, dg, hg);
     if (st != IRK_OK) return st;
     for (int q = 0; q < W.nsys; ++q) {
         Solve &S = *sv[q];
         const DevState &d = hg[q];
         const irk_options &o = S.h->opt;
         const double newrel = d.beta / S.bn;
+        S.est = d.prev_est / std::max(S.bn, 1e-300);
         S.cycles++;
-        if (nonf[q] || d.nonfinite || !std::isfinite(newrel)) { S.rel = newrel; finish(S, d, IRK_ERR_NONFINITE); continue; }
+        if (d.nonfinite || !std::isfinite(newrel)) { S.rel = newrel; finish(S, d, IRK_ERR_NONFINITE); continue; }
         if (newrel <= o.rtol) { S.rel = newrel; finish(S, d, IRK_OK); continue; }
-        if (brk[q] && !(newrel < 0.5 * S.rel)) {
+        if (d.prev_breakdown && !(newrel < 0.5 * S.rel)) {
             if (++S.stall >= 2) { S.rel = newrel; finish(S, d, IRK_ERR_BREAKDOWN); continue; }
         }
         S.rel = newrel;
@@ -1249,6 +1249,8 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming);
     hipEventCreate(&h->ev_s0);
     hipEventCreate(&h->ev_s1);
+    hipEventCreate(&h->ev_f0);
+    hipEventCreate(&h->ev_f1);
     std::vector<Item> all(W.items);
     all.insert(all.end(), h->fitems.begin(), h->fitems.end());
     bool ok = true;
@@ -1287,6 +1289,7 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
         HIPCHK(hipStreamSynchronize(h->stream));
     }
     h->factored = false;
+    h->factor_pending = false;
     if (h->ev_done) HIPCHK(hipEventRecord(h->ev_done, h->stream));
     return hipGetLastError() == hipSuccess ? IRK_OK : IRK_ERR_DEVICE;
 }
@@ -1295,20 +1298,21 @@ irk_status irk_factor_ilu(irk_handle *h)
 {
     if (!h) return IRK_ERR_ARG;
     if (h->opt.pc == IRK_PC_NONE) { h->factored = true; return IRK_OK; }
+    h->factor_pending = false;
     h->hst->singular = 0;
     h->hst->nonfinite = 0;
     HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
-    hipEventRecord(h->ev0, h->stream);
+    hipEventRecord(h->ev_f0, h->stream);
     const int pf = prof_begin(h);
     for (const Launch &F : h->fa)
         launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->stream);
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
     prof_end(h, pf, PK_FACTOR);
-    hipEventRecord(h->ev1, h->stream);
+    hipEventRecord(h->ev_f1, h->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    hipEventElapsedTime(&h->ms_factor, h->ev0, h->ev1);
+    hipEventElapsedTime(&h->ms_factor, h->ev_f0, h->ev_f1);
     HIPCHK(hipEventRecord(h->ev_done, h->stream));
     if (h->hst->singular) {
         h->bad_element = h->hst->singular - 1;
@@ -1317,6 +1321,27 @@ irk_status irk_factor_ilu(irk_handle *h)
     }
     h->bad_element = -1;
     h->factored = true;
+    return IRK_OK;
+}
+
+irk_status irk_factor_ilu_async(irk_handle *h)
+{
+    if (!h) return IRK_ERR_ARG;
+    if (h->opt.pc == IRK_PC_NONE) { h->factored = true; return IRK_OK; }
+    // flags cleared by a kernel (the pinned host copy may be in use)
+    launch_reset_factor_flags(h->dsys, h->ditems + h->W.fin.off, 1, h->stream);
+    hipEventRecord(h->ev_f0, h->stream);
+    const int pf = prof_begin(h);
+    for (const Launch &F : h->fa)
+        launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->stream);
+    if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
+    prof_end(h, pf, PK_FACTOR);
+    hipEventRecord(h->ev_f1, h->stream);
+    HIPCHK(hipEventRecord(h->ev_done, h->stream));
+    HIPCHK(hipGetLastError());
+    h->bad_element = -1;
+    h->factored = true;
+    h->factor_pending = true;
     return IRK_OK;
 }
 
@@ -1337,6 +1362,37 @@ irk_status irk_quantize_blocks(const double *src, long long nblk, int m, irk_pre
     return IRK_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The flags of an asynchronous factorization, once h->hst holds the state
+// copied after it: its time, and a singular pivot (the handle is then not
+// factored).
+irk_status settle_factor(irk_handle *h)
+{
+    if (!h->factor_pending) return IRK_OK;
+    h->factor_pending = false;
+    hipEventElapsedTime(&h->ms_factor, h->ev_f0, h->ev_f1);
+    if (h->hst->singular) {
+        h->bad_element = h->hst->singular - 1;
+        h->factored = false;
+        return IRK_ERR_SINGULAR;
+    }
+    return IRK_OK;
+}
+
+// The same for a call that has not read the state: waits for the stream.
+irk_status settle_factor_sync(irk_handle *h)
+{
+    if (!h->factor_pending) return IRK_OK;
+    HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return settle_factor(h);
+}
+}  // namespace
+
+extern "C" {
+
 irk_status irk_apply_operator(irk_handle *h, const double *x, double *y)
 {
     if (!h || !x || !y) return IRK_ERR_ARG;
@@ -1353,6 +1409,7 @@ irk_status irk_apply_preconditioner(irk_handle *h, const double *v, double *z)
 {
     if (!h || !v || !z) return IRK_ERR_ARG;
     if (!h->factored) return IRK_ERR_STATE;
+    if (irk_status fs = settle_factor_sync(h); fs != IRK_OK) return fs;
     const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
     if (h->opt.pc == IRK_PC_NONE) {
         HIPCHK(hipMemcpyAsync(z, v, bytes, hipMemcpyDeviceToDevice, h->stream));
@@ -1403,6 +1460,7 @@ irk_status irk_apply_preconditioner_inner(irk_handle *h, const double *v, double
 {
     if (!h || !v || !z) return IRK_ERR_ARG;
     if (!h->factored) return IRK_ERR_STATE;
+    if (irk_status fs = settle_factor_sync(h); fs != IRK_OK) return fs;
     if (!h->mixed || h->opt.pc == IRK_PC_NONE) return irk_apply_preconditioner(h, v, z);
     const size_t bytes = sizeof(double) * (size_t)h->hsys.N;
     const Item *vec = h->W.ditems + h->W.vec.off;
@@ -1423,6 +1481,7 @@ irk_status irk_export_factors(irk_handle *h, double *pinv, double *cross)
 {
     if (!h) return IRK_ERR_ARG;
     if (!h->factored || h->opt.pc == IRK_PC_NONE) return IRK_ERR_STATE;
+    if (irk_status fs = settle_factor_sync(h); fs != IRK_OK) return fs;
     launch_export(h->dsys, h->hsys, pinv, cross, h->coupled, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
     return IRK_OK;
@@ -1444,6 +1503,12 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
     S.x = x;
     std::vector<Solve *> sv{&S};
     irk_status st = init_systems(C, sv, h->dgather, h->hst);
+    // an asynchronous factorization ended before the initial residual (same
+    // stream): its flags are in the state just read
+    if (st == IRK_OK && h->factor_pending) {
+        st = settle_factor(h);
+        S.info.ms_factor = h->ms_factor;
+    }
     while (st == IRK_OK && !S.finished) st = run_cycle(C, sv, h->dgather, h->hst);
     // restore the workspace slots for the kernel-level entry points
     HIPCHK(hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
@@ -1761,6 +1826,8 @@ irk_status irk_destroy(irk_handle *h)
     if (h->ev_done) hipEventDestroy(h->ev_done);
     if (h->ev_s0) hipEventDestroy(h->ev_s0);
     if (h->ev_s1) hipEventDestroy(h->ev_s1);
+    if (h->ev_f0) hipEventDestroy(h->ev_f0);
+    if (h->ev_f1) hipEventDestroy(h->ev_f1);
     delete h;
     return IRK_OK;
 }
@@ -1854,6 +1921,7 @@ irk_status irk_batch_admit(irk_batch *b, irk_handle *h, const double *rhs, doubl
 {
     if (!b || !h || !rhs || !x) return IRK_ERR_ARG;
     if (!h->factored) return IRK_ERR_STATE;
+    if (irk_status fs = settle_factor_sync(h); fs != IRK_OK) return fs;
     if (b->free_slots.empty()) return IRK_ERR_NOMEM;
     long long elems = h->T;
     for (auto &m : b->members) elems += m.h->T;
@@ -2093,6 +2161,7 @@ irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_s
         irk_handle *h = hs[q];
         *h->hst = b->hgather[q];
         h->ms_factor = ms;             // the whole group's time
+        h->factor_pending = false;
         irk_status st = IRK_OK;
         if (h->opt.pc != IRK_PC_NONE && h->hst->singular) {
             h->bad_element = h->hst->singular - 1;
@@ -2297,6 +2366,7 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
 {
     if (!h) return IRK_ERR_ARG;
     if (h->opt.pc != IRK_PC_NONE && !h->factored) return IRK_ERR_STATE;
+    if (irk_status fs = settle_factor_sync(h); fs != IRK_OK) return fs;
     const std::vector<long long> key = tune_key(h);
     TuneVal best{h->tpw64, h->tpw32, h->sw64, h->sw32, 0.0f, 0.0f};
     bool cached = false;

@@ -49,6 +49,10 @@ struct DevState {
     int nonfinite;
     int iters;          // Arnoldi steps of the current solve
     double tol_abs;     // cycle ends when |g_{j+1}| <= tol_abs
+    // the finished cycle's breakdown flag and last estimate, kept by the
+    // start of the next cycle (so the host reads both in one copy)
+    int prev_breakdown;
+    double prev_est;
 };
 
 struct SysDesc {

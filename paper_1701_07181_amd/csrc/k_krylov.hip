@@ -234,6 +234,8 @@ __global__ __launch_bounds__(NTHREADS) void k_norm_finish(const SysDesc *__restr
         if (which == 0) {
             st->bnorm = nrm;
         } else {
+            st->prev_breakdown = st->breakdown;
+            st->prev_est = st->est;
             st->beta = nrm;
             st->rnorm2 = nrm;
             st->j = -1;

@@ -68,3 +68,54 @@ def test_nonfinite_jacobian_is_reported():
         sol.solve(sy.rhs)
     assert ei.value.status in (irk.ERR_SINGULAR, irk.ERR_NONFINITE)
 
+
+
+def test_async_factor_reports_singular_at_the_solve():
+    """irk_factor_ilu_async returns at once; the singular pivot comes back
+    from the solve, with the element, and the handle is then not factored."""
+    irk = _irk()
+    sy = dgsynth.config_system("cfg0")
+    bad = int(np.flatnonzero(sy.col_idx == 0)[0])
+    sy.M[0] = 0.0
+    sy.J[:, bad] = 0.0
+    sol = irk.Solver(sy, irk.Options(pc="uncoupled"))
+    sol.factor(wait=False)
+    x, info = sol.solve(sy.rhs, raise_on_error=False)
+    assert info["status"] == irk.ERR_SINGULAR
+    with pytest.raises(irk.IrkError) as ei:
+        sol.solve(sy.rhs)
+    assert ei.value.status == irk.ERR_STATE
+    # the same through a call that waits for the stream first
+    sol.factor(wait=False)
+    with pytest.raises(irk.IrkError) as ei:
+        sol.apply_preconditioner(sy.rhs)
+    assert ei.value.status == irk.ERR_SINGULAR
+
+
+@pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted"])
+def test_async_factor_equals_sync(pc):
+    """Same factors, same solve, bitwise, with and without waiting; a value
+    update between two asynchronous factorizations is honoured."""
+    irk = _irk()
+    sy = dgsynth.config_system("cfg0")
+    a = irk.Solver(sy, irk.Options(pc=pc))
+    b = irk.Solver(sy, irk.Options(pc=pc))
+    a.factor()
+    xa, ia = a.solve(sy.rhs)
+    b.factor(wait=False)
+    xb, ib = b.solve(sy.rhs)
+    assert ia["iters"] == ib["iters"] and torch.equal(xa, xb)
+    assert ib["ms_factor"] > 0
+    z = b.apply_preconditioner(sy.rhs)
+    assert torch.equal(z, a.apply_preconditioner(sy.rhs))
+    sy2 = dgsynth.config_system("cfg0", dt=0.3)
+    for s_ in (a, b):
+        s_.update_values(sy2.J, sy2.M, 0.3)
+    a.factor()
+    b.factor(wait=False)
+    b.factor(wait=False)
+    xa, ia = a.solve(sy.rhs)
+    xb, ib = b.solve(sy.rhs)
+    assert ia["iters"] == ib["iters"] and torch.equal(xa, xb)
+    a.close()
+    b.close()
