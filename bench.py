@@ -752,7 +752,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "autotune": {k: tune[k] for k in ("matvec_teams", "sweep_big_min", "sweep_teams", "sweep_big_form",
-                                              "sweep_flow", "sweep_chain_max")},
+                                              "sweep_flow", "sweep_chain_max", "sweep_split")},
         "iters": {"min": min(iters), "max": max(iters)},
         "equiv_mults": iters[0] * sy.s,
         "rel_res_true_max": res,

@@ -357,6 +357,8 @@ typedef struct {
                             Jacobian columns) */
     int sweep_chain_max; /* (sweep_flow 0) levels of fewer elements run chained: each run of
                             consecutive such levels of one form in one launch; 0 none */
+    int sweep_split;     /* (sweep_flow 0, streaming large levels) levels of fewer elements
+                            take sweep_teams / 2 elements per workgroup; 0 none */
 } irk_tune_info;
 
 /* Choose the launch shapes of a handle's matvec and preconditioner sweeps
@@ -370,16 +372,19 @@ typedef struct {
  * columns; then, on top of the best of these, the level size below which
  * consecutive levels run chained in one launch (32 to 1024, or every level),
  * each element waiting only for the neighbours it reads (variable
- * IRK_SWEEP_CHAIN fixes it); or every level of a direction in one launch in
+ * IRK_SWEEP_CHAIN fixes it), then the level size (256 to 1024) below which
+ * streaming levels take half the elements per workgroup (variable
+ * IRK_SWEEP_SPLIT fixes it); or every level of a direction in one launch in
  * one form (variable IRK_SWEEP_FLOW: 0 never, 1 always, 10 + form that form;
  * any value fixes this choice).  Each candidate is run once and timed over three runs on the
  * handle's stream; the fastest is kept.  The result is stored in a
  * process-wide table keyed by (m, s, preconditioner, precision, shared J,
  * row length, log2 T), and later calls for the same key (from any handle)
- * apply it without timing unless retime != 0.  The sweep results are
- * unchanged by the choice (every form accumulates in the same order); the
- * matvec's partial sums are combined in a different order, so results may
- * differ in the last bits.
+ * apply it without timing unless retime != 0.  The sweep results do not
+ * depend on the form or the chaining (each accumulates in the same order);
+ * the elements per workgroup of a level (the column groups of a team) and
+ * the matvec's shape change the order in which partial sums combine, so
+ * results may differ in the last bits.
  * h must be factored (IRK_ERR_STATE otherwise; any handle with pc NONE).
  * The handle's work vectors (not x, rhs or factors) are overwritten.
  * info may be NULL.  Synchronizes the handle's stream. */

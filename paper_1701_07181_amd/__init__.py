@@ -80,7 +80,7 @@ class _Tune(C.Structure):
     _fields_ = [("matvec_teams", C.c_int), ("sweep_big_min", C.c_int), ("sweep_teams", C.c_int),
                 ("from_cache", C.c_int), ("matvec_us", C.c_float), ("sweep_us", C.c_float),
                 ("sweep_big_form", C.c_int), ("sweep_flow", C.c_int),
-                ("sweep_chain_max", C.c_int)]
+                ("sweep_chain_max", C.c_int), ("sweep_split", C.c_int)]
 
 
 _vp = C.c_void_p

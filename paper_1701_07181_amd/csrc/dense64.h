@@ -22,7 +22,6 @@ namespace irk {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int D64_LDS_DOUBLES = 4291;       // the inversion's (the product uses none)
 
 // Fragment layouts of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l
 // supplies A(l % 16, l / 16) and B(l / 16, l % 16); element r of the result
@@ -56,17 +55,26 @@ struct D64Ops {
 // from global memory (leading dimension ld) or, with BLDS, from LDS
 // (leading dimension D64_LDX).
 constexpr int D64_LDX = 66;
+// LDS of the inversion: pivot columns and reciprocals (130 doubles), the
+// inverse (64 columns of D64_LDX doubles, where it stays after the call),
+// the permutation (130 ints).  The products take their LDS operand with the
+// same leading dimension.
+constexpr int D64_STAGE = 130;
+constexpr int D64_LDS_DOUBLES = D64_STAGE + 64 * D64_LDX + 65;
 
-template <bool BLDS>
+template <bool BLDS, bool ALDS = false>
 __device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, const GAS double *B, const double *Bs,
-                                             int m, int ld, int i0, int j0, int kq, int t)
+                                             int m, int ld, int i0, int j0, int kq, int t,
+                                             const double *As = nullptr)
 {
     const int kb = 8 * t + 2 * kq;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-            o.a[x][u] = A[(size_t)min(kb + u, m - 1) * ld + min(i0 + 16 * x, ld - 1)];
+        for (int u = 0; u < 2; ++u) {
+            if (ALDS) o.a[x][u] = As[min(kb + u, 63) * D64_LDX + i0 + 16 * x];
+            else o.a[x][u] = A[(size_t)min(kb + u, m - 1) * ld + min(i0 + 16 * x, ld - 1)];
+        }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
         if (BLDS) o.b[y] = *reinterpret_cast<const dbl2 *>(Bs + (j0 + 16 * y) * D64_LDX + min(kb, 62));
@@ -102,9 +110,14 @@ __device__ __forceinline__ void d64_mma_ops(const D64Ops &o, int m, int kq, int 
 // waits before each block's products leave the two later blocks' loads in
 // flight; otherwise blocks past the last one are skipped.
 // DEPTH operand buffers: DEPTH - 1 blocks in flight while one is multiplied.
-template <bool FULL, bool BLDS, int DEPTH = 3>
+// With BLDS / ALDS the operand comes from LDS (column-major, leading
+// dimension D64_LDX): entries outside the m x m block may hold anything
+// (those of K are zeroed, the others only reach result rows or columns
+// >= m).
+template <bool FULL, bool BLDS, int DEPTH = 3, bool ALDS = false>
 __device__ __forceinline__ void d64_accum(dbl4 (&acc)[2][2], int m, int ld, const GAS double *A,
-                                          const GAS double *B, const double *Bs, int nx, int ny)
+                                          const GAS double *B, const double *Bs, int nx, int ny,
+                                          const double *As = nullptr)
 {
     const int lane = threadIdx.x & 63, w = wave_id();
     const int r = lane & 15, kq = lane >> 4;
@@ -113,12 +126,12 @@ __device__ __forceinline__ void d64_accum(dbl4 (&acc)[2][2], int m, int ld, cons
     D64Ops o[DEPTH];
 #pragma unroll
     for (int t = 0; t < DEPTH - 1; ++t)
-        if (FULL || t < nb) d64_load_ops<BLDS>(o[t], A, B, Bs, m, ld, i0, j0, kq, t);
+        if (FULL || t < nb) d64_load_ops<BLDS, ALDS>(o[t], A, B, Bs, m, ld, i0, j0, kq, t, As);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         if (!FULL && t >= nb) continue;
         const int tn = t + DEPTH - 1;
-        if (FULL ? (tn < 8) : (tn < nb)) d64_load_ops<BLDS>(o[tn % DEPTH], A, B, Bs, m, ld, i0, j0, kq, tn);
+        if (FULL ? (tn < 8) : (tn < nb)) d64_load_ops<BLDS, ALDS>(o[tn % DEPTH], A, B, Bs, m, ld, i0, j0, kq, tn, As);
         d64_mma_ops<FULL>(o[t % DEPTH], m, kq, t, nx, ny, acc);
     }
 }
@@ -249,7 +262,8 @@ __device__ __forceinline__ void d64_publish(double v, unsigned long long unused,
 // with v_readlane and updates them.  The owner of column c+1 updates that
 // column first and publishes its pivot choice (look-ahead), so the search
 // overlaps the other updates and each step costs one barrier.
-// LDS: 2 * 64 + 2 + 64 * 64 doubles + 130 ints.
+// LDS: D64_LDS_DOUBLES; the inverse is left at lds + D64_STAGE (column c at
+// c * D64_LDX) for the caller's next product.
 __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *lds)
 {
     GAS double *g = gp(gptr);
@@ -257,8 +271,8 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
     const int lane = threadIdx.x & 63, w = wave_id();
     double *colbuf = lds;                                          // [2][64] pivot columns
     double *pinvbuf = lds + 128;                                   // [2] 1 / pivot
-    double *stage = lds + 130;                                     // [64][64] permuted result
-    int *pbuf = reinterpret_cast<int *>(lds + 130 + 64 * 64);      // [2] pivot row (+ flag)
+    double *stage = lds + D64_STAGE;                               // [64][D64_LDX] permuted result
+    int *pbuf = reinterpret_cast<int *>(lds + D64_STAGE + 64 * D64_LDX);   // [2] pivot row (+ flag)
     int *step_of_row = pbuf + 2;                                   // [64]
     int *row_of_step = pbuf + 66;                                  // [64]
     double a[16];
@@ -311,7 +325,7 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
     }
     __syncthreads();
     // the value kept for (row r, column c) is P^{-1}(step(r), row(c)) times
-    // the pivot of row r; stage[col * 64 + row] is written one column per
+    // the pivot of row r; stage[col * D64_LDX + row] is written one column per
     // instruction (conflict-free), then copied out column by column
     if (lane < m) {
         const int row = step_of_row[lane];
@@ -319,13 +333,13 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int c = 16 * w + j;
-            if (c < m) stage[row_of_step[c] * 64 + row] = a[j] * sc;
+            if (c < m) stage[row_of_step[c] * D64_LDX + row] = a[j] * sc;
         }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < m * 64; e += NTHREADS) {
         const int c = e >> 6, r = e & 63;
-        if (r < m) g[(size_t)c * ld + r] = stage[e];
+        if (r < m) g[(size_t)c * ld + r] = stage[c * D64_LDX + r];
     }
     __syncthreads();
     return bad;

@@ -31,8 +31,11 @@ struct Launch { int off, n; };
 struct SwLaunch { int off, n, tps; int form; int region; int chain; int group = -1; };
 // A run of consecutive chained levels of one form in one launch
 // (k_sweep_flow.hip): workgroup table at item offset tab (one Item per
-// workgroup: first record's item offset, records), nblk workgroups.
-struct SwChain { int tab, nblk, form, region, tps_max; };
+// workgroup: first record's item offset, records), nblk workgroups; region:
+// LDS elements per workgroup (the largest records-per-workgroup times team
+// region product of its levels; a workgroup of tps records gives each team
+// region / tps).
+struct SwChain { int tab, nblk, form, region; };
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -183,17 +186,24 @@ bool sweep_prefetch_fits(int S, bool coupled, int VJ, int VF, bool jac_cols = tr
 // form (0) with teams of at least 8 column groups, which keeps several
 // elements in flight per compute unit, or the prefetching form without the
 // Jacobian columns (2), which holds fewer registers than the full one.
+// Streaming levels of fewer than st_split elements take half tps_st elements
+// per workgroup (twice the threads per element), so that a level that does
+// not fill the compute units still spreads over them.
 struct SweepShape {
     int tps_pf; bool pf; int tps_st; int big_min; int big_form; bool pf_lite;
     bool flow;       // every level in one launch per direction (k_sweep_flow.hip)
     int flow_form;   // its form: 0 streaming (tps_st), 1 prefetching, 2 prefetching
                      // without the Jacobian columns (tps_pf)
     int chain_max;   // otherwise: levels of fewer elements run chained (0: none)
+    int st_split;    // 0: none
 };
+
+// elements per workgroup of the streaming levels below st_split (0: none)
+inline int st_small_tps(const SweepShape &sh) { return (sh.st_split > 0 && sh.tps_st >= 2) ? sh.tps_st / 2 : 0; }
 
 SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupled)
 {
-    SweepShape sh{0, false, 1, 0, 0, false, false, 0, 0};
+    SweepShape sh{0, false, 1, 0, 0, false, false, 0, 0, 0};
     const int RF = ldF / VF, RJ = ldJ / VJ, NQ = 8 / VF;
     for (int tpw = 1; tpw <= 16; tpw *= 2) {
         const int team = SW_THREADS / tpw;
@@ -216,6 +226,7 @@ SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupl
         if (f >= 10) sh.flow_form = (f - 10 == 1 && sh.pf) ? 1 : (f - 10 == 2 && sh.pf_lite) ? 2 : 0;
     }
     if (const char *e = std::getenv("IRK_SWEEP_CHAIN")) sh.chain_max = std::max(0, std::atoi(e));
+    if (const char *e = std::getenv("IRK_SWEEP_SPLIT")) sh.st_split = std::max(0, std::atoi(e));
     return sh;
 }
 
@@ -429,10 +440,11 @@ struct Ctx {
 };
 
 // Sweep records of every level (in level order) of one system, one launch
-// per level; region = LDS elements of one team.
+// per level; region = LDS elements of one team (region_st2: of a streaming
+// team at st_small_tps elements per workgroup).
 void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32_t *rp,
                        const int32_t *ci, bool fwd, const SweepShape &sh, int region_pf,
-                       int region_st, std::vector<SwLaunch> &out)
+                       int region_st, int region_st2, std::vector<SwLaunch> &out)
 {
     out.clear();
     const std::vector<int> &off = fwd ? sc.off_fwd : sc.off_bwd;
@@ -442,6 +454,10 @@ void add_level_records(std::vector<Item> &items, const Schedule &sc, const int32
         const bool lite = big && sh.big_form == 2 && sh.pf_lite;
         SwLaunch L{(int)items.size(), 0, (big && !lite) ? sh.tps_st : sh.tps_pf,
                    lite ? 2 : (sh.pf && !big ? 1 : 0), (big && !lite) ? region_st : region_pf};
+        if (big && !lite && st_small_tps(sh) && off[l + 1] - off[l] < sh.st_split) {
+            L.tps = st_small_tps(sh);
+            L.region = region_st2;
+        }
         if (sh.flow) {
             // one form for every level
             L.tps = sh.flow_form == 0 ? sh.tps_st : sh.tps_pf;
@@ -489,17 +505,16 @@ void make_chains(std::vector<Item> &items, std::vector<SwLaunch> &L, size_t w, s
     size_t a = 0;
     while (a < L.size()) {
         if (!fits(L[a])) { ++a; continue; }
-        int region = L[a].region, tps_max = L[a].tps;
+        int region = L[a].tps * L[a].region;
         size_t b = a + 1;
         while (b < L.size() && fits(L[b]) && L[b].form == L[a].form) {
-            const int r2 = std::max(region, L[b].region), t2 = std::max(tps_max, L[b].tps);
-            if (w * (size_t)t2 * r2 + 64 > 160 * 1024) break;
+            const int r2 = std::max(region, L[b].tps * L[b].region);
+            if (w * (size_t)r2 + 64 > 160 * 1024) break;
             region = r2;
-            tps_max = t2;
             ++b;
         }
-        if (b - a >= 2 && w * (size_t)tps_max * region + 64 <= 160 * 1024) {
-            SwChain c{(int)items.size(), 0, L[a].form, region, tps_max};
+        if (b - a >= 2 && w * (size_t)region + 64 <= 160 * 1024) {
+            SwChain c{(int)items.size(), 0, L[a].form, region};
             for (size_t q = a; q < b; ++q) {
                 for (int r = 0; r < L[q].n; r += L[q].tps) {
                     items.push_back(Item{0, L[q].off + 3 * r, L[q].tps, 0});
@@ -639,12 +654,14 @@ void build_merged(WorkSet &M, const std::vector<std::pair<irk_handle *, int>> &m
         const Plan &P = h->plan;
         const int mr = h->sc.maxrow;
         M.shm_mv64 = std::max(M.shm_mv64, lds_matvec(M.smax, h->m, mr, P.ld, 2, h->tpw64, sizeof(double)));
-        for (int tps : {h->sw64.tps_pf, h->sw64.tps_st})
-            M.shm_sw64 = std::max(M.shm_sw64, sizeof(double) * tps * (size_t)sw_region(M.smax, h->m, mr, P, true, h->ftype, tps));
+        for (int tps : {h->sw64.tps_pf, h->sw64.tps_st, st_small_tps(h->sw64)})
+            if (tps)
+                M.shm_sw64 = std::max(M.shm_sw64, sizeof(double) * tps * (size_t)sw_region(M.smax, h->m, mr, P, true, h->ftype, tps));
         if (M.mixed) {
             M.shm_mv32 = std::max(M.shm_mv32, lds_matvec(M.smax, h->m, mr, P.ld32, 4, h->tpw32, sizeof(float)));
-            for (int tps : {h->sw32.tps_pf, h->sw32.tps_st})
-                M.shm_sw32 = std::max(M.shm_sw32, sizeof(float) * tps * (size_t)sw_region(M.smax, h->m, mr, P, false, h->ftype, tps));
+            for (int tps : {h->sw32.tps_pf, h->sw32.tps_st, st_small_tps(h->sw32)})
+                if (tps)
+                    M.shm_sw32 = std::max(M.shm_sw32, sizeof(float) * tps * (size_t)sw_region(M.smax, h->m, mr, P, false, h->ftype, tps));
         }
     }
 }
@@ -671,7 +688,7 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
             if (ep && A.group >= 0) {
                 const SwChain &c = CH[A.group];
                 launch_sweep_flow(fwd, W.dsys, W.ditems, c.tab, c.nblk, c.region, W.smax, fp64, ft, W.coupled,
-                                  W.sharedJ, v_slot, v_index, acc, skip_done, w * c.tps_max * c.region, C.st,
+                                  W.sharedJ, v_slot, v_index, acc, skip_done, w * c.region, C.st,
                                   c.form, W.dticket, ep);
                 while (a < L.size() && L[a].group == A.group) ++a;
                 continue;
@@ -1034,13 +1051,15 @@ static irk_status build_items(irk_handle *h)
         const SweepShape &a = h->sw64, &b = h->sw32;
         const int pa = sw_region(s, m, mr, P, true, h->ftype, a.tps_pf);
         const int sa = sw_region(s, m, mr, P, true, h->ftype, a.tps_st);
-        add_level_records(W.items, h->sc, rp, ci, true, a, pa, sa, W.fwd64);
-        add_level_records(W.items, h->sc, rp, ci, false, a, pa, sa, W.bwd64);
+        const int sa2 = st_small_tps(a) ? sw_region(s, m, mr, P, true, h->ftype, st_small_tps(a)) : 0;
+        add_level_records(W.items, h->sc, rp, ci, true, a, pa, sa, sa2, W.fwd64);
+        add_level_records(W.items, h->sc, rp, ci, false, a, pa, sa, sa2, W.bwd64);
         if (h->mixed) {
             const int pb = sw_region(s, m, mr, P, false, h->ftype, b.tps_pf);
             const int sb = sw_region(s, m, mr, P, false, h->ftype, b.tps_st);
-            add_level_records(W.items, h->sc, rp, ci, true, b, pb, sb, W.fwd32);
-            add_level_records(W.items, h->sc, rp, ci, false, b, pb, sb, W.bwd32);
+            const int sb2 = st_small_tps(b) ? sw_region(s, m, mr, P, false, h->ftype, st_small_tps(b)) : 0;
+            add_level_records(W.items, h->sc, rp, ci, true, b, pb, sb, sb2, W.fwd32);
+            add_level_records(W.items, h->sc, rp, ci, false, b, pb, sb, sb2, W.bwd32);
         }
         make_chains(W.items, W.fwd64, sizeof(double), W.cf64);
         make_chains(W.items, W.bwd64, sizeof(double), W.cb64);
@@ -1095,10 +1114,11 @@ static irk_status build_items(irk_handle *h)
     const int maxrow = h->sc.maxrow;
     W.shm_mv64 = lds_matvec(s, m, maxrow, P.ld, 2, h->tpw64, sizeof(double));
     W.shm_mv32 = lds_matvec(s, m, maxrow, P.ld32, 4, h->tpw32, sizeof(float));
-    W.shm_sw64 = sizeof(double) * std::max(h->sw64.tps_pf * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_pf),
-                                           h->sw64.tps_st * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, h->sw64.tps_st));
-    W.shm_sw32 = sizeof(float) * std::max(h->sw32.tps_pf * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_pf),
-                                          h->sw32.tps_st * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, h->sw32.tps_st));
+    W.shm_sw64 = W.shm_sw32 = 0;
+    for (int tps : {h->sw64.tps_pf, h->sw64.tps_st, st_small_tps(h->sw64)})
+        if (tps) W.shm_sw64 = std::max(W.shm_sw64, sizeof(double) * tps * (size_t)sw_region(s, m, maxrow, P, true, h->ftype, tps));
+    for (int tps : {h->sw32.tps_pf, h->sw32.tps_st, st_small_tps(h->sw32)})
+        if (tps) W.shm_sw32 = std::max(W.shm_sw32, sizeof(float) * tps * (size_t)sw_region(s, m, maxrow, P, false, h->ftype, tps));
     // factorization: matrix-core products and register Gauss-Jordan, four
     // waves for m <= 64, eight above
     h->shm_fac = sizeof(double) * (size_t)((m <= 64) ? D64_LDS_DOUBLES : std::max(DM_LDS_DOUBLES, DMI_LDS_DOUBLES));
@@ -2418,6 +2438,7 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
             // single-launch / chaining choice)
             const bool flow_fixed = std::getenv("IRK_SWEEP_FLOW") != nullptr;
             const bool chain_fixed = std::getenv("IRK_SWEEP_CHAIN") != nullptr;
+            const bool split_fixed = std::getenv("IRK_SWEEP_SPLIT") != nullptr;
             auto time_shape = [&](const SweepShape &cand) -> irk_status {
                 sh = cand;
                 if (build_items(h) != IRK_OK) return IRK_OK;
@@ -2458,6 +2479,17 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
                     irk_status st = time_shape(c);
                     if (st != IRK_OK) return st;
                 }
+                // streaming levels below a size at half the elements per workgroup
+                const SweepShape chained = cbest;
+                if (!split_fixed && chained.tps_st >= 2 && chained.big_form == 0 && chained.big_min < (1 << 30)) {
+                    for (int sp : {256, 384, 512, 768, 1024}) {
+                        if (sp <= chained.big_min) continue;
+                        SweepShape c = chained;
+                        c.st_split = sp;
+                        irk_status st = time_shape(c);
+                        if (st != IRK_OK) return st;
+                    }
+                }
                 // every level of a direction in one launch, in each form that fits
                 for (int ff = 0; ff < 3 && !flow_fixed; ++ff) {
                     if ((ff == 1 && !base.pf) || (ff == 2 && !base.pf_lite)) continue;
@@ -2490,6 +2522,7 @@ extern "C" irk_status irk_autotune(irk_handle *h, int retime, irk_tune_info *inf
         info->sweep_big_form = sh.big_form;
         info->sweep_flow = sh.flow ? 1 + sh.flow_form : 0;
         info->sweep_chain_max = sh.flow ? 0 : sh.chain_max;
+        info->sweep_split = st_small_tps(sh) ? sh.st_split : 0;
         info->from_cache = cached ? 1 : 0;
         info->matvec_us = best.matvec_us;
         info->sweep_us = best.sweep_us;

@@ -199,8 +199,9 @@ void launch_sweep(bool forward, const SysDesc *dsys, const SwItem *recs, int nre
 // claim order (ticket counter, back at zero when the launch ends); each
 // element waits for the flags of the neighbours it reads, then publishes
 // its own flag = epoch.  A workgroup's records belong to one system and one
-// level (i = -1 pads).  region: LDS elements per team (the largest any
-// entry needs).  epoch: the same for every launch of one sweep, larger than
+// level (i = -1 pads).  region: LDS elements per workgroup; a workgroup of
+// tps records gives each team region / tps (at least what any entry
+// needs).  epoch: the same for every launch of one sweep, larger than
 // any epoch an earlier sweep used on these flags.
 void launch_sweep_flow(bool forward, const SysDesc *dsys, const Item *items, int tab, int nblk,
                        int region, int s_max, bool fp64, int ftype, bool coupled, bool sharedJ,

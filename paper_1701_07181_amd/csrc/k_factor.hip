@@ -146,6 +146,147 @@ __device__ __forceinline__ double *cross_blk(const SysDesc &d, long long i, int 
     return d.C64 + (i * (s - 1) * (s - 2) + e) * bs;
 }
 
+// This wave's accumulators (tiles of its quadrant) into an LDS block with
+// leading dimension D64_LDX.
+template <bool FULL>
+__device__ __forceinline__ void d64_put_lds(const dbl4 (&acc)[2][2], double *Ls, int nx, int ny)
+{
+    const int lane = threadIdx.x & 63, w = wave_id();
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            if (!FULL && (x >= nx || y >= ny)) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                Ls[d64_tile_col(lane, w, y) * D64_LDX + d64_tile_row(lane, w, x, q)] = acc[x][y][q];
+        }
+}
+
+// Stage round of task (k, i) for m <= 64, right after the inverse, which
+// leaves P_k^{-1} in LDS.  L = (k = 0: M_i; else C_lk) P_k^{-1} is kept in
+// LDS (in place of P_k^{-1}) for the products that consume it, so neither L
+// nor X goes through memory:
+//   k = 0: X = L M_i in registers; the later stages' pivots and stored
+//          cross blocks are written from X directly;
+//   k >= 1: for every later stage l, P_l -= L C_kl and C_lq -= L C_kq.
+// P_k^{-1} is read from LDS by the first L product when that is the only
+// one (k = 0 or k = s - 2), else from memory (the inverse has written it).
+// The products and their order are those of the file comment; the results
+// are those of the same products through memory.
+template <bool FULL, bool SHJ>
+__device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int k, double *lds)
+{
+    const int s = d.s, lane = threadIdx.x & 63, w = wave_id();
+    int m = d.m, ld = d.ld;
+    asm volatile("" : "+s"(m), "+s"(ld));
+    const long long bs = (long long)m * ld;
+    const int nx = FULL ? 2 : d64_ntiles(m, w & 1), ny = FULL ? 2 : d64_ntiles(m, w >> 1);
+    const bool act = nx > 0 && ny > 0;
+    double *Ls = lds + D64_STAGE;
+    const GAS double *Mi = gp(d.Mc + (long long)i * bs);
+    dbl4 acc[2][2];
+    auto clear = [&]() {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+    };
+    const bool one_l = (k == 0) || (k == s - 2);
+    for (int l = k + 1; l < s; ++l) {
+        // L = A P_k^{-1}
+        const GAS double *A = k == 0 ? Mi : gp(cross_blk(d, i, l, k));
+        clear();
+        if (act) {
+            if (one_l) d64_accum<FULL, true>(acc, m, ld, A, nullptr, Ls, nx, ny);
+            else d64_accum<FULL, false>(acc, m, ld, A, gp(d.P64 + ((long long)i * s + k) * bs), nullptr, nx, ny);
+        }
+        __syncthreads();                          // P_k^{-1} / the previous L is consumed
+        if (act) d64_put_lds<FULL>(acc, Ls, nx, ny);
+        __syncthreads();
+        if (k == 0) break;
+        // P_l -= L C_kl, C_lq -= L C_kq (q > k, q != l), q in order
+        for (int q = k + 1; q < s; ++q) {
+            GAS double *D = gp(q == l ? d.P64 + ((long long)i * s + l) * bs : cross_blk(d, i, l, q));
+            const GAS double *B = gp(cross_blk(d, i, k, q));
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
+                        const double old = D[(size_t)min(c, m - 1) * ld + min(r, m - 1)];
+                        acc[x][y][e] = (r < m && c < m) ? -old : 0.0;
+                    }
+            if (act) d64_accum<FULL, false, 3, true>(acc, m, ld, nullptr, B, nullptr, nx, ny, Ls);
+            if (act) {
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        if (!FULL && (x >= nx || y >= ny)) continue;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
+                            if (r < m && c < m) D[(size_t)c * ld + r] = -acc[x][y][e];
+                        }
+                    }
+            }
+        }
+        __syncthreads();                          // L is consumed before the next one is stored
+    }
+    if (k != 0) return;
+    // X = L M_i, then for every later stage l:
+    //   P_l = d_l M_i - dt J_l,ii - A^{-1}_l0 A^{-1}_0l X,  C_lq = A^{-1}_lq M_i - A^{-1}_l0 A^{-1}_0q X
+    clear();
+    if (act) d64_accum<FULL, false, 3, true>(acc, m, ld, nullptr, Mi, nullptr, nx, ny, Ls);
+    const double dt = d.dt;
+    const long long dp = gp(d.diag_pos)[i];
+    double mv[2][2][4];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
+                mv[x][y][e] = Mi[(size_t)min(c, m - 1) * ld + min(r, m - 1)];
+            }
+    for (int l = 1; l < s; ++l) {
+        const GAS double *Jd = gp(d.Jc + (SHJ ? 0 : (long long)l * d.nnzb * bs) + dp * bs);
+        const double dl = d.dcoef[l], fl = d.Ainv[l * SMAX] * d.Ainv[l];
+        GAS double *Pl = gp(d.P64 + ((long long)i * s + l) * bs);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
+                    if (c >= m || r >= ld) continue;
+                    const size_t o = (size_t)c * ld + r;
+                    // (padding rows r >= m of a block stay zero)
+                    Pl[o] = r < m ? dl * mv[x][y][e] - dt * Jd[o] - fl * acc[x][y][e] : 0.0;
+                }
+        for (int q = 1; q < s; ++q) {
+            if (q == l) continue;
+            GAS double *Cq = gp(cross_blk(d, i, l, q));
+            const double a = d.Ainv[l * SMAX + q], f = d.Ainv[l * SMAX] * d.Ainv[q];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
+                        if (c >= m || r >= ld) continue;
+                        Cq[(size_t)c * ld + r] = r < m ? a * mv[x][y][e] - f * acc[x][y][e] : 0.0;
+                    }
+        }
+    }
+}
+
 // One task: stage k of element i (see the file comment).  The products of a
 // task are one operation list (the neighbour products for m > 64, then the
 // stage round), so a kernel holds one inlined copy of the product and one of
@@ -176,7 +317,14 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
     if (CLS == 0) {
         if (m > 56) factor_small_products<true>(d, i, k, Jk, Pk, from_p, lds);
         else factor_small_products<false>(d, i, k, Jk, Pk, from_p, lds);
-    } else if (!from_p) {
+        if (d64_invert(Pk, m, ld, lds)) flag_singular(d, i);
+        if (COUPLED && k + 1 < s) {
+            if (m > 56) factor_round_small<true, SHJ>(d, i, k, lds);
+            else factor_round_small<false, SHJ>(d, i, k, lds);
+        }
+        return;
+    }
+    if (!from_p) {
         const double *Jd = Jk + (long long)diag_pos[i] * bs;
         const double dk = d.dcoef[k];
         for (long long e = threadIdx.x; e < bs; e += TEAM) gp(Pk)[e] = dk * gp(Mi)[e] - dt * gp(Jd)[e];

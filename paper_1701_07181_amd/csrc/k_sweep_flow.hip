@@ -19,7 +19,9 @@
 // so a task only waits for tasks with smaller tickets, which belong to
 // workgroups that are already running.  The last claimant sets the counter
 // back to zero, so every launch finds it at zero.  Entries may differ in
-// their records per workgroup (the members of a batch do), not in form.
+// their records per workgroup (the members of a batch do, and so may the
+// levels of one system), not in form; the LDS of a workgroup is split
+// evenly among its teams.
 //
 // Flags hold the epoch of the sweep that published them (a 64-bit number
 // that grows with every sweep of the process that chains levels), so they
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(SW_THREADS) void k_sweep_flow(const SysDesc *__rest
     const int tid = threadIdx.x % team;
     const SwItem rec = recs[threadIdx.x / team];
     const bool has = rec.i >= 0;
-    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PFM, true>(d, rec, has, tps, region, v_slot, v_index,
+    sweep_item<S, TJ, TF, TC, COUPLED, SHJ, FWD, PFM, true>(d, rec, has, tps, region / tps, v_slot, v_index,
                                                            acc_slot, smem_raw, epoch, &s_late);
     __syncthreads();
     if (s_late) {

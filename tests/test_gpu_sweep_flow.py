@@ -262,3 +262,40 @@ def test_chained_levels_equal_level_launches(pc, case, monkeypatch):
     assert info2["iters"] == info["iters"] and torch.equal(x, x2)
     sol.close()
     ref.close()
+
+
+@pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted"])
+@pytest.mark.parametrize("case", [(3, 2, 12, 16, 1), (2, 3, 5, 20, 2), (3, 2, 8, 64, 1)], ids=_ids)
+def test_split_streaming_levels(pc, case, monkeypatch):
+    """Streaming levels below IRK_SWEEP_SPLIT at half the elements per
+    workgroup: element-wise parity with the oracle; chained launches (whose
+    workgroups then differ in elements per workgroup) bitwise equal to one
+    launch per level with the same split; a solve converges to the same
+    iterations as without the split."""
+    irk = _irk()
+    s, dim, N, m, nJ = case
+    sy = _system(s, dim, N, m, nJ, seed=47)
+    opts = irk.Options(pc=pc)
+    v = np.random.default_rng(48).standard_normal(s * sy.T * sy.m)
+    A, _, _ = oracle.radau_iia(s)
+    zo = oracle.pc_apply(oracle.Problem(sy), A, pc, v)
+    lv = irk.level_schedule(sy.row_ptr, sy.col_idx)
+    sizes = sorted({int(b - a) for off in (lv[1], lv[3]) for a, b in zip(off[:-1], off[1:])})
+    _say("split", pc, case, "level sizes", sizes)
+    plain = _solver(irk, sy, opts, monkeypatch, "0", big="8", chain="0")
+    x0, info0 = plain.solve(sy.rhs)
+    plain.close()
+    for split in (str(sizes[len(sizes) // 2] + 1), str(1 << 30)):
+        monkeypatch.setenv("IRK_SWEEP_SPLIT", split)
+        ref = _solver(irk, sy, opts, monkeypatch, "0", big="8", chain="0")
+        zr = ref.apply_preconditioner(v)
+        assert _rel(zr.cpu().numpy(), zo) < 1e-11, split
+        sol = _solver(irk, sy, opts, monkeypatch, "0", big="8", chain=str(1 << 30))
+        _say("split chained", pc, case, split)
+        for _ in range(3):
+            assert torch.equal(sol.apply_preconditioner(v), zr), split
+        x, info = sol.solve(sy.rhs)
+        assert info["converged"] and info["iters"] == info0["iters"]
+        assert float(torch.linalg.norm(x - x0) / torch.linalg.norm(x0)) < 1e-11
+        sol.close()
+        ref.close()
