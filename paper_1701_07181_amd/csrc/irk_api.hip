@@ -270,7 +270,9 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     if (o->pc != IRK_PC_NONE) {
         P.o_P64 = take(sizeof(double) * (size_t)nblkP * m * P.ld);
         if (nblkC) P.o_C64 = take(sizeof(double) * (size_t)nblkC * m * P.ld);
-        P.o_Fscr = take(sizeof(double) * (size_t)nblkP * m * P.ld);
+        // product scratch of the factorization for m > 64 (smaller blocks
+        // keep their intermediate products in registers and LDS)
+        if (m > 64) P.o_Fscr = take(sizeof(double) * (size_t)nblkP * m * P.ld);
         if (mixed && ft == FT_F32) {
             P.o_P32 = take(sizeof(float) * (size_t)nblkP * m * P.ld32);
             if (nblkC) P.o_C32 = take(sizeof(float) * (size_t)nblkC * m * P.ld32);
@@ -535,7 +537,7 @@ std::atomic<unsigned long long> g_flow_epoch{0};
 int reduction_chunks(long long N)
 {
     const long long nb = (N + NTHREADS * 4 - 1) / (NTHREADS * 4);
-    return (int)std::max(1LL, std::min<long long>(nb, 512));
+    return (int)std::max(1LL, std::min<long long>(nb, RED_BANK));
 }
 
 size_t lds_matvec(int S, int m, int maxrow, int ld, int V, int tpw, size_t w)
@@ -1225,7 +1227,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     if (h->mixed) { d.Jc32 = (const float *)(ws + P.o_J32); d.Mc32 = (const float *)(ws + P.o_M32); }
     if (o->pc != IRK_PC_NONE) {
         d.P64 = (double *)(ws + P.o_P64);
-        d.Fscr = (double *)(ws + P.o_Fscr);
+        d.Fscr = P.o_Fscr ? (double *)(ws + P.o_Fscr) : nullptr;
         if (P.o_C64) d.C64 = (double *)(ws + P.o_C64);
         if (P.o_P32) d.P32 = (float *)(ws + P.o_P32);
         if (P.o_C32) d.C32 = (float *)(ws + P.o_C32);

@@ -17,7 +17,8 @@ constexpr int MMAX = 160;        // largest block size
 constexpr int RESTART_MAX = 64;  // largest Krylov dimension
 constexpr int NTHREADS = 256;    // threads per workgroup of the element kernels
 constexpr int SW_THREADS = 512;  // threads per workgroup of the sweep kernels
-constexpr int RED_BLOCKS = 1024; // workgroups of the vector reduction kernels (max)
+constexpr int RED_BLOCKS = 1024; // rows of reduction partials (two banks)
+constexpr int RED_BANK = RED_BLOCKS / 2;   // workgroups of a vector reduction kernel (max)
 
 enum Slot : int {
     SL_V = 0,   // Krylov basis, index j selects v_j            (FP64)

@@ -5,18 +5,22 @@
 //
 // Work items: a vector kernel gets one item per (system, chunk); chunk c of
 // a system with nc chunks covers the elements c*256 + t, stepping nc*256.
-// Reductions write one partial per chunk; a finish kernel with one
-// workgroup per system adds them in a fixed order (deterministic, and the
-// kernel boundary orders the partials without device-wide fences).
+// Reductions write one partial per chunk; the next kernel adds them in a
+// fixed order (deterministic, and the kernel boundary orders the partials
+// without device-wide fences): a finish kernel with one workgroup per
+// system, or, for coefficients the next pass needs, every workgroup of that
+// pass (the same sums in each).
 //
 // One Arnoldi step j (the same j for every system of a launch; systems whose
 // cycle already ended, st->done, skip):
-//   pass 0: h1 = V_{0..j}^T w
-//   pass 1: w -= V h1 and, with the same loaded basis entries, h2 = V^T w
-//   pass 2: w -= V h2 and ||w||^2; its finish kernel forms the Hessenberg
-//           column h1 + h2, applies the Givens rotations, updates the
-//           residual estimate |g_{j+1}| and sets done when it drops below the
-//           system's cycle tolerance (or on breakdown / non-finite values)
+//   pass 0: partials of h1 = V_{0..j}^T w
+//   pass 1: h1 from them; w -= V h1 and, with the same loaded basis
+//           entries, partials of h2 = V^T w
+//   pass 2: h2 from them; w -= V h2 and partials of ||w||^2; its finish
+//           kernel forms the Hessenberg column h1 + h2, applies the Givens
+//           rotations, updates the residual estimate |g_{j+1}| and sets done
+//           when it drops below the system's cycle tolerance (or on
+//           breakdown / non-finite values)
 //   scale:  v_{j+1} = w / ||w||
 #include "irk_device.h"
 
@@ -36,18 +40,20 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], int nv, double *lds) {
     __syncthreads();
 }
 
-// Add the partials part[b][p] (b < nblk, p < nv) in a fixed order: every
-// thread sums the blocks b = t, t + 256, ... for all p, then the fixed
-// wave/LDS tree.  One workgroup.
+// Partials are kept in two banks of RED_BANK rows (a pass reads the bank
+// the previous pass wrote while it writes the other).
+// Add the partials part[bank][b][p] (b < nblk, p < nv) in a fixed order:
+// every thread sums the blocks b = t, t + 256, ... for all p, then the
+// fixed wave/LDS tree.  Any workgroup that runs it gets the same sums.
 template <int NVMAX>
-__device__ void reduce_partials(const SysDesc &d, int nblk, int nv, double *out) {
+__device__ void reduce_partials(const SysDesc &d, int nblk, int nv, double *out, int bank = 0) {
     __shared__ double red[4 * NVMAX];
     const int stride = RESTART_MAX + 2;
     double a[NVMAX];
 #pragma unroll
     for (int p = 0; p < NVMAX; ++p) a[p] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += NTHREADS) {
-        const GAS double *row = gp(d.part) + (size_t)b * stride;
+        const GAS double *row = gp(d.part) + (size_t)(b + bank * RED_BANK) * stride;
 #pragma unroll
         for (int p = 0; p < NVMAX; ++p)
             if (p < nv) a[p] += row[p];
@@ -67,11 +73,11 @@ __device__ void reduce_partials(const SysDesc &d, int nblk, int nv, double *out)
 }
 
 __device__ __forceinline__ void store_partials(const SysDesc &d, int chunk, const double *lds,
-                                               int nv, int nvmax) {
+                                               int nv, int nvmax, int bank = 0) {
     for (int p = threadIdx.x; p < nv; p += NTHREADS) {
         double a = 0.0;
         for (int w2 = 0; w2 < NTHREADS / 64; ++w2) a += lds[w2 * nvmax + p];
-        gp(d.part)[(size_t)chunk * (RESTART_MAX + 2) + p] = a;
+        gp(d.part)[(size_t)(chunk + bank * RED_BANK) * (RESTART_MAX + 2) + p] = a;
     }
 }
 
@@ -89,25 +95,19 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
     const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[SL_V]));
     GAS double *w = gp(reinterpret_cast<double *>(d.vec[SL_W]));
     const int off2 = RESTART_MAX + 1;
-    for (int p = threadIdx.x; p < NVMAX; p += NTHREADS)
-        cf[p] = (PASS == 1) ? ((p < nv) ? d.hbuf[p] : 0.0)
-              : (PASS == 2) ? ((p < nv) ? d.hbuf[off2 + p] : 0.0) : 0.0;
-    __syncthreads();
+    for (int p = threadIdx.x; p < NVMAX; p += NTHREADS) cf[p] = 0.0;
     constexpr int NACC = (PASS == 2) ? 1 : NVMAX;
     double acc[NACC];
 #pragma unroll
     for (int p = 0; p < NACC; ++p) acc[p] = 0.0;
     const long long stride = (long long)it.count * NTHREADS;
-    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N; e += stride) {
-        double wv = w[e];
+    // one element: the basis entries vp (zero past nv) and w's entry wv
+    auto element = [&](long long e, const double (&vp)[NVMAX], double wv) {
         if (PASS == 0) {
 #pragma unroll
             for (int p = 0; p < NVMAX; ++p)
-                if (p < nv) acc[p] += V[p * N + e] * wv;
+                if (p < nv) acc[p] += vp[p] * wv;
         } else if (PASS == 1) {
-            double vp[NVMAX];
-#pragma unroll
-            for (int p = 0; p < NVMAX; ++p) vp[p] = (p < nv) ? V[p * N + e] : 0.0;
 #pragma unroll
             for (int p = 0; p < NVMAX; ++p) wv -= cf[p] * vp[p];
 #pragma unroll
@@ -116,57 +116,84 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs(const SysDesc *__restrict__ sy
         } else {
 #pragma unroll
             for (int p = 0; p < NVMAX; ++p)
-                if (p < nv) wv -= cf[p] * V[p * N + e];
+                if (p < nv) wv -= cf[p] * vp[p];
             acc[0] += wv * wv;
             w[e] = wv;
         }
+    };
+    // U elements of this thread (e, e + stride, ...) at a time: all their
+    // loads are issued before the arithmetic, which then runs element by
+    // element in the order of the one-at-a-time tail loop
+    constexpr int U = (NVMAX <= 8) ? 4 : (NVMAX <= 16) ? 2 : 1;
+    long long e = (long long)it.first * NTHREADS + threadIdx.x;
+    double wv[U], vp[U][NVMAX];
+    auto load = [&]() {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            wv[u] = w[e + u * stride];
+#pragma unroll
+            for (int p = 0; p < NVMAX; ++p) vp[u][p] = (p < nv) ? V[p * N + e + u * stride] : 0.0;
+        }
+    };
+    // the first group's loads are in flight while the coefficients of the
+    // previous pass are formed: h1 (pass 1) or h2 (pass 2) from that pass's
+    // partials, the same sums in every workgroup; chunk 0 keeps them for
+    // the Hessenberg column
+    if (e + (U - 1) * stride < N) load();
+    if (PASS >= 1) {
+        reduce_partials<NVMAX>(d, it.count, nv, cf, PASS == 1 ? 0 : 1);
+        if (it.first == 0)
+            for (int p = threadIdx.x; p < nv; p += NTHREADS) d.hbuf[(PASS == 1 ? 0 : off2) + p] = cf[p];
+    }
+    for (; e + (U - 1) * stride < N; e += U * stride) {
+        if (e != (long long)it.first * NTHREADS + threadIdx.x) load();
+#pragma unroll
+        for (int u = 0; u < U; ++u) element(e + u * stride, vp[u], wv[u]);
+    }
+    for (; e < N; e += stride) {
+        double vp[NVMAX];
+#pragma unroll
+        for (int p = 0; p < NVMAX; ++p) vp[p] = (p < nv) ? V[p * N + e] : 0.0;
+        element(e, vp, w[e]);
     }
     const int nred = (PASS == 2) ? 1 : nv;
     wg_sum<NACC>(acc, nred, lds);
-    store_partials(d, it.first, lds, nred, NACC);
+    store_partials(d, it.first, lds, nred, NACC, PASS == 1 ? 1 : 0);
 }
 
-// One workgroup per system: item = (sys, 0, number of chunks).
-template <int NVMAX, int PASS>
+// End of step j, one workgroup per system (item = (sys, 0, number of
+// chunks)): ||w|| from pass 2's partials; Hessenberg column j = h1 + h2
+// (kept by passes 1 and 2) with ||w|| below, the earlier Givens rotations
+// and a new one applied to it (in LDS, by one thread); estimate and flags.
+template <int NVMAX>
 __global__ __launch_bounds__(NTHREADS) void k_cgs_finish(const SysDesc *__restrict__ sysv,
                                                          const Item *__restrict__ items, int j)
 {
-    __shared__ double outv[NVMAX];
+    __shared__ double outv[1], hc[NVMAX + 1], csl[NVMAX], snl[NVMAX];
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
     if (d.st->done) return;
-    const int nv = j + 1;
     const int off2 = RESTART_MAX + 1;
-    constexpr int NACC = (PASS == 2) ? 1 : NVMAX;
-    reduce_partials<NACC>(d, it.count, (PASS == 2) ? 1 : nv, outv);
-    if (PASS == 0) {
-        for (int p = threadIdx.x; p < nv; p += NTHREADS) d.hbuf[p] = outv[p];
-        return;
-    }
-    if (PASS == 1) {
-        for (int p = threadIdx.x; p < nv; p += NTHREADS) d.hbuf[off2 + p] = outv[p];
-        return;
-    }
-    // Hessenberg column j, Givens rotation, estimate, flags
+    const int R = d.restart;
+    for (int p = threadIdx.x; p <= j; p += NTHREADS) hc[p] = d.hbuf[p] + d.hbuf[off2 + p];
+    for (int q = threadIdx.x; q < j; q += NTHREADS) { csl[q] = d.cs[q]; snl[q] = d.sn[q]; }
+    reduce_partials<1>(d, it.count, 1, outv);      // (its barriers cover the loads above)
     if (threadIdx.x == 0) {
-        const int R = d.restart;
-        double *H = d.H;
         DevState *st = d.st;
         const double hn = sqrt(outv[0]);
-        for (int p = 0; p <= j; ++p) H[p * R + j] = d.hbuf[p] + d.hbuf[off2 + p];
-        H[(j + 1) * R + j] = hn;
+        hc[j + 1] = hn;
         for (int q = 0; q < j; ++q) {
-            const double a = H[q * R + j], b = H[(q + 1) * R + j];
-            H[q * R + j] = d.cs[q] * a + d.sn[q] * b;
-            H[(q + 1) * R + j] = -d.sn[q] * a + d.cs[q] * b;
+            const double a = hc[q], b = hc[q + 1];
+            hc[q] = csl[q] * a + snl[q] * b;
+            hc[q + 1] = -snl[q] * a + csl[q] * b;
         }
-        const double a = H[j * R + j], b = H[(j + 1) * R + j];
+        const double a = hc[j], b = hc[j + 1];
         const double r = hypot(a, b);
         const double c = (r == 0.0) ? 1.0 : a / r, s = (r == 0.0) ? 0.0 : b / r;
         d.cs[j] = c;
         d.sn[j] = s;
-        H[j * R + j] = r;
-        H[(j + 1) * R + j] = 0.0;
+        hc[j] = r;
+        hc[j + 1] = 0.0;
         const double gj = d.g[j];
         d.g[j + 1] = -s * gj;
         d.g[j] = c * gj;
@@ -178,6 +205,8 @@ __global__ __launch_bounds__(NTHREADS) void k_cgs_finish(const SysDesc *__restri
         if (!(hn > 0.0)) { st->breakdown = 1; st->done = 1; }
         if (st->est <= st->tol_abs || j + 1 >= d.restart || st->iters >= d.max_iters) st->done = 1;
     }
+    __syncthreads();
+    for (int p = threadIdx.x; p <= j + 1; p += NTHREADS) d.H[p * R + j] = hc[p];
 }
 
 // dst = src / st->rnorm2 (zeros if that is not positive); skip_done: the
@@ -194,9 +223,16 @@ __global__ __launch_bounds__(NTHREADS) void k_scale(const SysDesc *__restrict__ 
     const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
     const double dv = d.st->rnorm2;
     const double inv = (dv > 0.0) ? 1.0 / dv : 0.0;
-    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
-         e += (long long)it.count * NTHREADS)
-        dst[e] = src[e] * inv;
+    const long long stride = (long long)it.count * NTHREADS;
+    long long e = (long long)it.first * NTHREADS + threadIdx.x;
+    for (; e + 3 * stride < N; e += 4 * stride) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[e + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[e + u * stride] = v[u] * inv;
+    }
+    for (; e < N; e += stride) dst[e] = src[e] * inv;
 }
 
 // partial sums of ||slot||^2
@@ -209,9 +245,16 @@ __global__ __launch_bounds__(NTHREADS) void k_norm(const SysDesc *__restrict__ s
     const long long N = d.N;
     const GAS double *x = gp(reinterpret_cast<const double *>(d.vec[slot]));
     double a[1] = {0.0};
-    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
-         e += (long long)it.count * NTHREADS)
-        a[0] += x[e] * x[e];
+    const long long stride = (long long)it.count * NTHREADS;
+    long long e = (long long)it.first * NTHREADS + threadIdx.x;
+    for (; e + 3 * stride < N; e += 4 * stride) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = x[e + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[0] += v[u] * v[u];
+    }
+    for (; e < N; e += stride) a[0] += x[e] * x[e];
     wg_sum<1>(a, 1, lds);
     store_partials(d, it.first, lds, 1, 1);
 }
@@ -256,26 +299,51 @@ template <int NVMAX>
 __global__ __launch_bounds__(NTHREADS) void k_cycle_end(const SysDesc *__restrict__ sysv,
                                                         const Item *__restrict__ items, int basis_slot)
 {
-    __shared__ double ys[NVMAX];
+    __shared__ double ys[NVMAX], gs[NVMAX], Hs[NVMAX * NVMAX];
     const Item it = items[blockIdx.x];
     const SysDesc &d = sysv[it.sys];
     const long long N = d.N;
     const int R = d.restart;
     const int nv = d.st->j + 1;
+    // the triangle of H and g into LDS (one load per thread), then the
+    // back substitution by one thread
+    for (int q = threadIdx.x; q < nv * nv; q += NTHREADS) {
+        const int i = q / nv, k = q - i * nv;
+        if (k >= i) Hs[i * NVMAX + k] = d.H[i * R + k];
+    }
+    for (int q = threadIdx.x; q < nv; q += NTHREADS) gs[q] = d.g[q];
+    __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = nv - 1; i >= 0; --i) {
-            double t = d.g[i];
-            for (int k = i + 1; k < nv; ++k) t -= d.H[i * R + k] * ys[k];
-            ys[i] = t / d.H[i * R + i];
+            double t = gs[i];
+            for (int k = i + 1; k < nv; ++k) t -= Hs[i * NVMAX + k] * ys[k];
+            ys[i] = t / Hs[i * NVMAX + i];
         }
-        if (it.first == 0)
-            for (int i = 0; i < nv; ++i) d.y[i] = ys[i];
     }
     __syncthreads();
+    if (it.first == 0)
+        for (int q = threadIdx.x; q < nv; q += NTHREADS) d.y[q] = ys[q];
     const GAS double *V = gp(reinterpret_cast<const double *>(d.vec[basis_slot]));
     GAS double *u = gp(reinterpret_cast<double *>(d.vec[SL_U]));
-    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
-         e += (long long)it.count * NTHREADS) {
+    const long long stride = (long long)it.count * NTHREADS;
+    constexpr int U = (NVMAX <= 8) ? 4 : (NVMAX <= 16) ? 2 : 1;
+    long long e = (long long)it.first * NTHREADS + threadIdx.x;
+    for (; e + (U - 1) * stride < N; e += U * stride) {
+        double vp[U][NVMAX];
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int p = 0; p < NVMAX; ++p) vp[q][p] = (p < nv) ? V[p * N + e + q * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            double a = 0.0;
+#pragma unroll
+            for (int p = 0; p < NVMAX; ++p)
+                if (p < nv) a += ys[p] * vp[q][p];
+            u[e + q * stride] = a;
+        }
+    }
+    for (; e < N; e += stride) {
         double a = 0.0;
 #pragma unroll
         for (int p = 0; p < NVMAX; ++p)
@@ -294,9 +362,16 @@ __global__ __launch_bounds__(NTHREADS) void k_axpy(const SysDesc *__restrict__ s
     const long long N = d.N;
     GAS double *dst = gp(reinterpret_cast<double *>(d.vec[dst_slot]));
     const GAS double *src = gp(reinterpret_cast<const double *>(d.vec[src_slot]));
-    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
-         e += (long long)it.count * NTHREADS)
-        dst[e] += src[e];
+    const long long stride = (long long)it.count * NTHREADS;
+    long long e = (long long)it.first * NTHREADS + threadIdx.x;
+    for (; e + 3 * stride < N; e += 4 * stride) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { a[u] = dst[e + u * stride]; b[u] = src[e + u * stride]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[e + u * stride] = a[u] + b[u];
+    }
+    for (; e < N; e += stride) dst[e] += src[e];
 }
 
 // SL_YH (compute type TD) = src_slot[src_index] (FP64)
@@ -327,9 +402,16 @@ __global__ __launch_bounds__(NTHREADS) void k_store_z(const SysDesc *__restrict_
     const long long N = d.N;
     const GAS TS *src = gp(reinterpret_cast<const TS *>(d.vec[SL_YH]));
     GAS double *dst = gp(reinterpret_cast<double *>(d.vec[SL_ZB])) + (long long)j * N;
-    for (long long e = (long long)it.first * NTHREADS + threadIdx.x; e < N;
-         e += (long long)it.count * NTHREADS)
-        dst[e] = (double)src[e];
+    const long long stride = (long long)it.count * NTHREADS;
+    long long e = (long long)it.first * NTHREADS + threadIdx.x;
+    for (; e + 3 * stride < N; e += 4 * stride) {
+        TS v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = src[e + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dst[e + u * stride] = (double)v[u];
+    }
+    for (; e < N; e += stride) dst[e] = (double)src[e];
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_fill_zero_slot(const SysDesc *__restrict__ sysv,
@@ -388,7 +470,8 @@ static void cgs_dispatch(const SysDesc *dsys, const Item *vec, int nvec, const I
 #define CGS(NV)                                                                              \
     do {                                                                                     \
         hipLaunchKernelGGL((k_cgs<NV, PASS>), dim3(nvec), b, 0, st, dsys, vec, j);          \
-        hipLaunchKernelGGL((k_cgs_finish<NV, PASS>), dim3(nfin), b, 0, st, dsys, fin, j);   \
+        if (PASS == 2)                                                                       \
+            hipLaunchKernelGGL((k_cgs_finish<NV>), dim3(nfin), b, 0, st, dsys, fin, j);      \
     } while (0)
     if (nv <= 8) CGS(8);
     else if (nv <= 16) CGS(16);
