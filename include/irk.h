@@ -174,13 +174,20 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
 irk_status irk_factor_ilu(irk_handle *h);
 
 /* The same factorization without waiting for it: returns once its launches
- * are enqueued on the handle's stream, so the host prepares the next calls
- * while it runs.  A singular pivot is reported by the next call that uses
- * the factors: irk_gmres_solve (which reads the flag with the state it
- * reads anyway after the initial residual), irk_apply_preconditioner(_inner),
- * irk_export_factors, irk_autotune and irk_batch_admit (which wait for the
- * stream first) return IRK_ERR_SINGULAR, irk_last_bad_element names the
- * element, and the handle is not factored. */
+ * are enqueued, so the host prepares the next calls while it runs.  It
+ * starts at the current point of the handle's stream and runs on a second
+ * stream of the handle (on the handle's stream itself while profiling is
+ * on); the handle's stream goes on when the factorization reaches its first
+ * wavefront with fewer tasks than the device has compute units, so work the
+ * caller enqueues next (a solve's initial residual, which needs no factors)
+ * runs beside its latency-bound last wavefronts.  Every call of this
+ * library that reads or writes the factors, or writes J, M or dt, makes the
+ * handle's stream wait for the factorization first.  A singular pivot is reported by the next call that uses the factors:
+ * irk_gmres_solve (which reads the flag with the first state read that
+ * follows the factorization), irk_apply_preconditioner(_inner),
+ * irk_export_factors, irk_autotune and irk_batch_admit (which wait for it
+ * first) return IRK_ERR_SINGULAR, irk_last_bad_element names the element,
+ * and the handle is not factored. */
 irk_status irk_factor_ilu_async(irk_handle *h);
 
 /* Solve B x = rhs (Sec. 4.3, Eq. big-irk) by restarted GMRES, right-

@@ -231,7 +231,7 @@ SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupl
 }
 
 struct Plan {
-    size_t o_dsys, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
+    size_t o_dsys, o_dsys2, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
         o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
         o_hbuf, o_part, o_gather, o_flow, o_ticket, total;
     int ld, ld32, ld16, nitems_max;
@@ -258,6 +258,7 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o2 = off; off = align256(off + bytes); return o2; };
     P.o_dsys = take(sizeof(SysDesc));
+    P.o_dsys2 = take(sizeof(SysDesc));
     P.o_st = take(sizeof(DevState));
     P.o_ints = take(sizeof(int) * ((size_t)(T + 1) + 2 * (size_t)p->nnzb + 3 * (size_t)T));
     P.o_items = take(sizeof(Item) * (size_t)P.nitems_max);
@@ -374,6 +375,16 @@ struct irk_handle {
     hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr;   // span of a time step
     hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr;   // span of the last factorization
     SysDesc solve_desc;  // descriptor with the caller's rhs / x (staging for the copy)
+    SysDesc *dsys_solve = nullptr;   // its device copy (the work set's descriptor during a solve)
+    // An asynchronous factorization runs on sstream (ev_pre: the point of
+    // the handle's stream it starts from; ev_factored: its end), so that what
+    // the caller enqueues next on the handle's stream (a solve's initial
+    // residual) runs beside it.  factor_side: the handle's stream has not
+    // waited for it yet (join_factor).
+    hipStream_t sstream = nullptr;
+    hipEvent_t ev_pre = nullptr, ev_factored = nullptr, ev_tail = nullptr;
+    bool factor_side = false;
+    int ncu = 0;         // compute units of the device
     // profiling: event pool and recorded intervals (kind, event index)
     bool prof;
     std::vector<hipEvent_t> pool;
@@ -419,6 +430,16 @@ namespace {
 enum ProfKind { PK_MV64 = 0, PK_MV32, PK_PC, PK_ORTH, PK_FACTOR, PK_UNTR, PK_N };
 
 // Start an interval; returns its pool index or -1.
+// The handle's stream waits for an asynchronous factorization running on
+// the side stream (before anything that reads or writes the factors, or
+// writes what the factorization reads).
+irk_status join_factor(irk_handle *h)
+{
+    if (!h->factor_side) return IRK_OK;
+    h->factor_side = false;
+    return hipStreamWaitEvent(h->stream, h->ev_factored, 0) == hipSuccess ? IRK_OK : IRK_ERR_DEVICE;
+}
+
 int prof_begin(irk_handle *h)
 {
     if (!h || !h->prof) return -1;
@@ -1244,6 +1265,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     d.part = (double *)(ws + P.o_part);
     d.st = (DevState *)(ws + P.o_st);
     h->dsys = (SysDesc *)(ws + P.o_dsys);
+    h->dsys_solve = (SysDesc *)(ws + P.o_dsys2);
     h->ditems = (Item *)(ws + P.o_items);
     h->dst = d.st;
     h->dgather = (DevState *)(ws + P.o_gather);
@@ -1273,6 +1295,17 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     hipEventCreate(&h->ev_s1);
     hipEventCreate(&h->ev_f0);
     hipEventCreate(&h->ev_f1);
+    hipEventCreateWithFlags(&h->ev_pre, hipEventDisableTiming);
+    hipEventCreateWithFlags(&h->ev_factored, hipEventDisableTiming);
+    hipEventCreateWithFlags(&h->ev_tail, hipEventDisableTiming);
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            h->ncu = 0;
+    }
+    // (non-blocking: no implicit ordering with a legacy default stream)
+    if (hipStreamCreateWithFlags(&h->sstream, hipStreamNonBlocking) != hipSuccess) h->sstream = nullptr;
     std::vector<Item> all(W.items);
     all.insert(all.end(), h->fitems.begin(), h->fitems.end());
     bool ok = true;
@@ -1296,6 +1329,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
 irk_status irk_update_values(irk_handle *h, const double *J, const double *M, double dt)
 {
     if (!h || !J || !M || !(dt > 0.0) || !std::isfinite(dt)) return IRK_ERR_ARG;
+    if (irk_status js = join_factor(h); js != IRK_OK) return js;
     const SysDesc &d = h->hsys;
     const long long nJb = (long long)h->nJ * h->nnzb;
     launch_relayout(J, (void *)d.Jc, 0, nJb, h->m, d.ld, h->stream);
@@ -1320,6 +1354,7 @@ irk_status irk_factor_ilu(irk_handle *h)
 {
     if (!h) return IRK_ERR_ARG;
     if (h->opt.pc == IRK_PC_NONE) { h->factored = true; return IRK_OK; }
+    if (irk_status js = join_factor(h); js != IRK_OK) return js;
     h->factor_pending = false;
     h->hst->singular = 0;
     h->hst->nonfinite = 0;
@@ -1350,16 +1385,40 @@ irk_status irk_factor_ilu_async(irk_handle *h)
 {
     if (!h) return IRK_ERR_ARG;
     if (h->opt.pc == IRK_PC_NONE) { h->factored = true; return IRK_OK; }
-    // flags cleared by a kernel (the pinned host copy may be in use)
+    if (irk_status js = join_factor(h); js != IRK_OK) return js;
+    // flags cleared by a kernel (the pinned host copy may be in use), in the
+    // handle's stream order
     launch_reset_factor_flags(h->dsys, h->ditems + h->W.fin.off, 1, h->stream);
-    hipEventRecord(h->ev_f0, h->stream);
+    // the factorization itself on the side stream (unless profiled: the
+    // profile's events are on the handle's stream), from this point on
+    const bool side = h->sstream && !h->prof;
+    hipStream_t fs = side ? h->sstream : h->stream;
+    if (side) {
+        HIPCHK(hipEventRecord(h->ev_pre, h->stream));
+        HIPCHK(hipStreamWaitEvent(fs, h->ev_pre, 0));
+    }
+    hipEventRecord(h->ev_f0, fs);
     const int pf = prof_begin(h);
-    for (const Launch &F : h->fa)
-        launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->stream);
-    if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
+    bool tail = false;
+    for (const Launch &F : h->fa) {
+        // the handle's stream goes on (a solve's initial residual) when the
+        // first wavefront with fewer tasks than compute units starts: the
+        // earlier ones fill the device, the later ones leave most of it idle
+        if (side && !tail && F.n < h->ncu) {
+            HIPCHK(hipEventRecord(h->ev_tail, fs));
+            HIPCHK(hipStreamWaitEvent(h->stream, h->ev_tail, 0));
+            tail = true;
+        }
+        launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, fs);
+    }
+    if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, fs);
     prof_end(h, pf, PK_FACTOR);
-    hipEventRecord(h->ev_f1, h->stream);
-    HIPCHK(hipEventRecord(h->ev_done, h->stream));
+    hipEventRecord(h->ev_f1, fs);
+    HIPCHK(hipEventRecord(h->ev_done, fs));
+    if (side) {
+        HIPCHK(hipEventRecord(h->ev_factored, fs));
+        h->factor_side = true;
+    }
     HIPCHK(hipGetLastError());
     h->bad_element = -1;
     h->factored = true;
@@ -1406,6 +1465,7 @@ irk_status settle_factor(irk_handle *h)
 // The same for a call that has not read the state: waits for the stream.
 irk_status settle_factor_sync(irk_handle *h)
 {
+    if (irk_status js = join_factor(h); js != IRK_OK) return js;
     if (!h->factor_pending) return IRK_OK;
     HIPCHK(hipMemcpyAsync(h->hst, h->dst, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
@@ -1513,27 +1573,43 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
 {
     if (!h || !rhs || !x) return IRK_ERR_ARG;
     if (!h->factored) return IRK_ERR_STATE;
-    // the solve reads rhs and updates x in place: point the slots at them
+    // the solve's descriptor (caller's rhs and x) is the work set's during
+    // the solve; the workspace's own descriptor stays as it is
     h->solve_desc = h->hsys;
     h->solve_desc.vec[SL_B] = const_cast<double *>(rhs);
     h->solve_desc.vec[SL_X] = x;
     hipEventRecord(h->ev0, h->stream);
-    HIPCHK(hipMemcpyAsync(h->dsys, &h->solve_desc, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->dsys_solve, &h->solve_desc, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
+    const SysDesc *const dsys_ws = h->W.dsys;
+    h->W.dsys = h->dsys_solve;
     Ctx C{&h->W, h->stream, h};
     Solve S;
     S.h = h;
     S.x = x;
     std::vector<Solve *> sv{&S};
+    // The initial residual needs no factors: after an asynchronous
+    // factorization on the side stream it runs beside it, and the Arnoldi
+    // steps wait for it.  Its flags are read with the first state read that
+    // follows it: the initial one if it ran on this stream, else the end of
+    // the first cycle (or a wait at the end).
+    const bool side = h->factor_side;
     irk_status st = init_systems(C, sv, h->dgather, h->hst);
-    // an asynchronous factorization ended before the initial residual (same
-    // stream): its flags are in the state just read
-    if (st == IRK_OK && h->factor_pending) {
+    if (st == IRK_OK) st = join_factor(h);
+    bool settled = !h->factor_pending;
+    if (st == IRK_OK && !settled && !side) {
+        settled = true;
         st = settle_factor(h);
-        S.info.ms_factor = h->ms_factor;
     }
-    while (st == IRK_OK && !S.finished) st = run_cycle(C, sv, h->dgather, h->hst);
-    // restore the workspace slots for the kernel-level entry points
-    HIPCHK(hipMemcpyAsync(h->dsys, &h->hsys, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
+    while (st == IRK_OK && !S.finished) {
+        st = run_cycle(C, sv, h->dgather, h->hst);
+        if (st == IRK_OK && !settled) {
+            settled = true;
+            st = settle_factor(h);
+        }
+    }
+    if (st == IRK_OK && !settled) st = settle_factor_sync(h);
+    S.info.ms_factor = h->ms_factor;
+    h->W.dsys = dsys_ws;
     hipEventRecord(h->ev1, h->stream);
     HIPCHK(hipStreamSynchronize(h->stream));
     if (st != IRK_OK) return st;
@@ -1662,6 +1738,7 @@ irk_status irk_radau_step(irk_handle *h, const irk_rhs *f, const double *b, doub
     if (f->eps != 0.0 && h->nJ != h->s) return IRK_ERR_ARG; // stage Jacobians differ
     const StepPlan SP = step_plan(h, 0);
     if (work_bytes < SP.total) return IRK_ERR_NOMEM;
+    if (irk_status js = join_factor(h); js != IRK_OK) return js;
     const StepBufs B = step_bufs(SP, work);
     const int s = h->s;
     const long long n = (long long)h->T * h->m, N = (long long)s * n;
@@ -1739,6 +1816,7 @@ irk_status irk_dirk_step(irk_handle *h, const irk_rhs *f, int stages, const doub
     }
     const StepPlan SP = step_plan(h, stages);
     if (work_bytes < SP.total) return IRK_ERR_NOMEM;
+    if (irk_status js = join_factor(h); js != IRK_OK) return js;
     const StepBufs B = step_bufs(SP, work);
     const long long n = (long long)h->T * h->m;
     const double dt = h->dt;
@@ -1850,6 +1928,11 @@ irk_status irk_destroy(irk_handle *h)
     if (h->ev_s1) hipEventDestroy(h->ev_s1);
     if (h->ev_f0) hipEventDestroy(h->ev_f0);
     if (h->ev_f1) hipEventDestroy(h->ev_f1);
+    if (h->sstream) hipStreamSynchronize(h->sstream);
+    if (h->ev_pre) hipEventDestroy(h->ev_pre);
+    if (h->ev_factored) hipEventDestroy(h->ev_factored);
+    if (h->ev_tail) hipEventDestroy(h->ev_tail);
+    if (h->sstream) hipStreamDestroy(h->sstream);
     delete h;
     return IRK_OK;
 }
@@ -2105,11 +2188,13 @@ namespace {
 irk_status factor_group(irk_batch *b, const std::vector<irk_handle *> &hs, irk_status *status)
 {
     const int n = (int)hs.size();
-    for (irk_handle *h : hs)
+    for (irk_handle *h : hs) {
+        if (irk_status js = join_factor(h); js != IRK_OK) return js;
         if (h->stream != b->stream) {
             HIPCHK(hipEventRecord(h->ev_ready, h->stream));
             HIPCHK(hipStreamWaitEvent(b->stream, h->ev_ready, 0));
         }
+    }
     for (int q = 0; q < n; ++q) b->htab[q] = hs[q]->hsys;
     struct FL { int off, n; bool coupled, sharedJ; int m; size_t shm; };
     std::vector<Item> items;

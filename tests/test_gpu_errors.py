@@ -93,6 +93,43 @@ def test_async_factor_reports_singular_at_the_solve():
 
 
 @pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted"])
+def test_async_factor_overlapped_initial_residual(pc):
+    """An asynchronous factorization runs on a second stream, and the
+    initial residual of the solve that follows runs beside it: bitwise the
+    same solution as after a synchronous factorization, on a mesh whose
+    factorization runs many wavefronts, also when the solve's zero initial
+    guess is written (in the handle's stream order, after the factorization
+    was enqueued) into memory that held the previous solution; a zero
+    right-hand side right after an asynchronous factorization; a value
+    update right after one; solves that follow with the same factors."""
+    irk = _irk()
+    print("async overlap", pc, flush=True)
+    sy = dgsynth.config_system("cfg1", N=24)
+    a = irk.Solver(sy, irk.Options(pc=pc))
+    b = irk.Solver(sy, irk.Options(pc=pc))
+    a.factor()
+    xa, ia = a.solve(sy.rhs)
+    for _ in range(3):
+        b.factor(wait=False)
+        xb, ib = b.solve(sy.rhs)
+        assert ib["converged"] and ib["iters"] == ia["iters"] and torch.equal(xb, xa)
+        assert ib["ms_factor"] > 0
+        del xb          # (its memory may become the next solve's x)
+    b.factor(wait=False)
+    b.update_values(sy.J, sy.M, sy.dt)
+    b.factor(wait=False)
+    xb, ib = b.solve(sy.rhs)
+    assert ib["iters"] == ia["iters"] and torch.equal(xb, xa)
+    b.factor(wait=False)
+    x0, i0 = b.solve(np.zeros_like(sy.rhs))
+    assert i0["converged"] and int(torch.count_nonzero(x0)) == 0
+    xb, ib = b.solve(sy.rhs)
+    assert ib["iters"] == ia["iters"] and torch.equal(xb, xa)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted"])
 def test_async_factor_equals_sync(pc):
     """Same factors, same solve, bitwise, with and without waiting; a value
     update between two asynchronous factorizations is honoured."""
