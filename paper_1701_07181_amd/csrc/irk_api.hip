@@ -383,6 +383,7 @@ struct irk_handle {
     // waited for it yet (join_factor).
     hipStream_t sstream = nullptr;
     hipEvent_t ev_pre = nullptr, ev_factored = nullptr, ev_tail = nullptr;
+    hipEvent_t ev_read = nullptr;   // end of an in-cycle state copy (run_cycle)
     bool factor_side = false;
     int ncu = 0;         // compute units of the device
     // profiling: event pool and recorded intervals (kind, event index)
@@ -424,6 +425,7 @@ struct irk_batch {
     std::vector<int> free_slots;
     hipEvent_t ev_end;
     hipEvent_t ev_f0 = nullptr, ev_f1 = nullptr;   // span of a batched factorization
+    hipEvent_t ev_read = nullptr;                  // end of an in-cycle state copy (run_cycle)
 };
 
 namespace {
@@ -460,6 +462,7 @@ struct Ctx {
     WorkSet *W;
     hipStream_t st;
     irk_handle *prof;      // handle whose event pool records intervals (or null)
+    hipEvent_t ev_read = nullptr;   // end of a state copy the host reads later (or null)
 };
 
 // Sweep records of every level (in level order) of one system, one launch
@@ -825,6 +828,33 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
     int next_check = (W.nsys == 1) ? std::min(1, W.restart - 1) : check_every - 1;
     double prev_est = (W.nsys == 1) ? hg[0].beta : -1.0;
     int prev_j = -1;
+    // A read expected not to end the cycle overlaps the next step: its copy
+    // is issued after step j, the next step is enqueued, and only then does
+    // the host wait for the copy (the device runs that step meanwhile; if
+    // the read shows the cycle ended, the step's kernels skip the ended
+    // systems).  The last step of a cycle, and a single system's steps from
+    // the one at which its estimate is predicted to meet the tolerance on,
+    // are read at once.
+    int pend_j = -1;          // step whose state copy is in flight
+    int last_pred = -1;       // one system: step predicted to end the cycle
+    auto consume = [&](int rj) -> bool {
+        bool all_done = true;
+        for (int q = 0; q < W.nsys; ++q) all_done = all_done && hg[q].done;
+        if (all_done) return true;
+        next_check = rj + check_every;
+        if (W.nsys == 1) {
+            const double est = hg[0].est, tol = hg[0].tol_abs;
+            if (prev_est > 0.0 && est > 0.0 && est < prev_est && tol > 0.0 && tol < est) {
+                // steps still needed at the per-step rate since the last read
+                const double steps = std::log(tol / est) * (rj - prev_j) / std::log(est / prev_est);
+                if (steps > 2.0 && steps < 1e6) next_check = rj + (int)steps - 1;
+                if (steps > 0.0 && steps < 1e6) last_pred = rj + std::max(1, (int)steps);
+            }
+            prev_est = est;
+            prev_j = rj;
+        }
+        return false;
+    };
     for (int j = 0; j < W.restart; ++j) {
         if (W.has_pc) {
             enqueue_pc(C, fp64, SL_V, j, -1, 1);
@@ -836,25 +866,30 @@ irk_status run_cycle(Ctx &C, std::vector<Solve *> &sv, DevState *dg, DevState *h
         const int po = prof_begin(C.prof);
         launch_arnoldi(W.dsys, vec, W.vec.n, fin, W.fin.n, j, C.st);
         prof_end(C.prof, po, PK_ORTH);
+        if (pend_j >= 0) {
+            HIPCHK(hipEventSynchronize(C.ev_read));
+            const int rj = pend_j;
+            pend_j = -1;
+            if (consume(rj)) break;
+        }
         if (j >= next_check || j + 1 == W.restart) {
-            irk_status st = sync_states(C, dg, hg);
-            if (st != IRK_OK) return st;
-            bool all_done = true;
-            for (int q = 0; q < W.nsys; ++q) all_done = all_done && hg[q].done;
-            if (all_done) break;
-            next_check = j + check_every;
-            if (W.nsys == 1) {
-                const double est = hg[0].est, tol = hg[0].tol_abs;
-                if (prev_est > 0.0 && est > 0.0 && est < prev_est && tol > 0.0 && tol < est) {
-                    // steps still needed at the per-step rate since the last read
-                    const double steps = std::log(tol / est) * (j - prev_j) / std::log(est / prev_est);
-                    if (steps > 2.0 && steps < 1e6) next_check = j + (int)steps - 1;
-                }
-                prev_est = est;
-                prev_j = j;
+            const bool at_once = !C.ev_read || j + 1 == W.restart ||
+                                 (W.nsys == 1 && last_pred >= 0 && j >= last_pred);
+            if (at_once) {
+                irk_status st = sync_states(C, dg, hg);
+                if (st != IRK_OK) return st;
+                if (consume(j)) break;
+            } else {
+                launch_gather_state(W.dsys, fin, W.fin.n, dg, C.st);
+                HIPCHK(hipMemcpyAsync(hg, dg, sizeof(DevState) * W.fin.n, hipMemcpyDeviceToHost, C.st));
+                HIPCHK(hipEventRecord(C.ev_read, C.st));
+                pend_j = j;
             }
         }
     }
+    // (a copy still in flight is that of a step whose successor was the
+    // last: it ended with a read at once)
+    if (pend_j >= 0) HIPCHK(hipEventSynchronize(C.ev_read));
     // x += Z y with the stored z_j = P^{-1} v_j (equal to P^{-1} V y, without
     // one more preconditioner application)
     launch_cycle_end(W.dsys, vec, W.vec.n, W.restart, W.has_pc ? SL_ZB : SL_V, C.st);
@@ -1298,6 +1333,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     hipEventCreateWithFlags(&h->ev_pre, hipEventDisableTiming);
     hipEventCreateWithFlags(&h->ev_factored, hipEventDisableTiming);
     hipEventCreateWithFlags(&h->ev_tail, hipEventDisableTiming);
+    hipEventCreateWithFlags(&h->ev_read, hipEventDisableTiming);
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -1582,7 +1618,7 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
     HIPCHK(hipMemcpyAsync(h->dsys_solve, &h->solve_desc, sizeof(SysDesc), hipMemcpyHostToDevice, h->stream));
     const SysDesc *const dsys_ws = h->W.dsys;
     h->W.dsys = h->dsys_solve;
-    Ctx C{&h->W, h->stream, h};
+    Ctx C{&h->W, h->stream, h, h->ev_read};
     Solve S;
     S.h = h;
     S.x = x;
@@ -1932,6 +1968,7 @@ irk_status irk_destroy(irk_handle *h)
     if (h->ev_pre) hipEventDestroy(h->ev_pre);
     if (h->ev_factored) hipEventDestroy(h->ev_factored);
     if (h->ev_tail) hipEventDestroy(h->ev_tail);
+    if (h->ev_read) hipEventDestroy(h->ev_read);
     if (h->sstream) hipStreamDestroy(h->sstream);
     delete h;
     return IRK_OK;
@@ -1995,6 +2032,7 @@ static irk_status batch_init(irk_batch *b, int capacity, long long max_elements,
     HIPCHK(hipEventCreate(&b->ev_end));
     HIPCHK(hipEventCreate(&b->ev_f0));
     HIPCHK(hipEventCreate(&b->ev_f1));
+    HIPCHK(hipEventCreateWithFlags(&b->ev_read, hipEventDisableTiming));
     return IRK_OK;
 }
 
@@ -2152,7 +2190,7 @@ irk_status irk_batch_advance(irk_batch *b, int cycles)
             sol[q].cycles = m.cycles; sol[q].stall = m.stall;
             sv.push_back(&sol[q]);
         }
-        Ctx C{&W, b->stream, nullptr};
+        Ctx C{&W, b->stream, nullptr, b->ev_read};
         st = run_cycle(C, sv, b->dgather, b->hgather);
         if (st != IRK_OK) return st;
         batch_retire_finished(b, sol, idx);
@@ -2415,6 +2453,7 @@ irk_status irk_batch_destroy(irk_batch *b)
     if (b->ev_end) hipEventDestroy(b->ev_end);
     if (b->ev_f0) hipEventDestroy(b->ev_f0);
     if (b->ev_f1) hipEventDestroy(b->ev_f1);
+    if (b->ev_read) hipEventDestroy(b->ev_read);
     delete b;
     return IRK_OK;
 }
