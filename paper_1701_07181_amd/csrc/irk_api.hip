@@ -384,6 +384,11 @@ struct irk_handle {
     hipStream_t sstream = nullptr;
     hipEvent_t ev_pre = nullptr, ev_factored = nullptr, ev_tail = nullptr;
     hipEvent_t ev_read = nullptr;   // end of an in-cycle state copy (run_cycle)
+    // part_levels > 0: ev_part marks the end of the wavefront after which the
+    // factors of the first part_levels forward levels are final (those of
+    // the forward sweep's first launch group)
+    hipEvent_t ev_part = nullptr;
+    int part_levels = 0;
     bool factor_side = false;
     int ncu = 0;         // compute units of the device
     // profiling: event pool and recorded intervals (kind, event index)
@@ -463,6 +468,11 @@ struct Ctx {
     hipStream_t st;
     irk_handle *prof;      // handle whose event pool records intervals (or null)
     hipEvent_t ev_read = nullptr;   // end of a state copy the host reads later (or null)
+    // the next forward sweep waits for ev_rest before its launches of
+    // levels >= rest_level (the end of a factorization whose earlier
+    // wavefronts it already waited for); cleared once that wait is enqueued
+    hipEvent_t ev_rest = nullptr;
+    int rest_level = 0;
 };
 
 // Sweep records of every level (in level order) of one system, one launch
@@ -710,6 +720,11 @@ void enqueue_pc(Ctx &C, bool fp64, int v_slot, int v_index, int acc_slot, int sk
         const unsigned long long ep = (!CH.empty() && W.dticket) ? ++g_flow_epoch : 0;
         size_t a = 0;
         while (a < L.size()) {
+            if (C.ev_rest && (!fwd || (int)a >= C.rest_level)) {
+                // (a failure shows in the caller's hipGetLastError check)
+                (void)hipStreamWaitEvent(C.st, C.ev_rest, 0);
+                C.ev_rest = nullptr;
+            }
             const SwLaunch &A = L[a];
             if (ep && A.group >= 0) {
                 const SwChain &c = CH[A.group];
@@ -1334,6 +1349,7 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     hipEventCreateWithFlags(&h->ev_factored, hipEventDisableTiming);
     hipEventCreateWithFlags(&h->ev_tail, hipEventDisableTiming);
     hipEventCreateWithFlags(&h->ev_read, hipEventDisableTiming);
+    hipEventCreateWithFlags(&h->ev_part, hipEventDisableTiming);
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -1435,8 +1451,21 @@ irk_status irk_factor_ilu_async(irk_handle *h)
     }
     hipEventRecord(h->ev_f0, fs);
     const int pf = prof_begin(h);
+    // the forward sweep's first launch group (levels 0 .. a-1) reads only
+    // the factors of its own elements, final after wavefront a - 1 (+ s - 1
+    // when coupled: task (k, i) is in wavefront level(i) + k)
+    int a = 0;
+    const std::vector<SwLaunch> &F0 = h->W.fwd64;
+    if (!F0.empty()) {
+        a = 1;
+        if (F0[0].group >= 0)
+            while (a < (int)F0.size() && F0[a].group == F0[0].group) ++a;
+    }
+    const int wpart = (side && !h->mixed && a > 0) ? (h->coupled ? a - 1 + h->s - 1 : a - 1) : -1;
+    h->part_levels = 0;
     bool tail = false;
-    for (const Launch &F : h->fa) {
+    for (size_t w = 0; w < h->fa.size(); ++w) {
+        const Launch &F = h->fa[w];
         // the handle's stream goes on (a solve's initial residual) when the
         // first wavefront with fewer tasks than compute units starts: the
         // earlier ones fill the device, the later ones leave most of it idle
@@ -1446,6 +1475,10 @@ irk_status irk_factor_ilu_async(irk_handle *h)
             tail = true;
         }
         launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, fs);
+        if ((int)w == wpart && w + 1 < h->fa.size()) {
+            HIPCHK(hipEventRecord(h->ev_part, fs));
+            h->part_levels = a;
+        }
     }
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, fs);
     prof_end(h, pf, PK_FACTOR);
@@ -1630,7 +1663,17 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
     // the first cycle (or a wait at the end).
     const bool side = h->factor_side;
     irk_status st = init_systems(C, sv, h->dgather, h->hst);
-    if (st == IRK_OK) st = join_factor(h);
+    if (st == IRK_OK && h->factor_side && h->part_levels > 0) {
+        // the first forward launch group runs once its levels' factors are
+        // final (beside the factorization's last wavefronts); the later
+        // launches wait for the whole factorization (C.ev_rest)
+        HIPCHK(hipStreamWaitEvent(h->stream, h->ev_part, 0));
+        C.ev_rest = h->ev_factored;
+        C.rest_level = h->part_levels;
+        h->factor_side = false;
+    } else if (st == IRK_OK) {
+        st = join_factor(h);
+    }
     bool settled = !h->factor_pending;
     if (st == IRK_OK && !settled && !side) {
         settled = true;
@@ -1642,6 +1685,11 @@ irk_status irk_gmres_solve(irk_handle *h, const double *rhs, double *x, irk_solv
             settled = true;
             st = settle_factor(h);
         }
+    }
+    if (C.ev_rest) {
+        // (no preconditioner application ran)
+        HIPCHK(hipStreamWaitEvent(h->stream, C.ev_rest, 0));
+        C.ev_rest = nullptr;
     }
     if (st == IRK_OK && !settled) st = settle_factor_sync(h);
     S.info.ms_factor = h->ms_factor;
@@ -1969,6 +2017,7 @@ irk_status irk_destroy(irk_handle *h)
     if (h->ev_factored) hipEventDestroy(h->ev_factored);
     if (h->ev_tail) hipEventDestroy(h->ev_tail);
     if (h->ev_read) hipEventDestroy(h->ev_read);
+    if (h->ev_part) hipEventDestroy(h->ev_part);
     if (h->sstream) hipStreamDestroy(h->sstream);
     delete h;
     return IRK_OK;

@@ -92,18 +92,25 @@ def test_async_factor_reports_singular_at_the_solve():
     assert ei.value.status == irk.ERR_SINGULAR
 
 
+@pytest.mark.parametrize("chain", ["none", "all"])
 @pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted"])
-def test_async_factor_overlapped_initial_residual(pc):
-    """An asynchronous factorization runs on a second stream, and the
-    initial residual of the solve that follows runs beside it: bitwise the
-    same solution as after a synchronous factorization, on a mesh whose
-    factorization runs many wavefronts, also when the solve's zero initial
-    guess is written (in the handle's stream order, after the factorization
-    was enqueued) into memory that held the previous solution; a zero
-    right-hand side right after an asynchronous factorization; a value
-    update right after one; solves that follow with the same factors."""
+def test_async_factor_overlapped_initial_residual(pc, chain, monkeypatch):
+    """An asynchronous factorization runs on a second stream; the initial
+    residual of the solve that follows runs beside its last wavefronts, and
+    the first forward sweep's first launch group (one level, or the chained
+    run of streaming levels) once the factors of its levels are final:
+    bitwise the same solution as after a synchronous factorization, on a
+    mesh whose factorization runs many wavefronts, also when the solve's
+    zero initial guess is written (in the handle's stream order, after the
+    factorization was enqueued) into memory that held the previous solution;
+    a zero right-hand side right after an asynchronous factorization; a
+    value update right after one; solves that follow with the same
+    factors."""
     irk = _irk()
-    print("async overlap", pc, flush=True)
+    print("async overlap", pc, chain, flush=True)
+    if chain == "all":
+        monkeypatch.setenv("IRK_SWEEP_CHAIN", str(1 << 30))
+        monkeypatch.setenv("IRK_SWEEP_BIG", "40")
     sy = dgsynth.config_system("cfg1", N=24)
     a = irk.Solver(sy, irk.Options(pc=pc))
     b = irk.Solver(sy, irk.Options(pc=pc))
