@@ -182,7 +182,10 @@ irk_status irk_factor_ilu(irk_handle *h);
  * caller enqueues next (a solve's initial residual, which needs no factors)
  * runs beside its latency-bound last wavefronts.  Every call of this
  * library that reads or writes the factors, or writes J, M or dt, makes the
- * handle's stream wait for the factorization first.  A singular pivot is reported by the next call that uses the factors:
+ * handle's stream wait for the factorization first, except that
+ * irk_gmres_solve starts its first forward sweep's first launch group
+ * (the first level, or the first run of chained levels) once the
+ * wavefront that makes those levels' factors final has ended.  A singular pivot is reported by the next call that uses the factors:
  * irk_gmres_solve (which reads the flag with the first state read that
  * follows the factorization), irk_apply_preconditioner(_inner),
  * irk_export_factors, irk_autotune and irk_batch_admit (which wait for it
