@@ -263,7 +263,9 @@ __device__ __forceinline__ void d64_publish(double v, unsigned long long unused,
 // column first and publishes its pivot choice (look-ahead), so the search
 // overlaps the other updates and each step costs one barrier.
 // LDS: D64_LDS_DOUBLES; the inverse is left at lds + D64_STAGE (column c at
-// c * D64_LDX) for the caller's next product.
+// c * D64_LDX) for the caller's next product.  FROM_LDS: P is read from that
+// same place (the caller stored it there) instead of from gptr.
+template <bool FROM_LDS = false>
 __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *lds)
 {
     GAS double *g = gp(gptr);
@@ -279,7 +281,8 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int c = 16 * w + j;
-        a[j] = (lane < m && c < m) ? g[(size_t)c * ld + lane] : (lane == c ? 1.0 : 0.0);
+        a[j] = (lane < m && c < m) ? (FROM_LDS ? stage[c * D64_LDX + lane] : g[(size_t)c * ld + lane])
+                                   : (lane == c ? 1.0 : 0.0);
     }
     unsigned long long unused = (m >= 64) ? ~0ull : ((1ull << m) - 1ull);
     double myscale = 1.0;           // pivot value of this lane's row once it has been used

@@ -66,7 +66,8 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
 // P_{k,i} stay in registers from their starting value (d_k M_i - dt J_ii, or
 // the stored P_{k,i} when from_p) through every lower neighbour j, and
 // X = -dt^2 P_j^{-1} J_ji passes through LDS (64 x 66 doubles) into
-// P_{k,i} += J_ij X; P_{k,i} is written once.
+// P_{k,i} += J_ij X; P_{k,i} is left in LDS where the inverse reads it
+// (lds + D64_STAGE, leading dimension D64_LDX).
 template <bool FULL>
 __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, int k, const double *Jk,
                                                       double *Pk, bool from_p, double *Xs)
@@ -120,8 +121,9 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
         __syncthreads();
         if (act) d64_accum<FULL, true, 2>(acc, m, ld, gp(Jk + (long long)p * bs), nullptr, Xs, nx, ny);
     }
-    __syncthreads();                              // every wave has read the stored P_{k,i}
+    __syncthreads();                              // every wave is done with X in LDS
     if (act) {
+        double *Pst = Xs + D64_STAGE;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -130,7 +132,7 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
-                    if (r < m && c < m) gp(Pk)[(size_t)c * ld + r] = acc[x][y][q];
+                    if (r < m && c < m) Pst[c * D64_LDX + r] = acc[x][y][q];
                 }
             }
     }
@@ -317,7 +319,7 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
     if (CLS == 0) {
         if (m > 56) factor_small_products<true>(d, i, k, Jk, Pk, from_p, lds);
         else factor_small_products<false>(d, i, k, Jk, Pk, from_p, lds);
-        if (d64_invert(Pk, m, ld, lds)) flag_singular(d, i);
+        if (d64_invert<true>(Pk, m, ld, lds)) flag_singular(d, i);
         if (COUPLED && k + 1 < s) {
             if (m > 56) factor_round_small<true, SHJ>(d, i, k, lds);
             else factor_round_small<false, SHJ>(d, i, k, lds);
