@@ -1158,8 +1158,15 @@ static irk_status build_items(irk_handle *h)
                 for (int k = 0; k < s; ++k) {
                     const int l = wf - k;
                     if (l < 0 || l >= L) continue;
-                    for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
-                        h->fitems.push_back(Item{0, h->sc.lvl_fwd[a], 1, k});
+                    // the longest tasks (most lower neighbours) first, so the
+                    // wavefront does not end on one of them
+                    std::vector<int> el(h->sc.lvl_fwd.begin() + h->sc.off_fwd[l],
+                                        h->sc.lvl_fwd.begin() + h->sc.off_fwd[l + 1]);
+                    std::stable_sort(el.begin(), el.end(), [&](int x, int y) {
+                        return h->sc.diag[x] - rp[x] > h->sc.diag[y] - rp[y];
+                    });
+                    for (int e : el) {
+                        h->fitems.push_back(Item{0, e, 1, k});
                         A.n++;
                     }
                 }
