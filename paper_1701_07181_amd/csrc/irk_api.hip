@@ -1155,20 +1155,29 @@ static irk_status build_items(irk_handle *h)
         for (int wf = 0; wf < nw; ++wf) {
             Launch A{(int)(W.items.size() + h->fitems.size()), 0};
             if (h->coupled) {
+                // the longest tasks first, so the wavefront does not end on
+                // one of them: block products per task = 2 per lower
+                // neighbour + the stage round's (k = 0: two and an
+                // element-wise pass, counted as three; 0 < k < s - 1: one L
+                // product and s - 1 - k updates per later stage)
+                std::vector<std::pair<int, Item>> tk;
                 for (int k = 0; k < s; ++k) {
                     const int l = wf - k;
                     if (l < 0 || l >= L) continue;
-                    // the longest tasks (most lower neighbours) first, so the
-                    // wavefront does not end on one of them
-                    std::vector<int> el(h->sc.lvl_fwd.begin() + h->sc.off_fwd[l],
-                                        h->sc.lvl_fwd.begin() + h->sc.off_fwd[l + 1]);
-                    std::stable_sort(el.begin(), el.end(), [&](int x, int y) {
-                        return h->sc.diag[x] - rp[x] > h->sc.diag[y] - rp[y];
-                    });
-                    for (int e : el) {
-                        h->fitems.push_back(Item{0, e, 1, k});
-                        A.n++;
+                    const int later = s - 1 - k;
+                    const int round = (k == 0 && s > 1) ? 3 : later * (1 + later);
+                    for (int a = h->sc.off_fwd[l]; a < h->sc.off_fwd[l + 1]; ++a) {
+                        const int e = h->sc.lvl_fwd[a];
+                        tk.push_back({2 * (h->sc.diag[e] - rp[e]) + round, Item{0, e, 1, k}});
                     }
+                }
+                std::stable_sort(tk.begin(), tk.end(),
+                                 [](const std::pair<int, Item> &x, const std::pair<int, Item> &y) {
+                                     return x.first > y.first;
+                                 });
+                for (const auto &t : tk) {
+                    h->fitems.push_back(t.second);
+                    A.n++;
                 }
             } else {
                 const int a0 = h->sc.off_fwd[wf], ne = h->sc.off_fwd[wf + 1] - a0;
