@@ -1140,13 +1140,14 @@ static irk_status build_items(irk_handle *h)
         make_chains(W.items, W.bwd32, sizeof(float), W.cb32);
     }
     // factor tasks, one launch per wavefront (stored after the work set's
-    // items).  Uncoupled: wavefront = forward level; workgroup w takes stage
-    // k = (w / 8) % s of element 8 (w / (8 s)) + w % 8, so the s tasks of an
-    // element run on one XCD (workgroups go to the XCDs round-robin) and
-    // share its L2 for the blocks common to all stages; first = -1 pads the
-    // last group of eight.  Coupled: task (k, i) belongs to wavefront
-    // level(i) + k (its own earlier stages and the lower neighbours' same
-    // stage are done by then).
+    // items).  Uncoupled: wavefront = forward level; with the level's
+    // elements listed by lower-neighbour count, most first (the longest
+    // tasks start first), workgroup w takes stage k = (w / 8) % s of element
+    // 8 (w / (8 s)) + w % 8 of that list, so the s tasks of an element run on
+    // one XCD (workgroups go to the XCDs round-robin) and share its L2 for
+    // the blocks common to all stages; first = -1 pads the last group of
+    // eight.  Coupled: task (k, i) belongs to wavefront level(i) + k (its own
+    // earlier stages and the lower neighbours' same stage are done by then).
     h->fa.clear();
     h->fitems.clear();
     if (o->pc != IRK_PC_NONE) {
@@ -1180,12 +1181,18 @@ static irk_status build_items(irk_handle *h)
                     A.n++;
                 }
             } else {
-                const int a0 = h->sc.off_fwd[wf], ne = h->sc.off_fwd[wf + 1] - a0;
+                // elements with the most lower neighbours (the longest tasks) first
+                std::vector<int> el(h->sc.lvl_fwd.begin() + h->sc.off_fwd[wf],
+                                    h->sc.lvl_fwd.begin() + h->sc.off_fwd[wf + 1]);
+                std::stable_sort(el.begin(), el.end(), [&](int x, int y) {
+                    return h->sc.diag[x] - rp[x] > h->sc.diag[y] - rp[y];
+                });
+                const int ne = (int)el.size();
                 for (int g = 0; g < (ne + 7) / 8; ++g)
                     for (int k = 0; k < s; ++k)
                         for (int r = 0; r < 8; ++r) {
                             const int e = 8 * g + r;
-                            h->fitems.push_back(Item{0, e < ne ? h->sc.lvl_fwd[a0 + e] : -1, 1, k});
+                            h->fitems.push_back(Item{0, e < ne ? el[e] : -1, 1, k});
                             A.n++;
                         }
             }
