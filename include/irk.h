@@ -174,7 +174,11 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
 irk_status irk_factor_ilu(irk_handle *h);
 
 /* The same factorization without waiting for it: returns once its launches
- * are enqueued, so the host prepares the next calls while it runs.  It
+ * are enqueued, so the host prepares the next calls while it runs.  The
+ * stage-coupled form with m <= 64 runs runs of consecutive wavefronts in
+ * one launch, each task waiting only for the tasks whose blocks it reads
+ * (the same arithmetic: the factors equal irk_factor_ilu's bit for bit;
+ * variable IRK_FACTOR_FLOW=0 at set-up keeps one launch per wavefront).  It
  * starts at the current point of the handle's stream and runs on a second
  * stream of the handle (on the handle's stream itself while profiling is
  * on); the handle's stream goes on when the factorization reaches its first

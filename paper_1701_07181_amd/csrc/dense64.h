@@ -62,7 +62,20 @@ constexpr int D64_LDX = 66;
 constexpr int D64_STAGE = 130;
 constexpr int D64_LDS_DOUBLES = D64_STAGE + 64 * D64_LDX + 65;
 
-template <bool BLDS, bool ALDS = false>
+// Loads and stores coherent across the XCDs' L2 caches (device-scope
+// relaxed atomics): for blocks that other workgroups of the same launch
+// write or read (the dependency-driven factorization, k_factor.hip).
+__device__ __forceinline__ double ld_coh(const GAS double *p)
+{
+    return __hip_atomic_load((double *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(GAS double *p, double v)
+{
+    __hip_atomic_store((double *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// COH: bit 0 -- A, bit 1 -- B read from memory with coherent loads.
+template <bool BLDS, bool ALDS = false, int COH = 0>
 __device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, const GAS double *B, const double *Bs,
                                              int m, int ld, int i0, int j0, int kq, int t,
                                              const double *As = nullptr)
@@ -73,12 +86,20 @@ __device__ __forceinline__ void d64_load_ops(D64Ops &o, const GAS double *A, con
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (ALDS) o.a[x][u] = As[min(kb + u, 63) * D64_LDX + i0 + 16 * x];
+            else if (COH & 1) o.a[x][u] = ld_coh(A + (size_t)min(kb + u, m - 1) * ld + min(i0 + 16 * x, ld - 1));
             else o.a[x][u] = A[(size_t)min(kb + u, m - 1) * ld + min(i0 + 16 * x, ld - 1)];
         }
 #pragma unroll
     for (int y = 0; y < 2; ++y) {
-        if (BLDS) o.b[y] = *reinterpret_cast<const dbl2 *>(Bs + (j0 + 16 * y) * D64_LDX + min(kb, 62));
-        else o.b[y] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j0 + 16 * y, m - 1) * ld + min(kb, ld - 2));
+        if (BLDS) {
+            o.b[y] = *reinterpret_cast<const dbl2 *>(Bs + (j0 + 16 * y) * D64_LDX + min(kb, 62));
+        } else if (COH & 2) {
+            const GAS double *q = B + (size_t)min(j0 + 16 * y, m - 1) * ld + min(kb, ld - 2);
+            o.b[y].x = ld_coh(q);
+            o.b[y].y = ld_coh(q + 1);
+        } else {
+            o.b[y] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j0 + 16 * y, m - 1) * ld + min(kb, ld - 2));
+        }
     }
 }
 
@@ -114,7 +135,7 @@ __device__ __forceinline__ void d64_mma_ops(const D64Ops &o, int m, int kq, int 
 // dimension D64_LDX): entries outside the m x m block may hold anything
 // (those of K are zeroed, the others only reach result rows or columns
 // >= m).
-template <bool FULL, bool BLDS, int DEPTH = 3, bool ALDS = false>
+template <bool FULL, bool BLDS, int DEPTH = 3, bool ALDS = false, int COH = 0>
 __device__ __forceinline__ void d64_accum(dbl4 (&acc)[2][2], int m, int ld, const GAS double *A,
                                           const GAS double *B, const double *Bs, int nx, int ny,
                                           const double *As = nullptr)
@@ -126,12 +147,12 @@ __device__ __forceinline__ void d64_accum(dbl4 (&acc)[2][2], int m, int ld, cons
     D64Ops o[DEPTH];
 #pragma unroll
     for (int t = 0; t < DEPTH - 1; ++t)
-        if (FULL || t < nb) d64_load_ops<BLDS, ALDS>(o[t], A, B, Bs, m, ld, i0, j0, kq, t, As);
+        if (FULL || t < nb) d64_load_ops<BLDS, ALDS, COH>(o[t], A, B, Bs, m, ld, i0, j0, kq, t, As);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         if (!FULL && t >= nb) continue;
         const int tn = t + DEPTH - 1;
-        if (FULL ? (tn < 8) : (tn < nb)) d64_load_ops<BLDS, ALDS>(o[tn % DEPTH], A, B, Bs, m, ld, i0, j0, kq, tn, As);
+        if (FULL ? (tn < 8) : (tn < nb)) d64_load_ops<BLDS, ALDS, COH>(o[tn % DEPTH], A, B, Bs, m, ld, i0, j0, kq, tn, As);
         d64_mma_ops<FULL>(o[t % DEPTH], m, kq, t, nx, ny, acc);
     }
 }
@@ -264,8 +285,9 @@ __device__ __forceinline__ void d64_publish(double v, unsigned long long unused,
 // overlaps the other updates and each step costs one barrier.
 // LDS: D64_LDS_DOUBLES; the inverse is left at lds + D64_STAGE (column c at
 // c * D64_LDX) for the caller's next product.  FROM_LDS: P is read from that
-// same place (the caller stored it there) instead of from gptr.
-template <bool FROM_LDS = false>
+// same place (the caller stored it there) instead of from gptr.  COH: the
+// inverse is written to gptr with coherent stores.
+template <bool FROM_LDS = false, bool COH = false>
 __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *lds)
 {
     GAS double *g = gp(gptr);
@@ -342,7 +364,10 @@ __device__ __forceinline__ int d64_invert(double *gptr, int m, int ld, double *l
     __syncthreads();
     for (int e = threadIdx.x; e < m * 64; e += NTHREADS) {
         const int c = e >> 6, r = e & 63;
-        if (r < m) g[(size_t)c * ld + r] = stage[c * D64_LDX + r];
+        if (r < m) {
+            if (COH) st_coh(g + (size_t)c * ld + r, stage[c * D64_LDX + r]);
+            else g[(size_t)c * ld + r] = stage[c * D64_LDX + r];
+        }
     }
     __syncthreads();
     return bad;

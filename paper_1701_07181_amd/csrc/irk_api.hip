@@ -233,7 +233,7 @@ SweepShape pick_sweep(int m, int ldJ, int VJ, int ldF, int VF, int s, bool coupl
 struct Plan {
     size_t o_dsys, o_dsys2, o_st, o_ints, o_items, o_J, o_M, o_J32, o_M32, o_P64, o_C64, o_P32, o_C32,
         o_P16, o_C16, o_P16e, o_C16e, o_Fscr, o_vec[NSLOT], o_H, o_g, o_cs, o_sn, o_y,
-        o_hbuf, o_part, o_gather, o_flow, o_ticket, total;
+        o_hbuf, o_part, o_gather, o_flow, o_ticket, o_fflag, o_fticket, total;
     int ld, ld32, ld16, nitems_max;
 };
 
@@ -303,6 +303,8 @@ Plan make_plan(const irk_problem *p, const irk_options *o)
     if (o->pc != IRK_PC_NONE) {
         P.o_flow = take(sizeof(unsigned long long) * (size_t)T);   // single-launch sweep flags
         P.o_ticket = take(sizeof(unsigned));                        // its ticket counter
+        P.o_fflag = take(sizeof(unsigned long long) * (size_t)T * s);   // factorization task flags
+        P.o_fticket = take(sizeof(unsigned));                             // their ticket counter
     }
     P.total = off;
     return P;
@@ -389,6 +391,11 @@ struct irk_handle {
     // the forward sweep's first launch group)
     hipEvent_t ev_part = nullptr;
     int part_levels = 0;
+    // dependency-driven coupled factorization (k_factor_flow): its task
+    // flags and ticket counter
+    bool factor_flow = false;
+    unsigned long long *dfflag = nullptr;
+    unsigned *dfticket = nullptr;
     bool factor_side = false;
     int ncu = 0;         // compute units of the device
     // profiling: event pool and recorded intervals (kind, event index)
@@ -1345,6 +1352,8 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     if (o->pc != IRK_PC_NONE) {
         d.flow = (unsigned long long *)(ws + P.o_flow);
         W.dticket = (unsigned *)(ws + P.o_ticket);
+        h->dfflag = (unsigned long long *)(ws + P.o_fflag);
+        h->dfticket = (unsigned *)(ws + P.o_fticket);
     }
     W.dsys = h->dsys;
     W.ditems = h->ditems;
@@ -1381,6 +1390,12 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     }
     // (non-blocking: no implicit ordering with a legacy default stream)
     if (hipStreamCreateWithFlags(&h->sstream, hipStreamNonBlocking) != hipSuccess) h->sstream = nullptr;
+    // the dependency-driven coupled factorization of irk_factor_ilu_async
+    // (variable IRK_FACTOR_FLOW=0 turns it off)
+    {
+        const char *e = std::getenv("IRK_FACTOR_FLOW");
+        h->factor_flow = h->coupled && m <= 64 && o->pc != IRK_PC_NONE && !(e && std::atoi(e) == 0);
+    }
     std::vector<Item> all(W.items);
     all.insert(all.end(), h->fitems.begin(), h->fitems.end());
     bool ok = true;
@@ -1391,6 +1406,8 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     if (o->pc != IRK_PC_NONE) {
         // sweep flags at epoch 0 (every sweep uses a larger one), ticket counter at 0
         ok &= hipMemsetAsync(d.flow, 0, sizeof(unsigned long long) * (size_t)T, stream) == hipSuccess;
+        ok &= hipMemsetAsync(h->dfflag, 0, sizeof(unsigned long long) * (size_t)T * s, stream) == hipSuccess;
+        ok &= hipMemsetAsync(h->dfticket, 0, sizeof(unsigned), stream) == hipSuccess;
         ok &= hipMemsetAsync(W.dticket, 0, sizeof(unsigned), stream) == hipSuccess;
     }
     if (!ok) { irk_destroy(h); return IRK_ERR_DEVICE; }
@@ -1486,21 +1503,53 @@ irk_status irk_factor_ilu_async(irk_handle *h)
     }
     const int wpart = (side && !h->mixed && a > 0) ? (h->coupled ? a - 1 + h->s - 1 : a - 1) : -1;
     h->part_levels = 0;
-    bool tail = false;
-    for (size_t w = 0; w < h->fa.size(); ++w) {
-        const Launch &F = h->fa[w];
-        // the handle's stream goes on (a solve's initial residual) when the
-        // first wavefront with fewer tasks than compute units starts: the
-        // earlier ones fill the device, the later ones leave most of it idle
-        if (side && !tail && F.n < h->ncu) {
-            HIPCHK(hipEventRecord(h->ev_tail, fs));
-            HIPCHK(hipStreamWaitEvent(h->stream, h->ev_tail, 0));
-            tail = true;
+    const int nw = (int)h->fa.size();
+    if (h->factor_flow) {
+        // runs of consecutive wavefronts in one launch each (k_factor_flow),
+        // cut (on the side stream) where the handle's stream goes on and
+        // where the first forward launch group's factors are final
+        int wtail = -1;
+        for (int w = 0; w < nw && wtail < 0 && side; ++w)
+            if (h->fa[w].n < h->ncu) wtail = w;
+        std::vector<int> cuts{0, nw};
+        if (wtail > 0) cuts.push_back(wtail);
+        if (wpart >= 0 && wpart + 1 < nw) cuts.push_back(wpart + 1);
+        std::sort(cuts.begin(), cuts.end());
+        cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+        const unsigned long long ep = ++g_flow_epoch;
+        for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+            const int w0 = cuts[c], w1 = cuts[c + 1];
+            if (w0 == wtail) {
+                HIPCHK(hipEventRecord(h->ev_tail, fs));
+                HIPCHK(hipStreamWaitEvent(h->stream, h->ev_tail, 0));
+            }
+            int n = 0;
+            for (int w = w0; w < w1; ++w) n += h->fa[w].n;
+            launch_factor_flow(h->dsys, h->ditems, h->fa[w0].off, n, h->sharedJ, h->shm_fac, h->dfflag,
+                               h->dfticket, ep, fs);
+            if (w1 == wpart + 1 && w1 < nw) {
+                HIPCHK(hipEventRecord(h->ev_part, fs));
+                h->part_levels = a;
+            }
         }
-        launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, fs);
-        if ((int)w == wpart && w + 1 < h->fa.size()) {
-            HIPCHK(hipEventRecord(h->ev_part, fs));
-            h->part_levels = a;
+    } else {
+        bool tail = false;
+        for (int w = 0; w < nw; ++w) {
+            const Launch &F = h->fa[w];
+            // the handle's stream goes on (a solve's initial residual) when
+            // the first wavefront with fewer tasks than compute units starts:
+            // the earlier ones fill the device, the later ones leave most of
+            // it idle
+            if (side && !tail && F.n < h->ncu) {
+                HIPCHK(hipEventRecord(h->ev_tail, fs));
+                HIPCHK(hipStreamWaitEvent(h->stream, h->ev_tail, 0));
+                tail = true;
+            }
+            launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, fs);
+            if (w == wpart && w + 1 < nw) {
+                HIPCHK(hipEventRecord(h->ev_part, fs));
+                h->part_levels = a;
+            }
         }
     }
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, fs);

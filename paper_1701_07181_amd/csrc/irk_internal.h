@@ -261,5 +261,11 @@ void launch_reset_factor_flags(const SysDesc *dsys, const Item *fin, int nfin, h
 void launch_export(const SysDesc *dsys, const SysDesc &hsys, double *pinv, double *cross, bool coupled,
                    hipStream_t st);
 void factor_set_lds_limit(size_t bytes);
+// Tasks items[off .. off + n) (consecutive wavefronts of one system's
+// coupled factorization, m <= 64) in one launch, each waiting only for the
+// tasks it reads (flags fflag[T][s] = epoch; ticket counter at zero on
+// entry and on exit); k_factor.hip.
+void launch_factor_flow(const SysDesc *dsys, const Item *items, int off, int n, bool sharedJ, size_t shmem,
+                        unsigned long long *fflag, unsigned *ticket, unsigned long long epoch, hipStream_t st);
 
 }  // namespace irk

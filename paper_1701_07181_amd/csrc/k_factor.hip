@@ -58,6 +58,8 @@ __device__ __forceinline__ int blk_inverse(double *g, int m, int ld, double *lds
 
 template <int CLS> constexpr int team_of() { return CLS == 0 ? NTHREADS : DM_TEAM; }
 
+constexpr int FACTOR_SPIN_MAX = 1 << 22;
+
 __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
     if (threadIdx.x == 0) atomicCAS(&d.st->singular, 0, elem + 1);
 }
@@ -68,7 +70,7 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
 // X = -dt^2 P_j^{-1} J_ji passes through LDS (64 x 66 doubles) into
 // P_{k,i} += J_ij X; P_{k,i} is left in LDS where the inverse reads it
 // (lds + D64_STAGE, leading dimension D64_LDX).
-template <bool FULL>
+template <bool FULL, bool FLOW = false>
 __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, int k, const double *Jk,
                                                       double *Pk, bool from_p, double *Xs)
 {
@@ -92,7 +94,7 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
             for (int q = 0; q < 4; ++q) {
                 const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
                 const size_t e = (size_t)min(c, m - 1) * ld + min(r, m - 1);
-                acc[x][y][q] = from_p ? Ps[e] : dk * Mi[e] - dt * Jd[e];
+                acc[x][y][q] = from_p ? (FLOW ? ld_coh(Ps + e) : Ps[e]) : dk * Mi[e] - dt * Jd[e];
             }
     const int p0 = row_ptr[i], pd = diag_pos[i];
     for (int p = p0; p < pd; ++p) {
@@ -104,8 +106,8 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
 #pragma unroll
             for (int y = 0; y < 2; ++y) ax[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
         if (act)
-            d64_accum<FULL, false, 2>(ax, m, ld, gp(d.P64 + (j * s + k) * bs), gp(Jk + (long long)tpos[p] * bs),
-                                      nullptr, nx, ny);
+            d64_accum<FULL, false, 2, false, FLOW ? 1 : 0>(ax, m, ld, gp(d.P64 + (j * s + k) * bs),
+                                                           gp(Jk + (long long)tpos[p] * bs), nullptr, nx, ny);
         __syncthreads();                          // the previous neighbour's X is consumed
         if (act) {
 #pragma unroll
@@ -176,7 +178,7 @@ __device__ __forceinline__ void d64_put_lds(const dbl4 (&acc)[2][2], double *Ls,
 // one (k = 0 or k = s - 2), else from memory (the inverse has written it).
 // The products and their order are those of the file comment; the results
 // are those of the same products through memory.
-template <bool FULL, bool SHJ>
+template <bool FULL, bool SHJ, bool FLOW = false>
 __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int k, double *lds)
 {
     const int s = d.s, lane = threadIdx.x & 63, w = wave_id();
@@ -200,8 +202,11 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
         const GAS double *A = k == 0 ? Mi : gp(cross_blk(d, i, l, k));
         clear();
         if (act) {
-            if (one_l) d64_accum<FULL, true>(acc, m, ld, A, nullptr, Ls, nx, ny);
-            else d64_accum<FULL, false>(acc, m, ld, A, gp(d.P64 + ((long long)i * s + k) * bs), nullptr, nx, ny);
+            // (with FLOW, blocks written by other tasks of the launch are
+            // read coherently: the cross blocks, and P_k^{-1} from memory)
+            if (one_l) d64_accum<FULL, true, 3, false, FLOW ? 1 : 0>(acc, m, ld, A, nullptr, Ls, nx, ny);
+            else d64_accum<FULL, false, 3, false, FLOW ? 3 : 0>(acc, m, ld, A, gp(d.P64 + ((long long)i * s + k) * bs),
+                                                                nullptr, nx, ny);
         }
         __syncthreads();                          // P_k^{-1} / the previous L is consumed
         if (act) d64_put_lds<FULL>(acc, Ls, nx, ny);
@@ -218,10 +223,11 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
-                        const double old = D[(size_t)min(c, m - 1) * ld + min(r, m - 1)];
+                        const GAS double *po = D + (size_t)min(c, m - 1) * ld + min(r, m - 1);
+                        const double old = FLOW ? ld_coh(po) : *po;
                         acc[x][y][e] = (r < m && c < m) ? -old : 0.0;
                     }
-            if (act) d64_accum<FULL, false, 3, true>(acc, m, ld, nullptr, B, nullptr, nx, ny, Ls);
+            if (act) d64_accum<FULL, false, 3, true, FLOW ? 2 : 0>(acc, m, ld, nullptr, B, nullptr, nx, ny, Ls);
             if (act) {
 #pragma unroll
                 for (int x = 0; x < 2; ++x)
@@ -231,7 +237,10 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
-                            if (r < m && c < m) D[(size_t)c * ld + r] = -acc[x][y][e];
+                            if (r < m && c < m) {
+                                if (FLOW) st_coh(D + (size_t)c * ld + r, -acc[x][y][e]);
+                                else D[(size_t)c * ld + r] = -acc[x][y][e];
+                            }
                         }
                     }
             }
@@ -269,7 +278,9 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
                     if (c >= m || r >= ld) continue;
                     const size_t o = (size_t)c * ld + r;
                     // (padding rows r >= m of a block stay zero)
-                    Pl[o] = r < m ? dl * mv[x][y][e] - dt * Jd[o] - fl * acc[x][y][e] : 0.0;
+                    const double v = r < m ? dl * mv[x][y][e] - dt * Jd[o] - fl * acc[x][y][e] : 0.0;
+                    if (FLOW) st_coh(Pl + o, v);
+                    else Pl[o] = v;
                 }
         for (int q = 1; q < s; ++q) {
             if (q == l) continue;
@@ -283,7 +294,9 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
                     for (int e = 0; e < 4; ++e) {
                         const int r = d64_tile_row(lane, w, x, e), c = d64_tile_col(lane, w, y);
                         if (c >= m || r >= ld) continue;
-                        Cq[(size_t)c * ld + r] = r < m ? a * mv[x][y][e] - f * acc[x][y][e] : 0.0;
+                        const double v = r < m ? a * mv[x][y][e] - f * acc[x][y][e] : 0.0;
+                        if (FLOW) st_coh(Cq + (size_t)c * ld + r, v);
+                        else Cq[(size_t)c * ld + r] = v;
                     }
         }
     }
@@ -293,12 +306,10 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
 // task are one operation list (the neighbour products for m > 64, then the
 // stage round), so a kernel holds one inlined copy of the product and one of
 // the inverse.
-template <bool COUPLED, bool SHJ, int CLS>
-__device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sysv,
-                                                 const Item *__restrict__ items, double *lds)
+template <bool COUPLED, bool SHJ, int CLS, bool FLOW = false>
+__device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sysv, const Item it, double *lds)
 {
     constexpr int TEAM = team_of<CLS>();
-    const Item it = items[blockIdx.x];
     if (it.first < 0) return;                     // padding task (whole workgroup)
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, m = d.m, ld = d.ld;
@@ -317,12 +328,12 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
     const int p0 = row_ptr[i], pd = diag_pos[i];
     const int nnb = (CLS == 0) ? 0 : 2 * (pd - p0);   // neighbour products (m > 64)
     if (CLS == 0) {
-        if (m > 56) factor_small_products<true>(d, i, k, Jk, Pk, from_p, lds);
-        else factor_small_products<false>(d, i, k, Jk, Pk, from_p, lds);
-        if (d64_invert<true>(Pk, m, ld, lds)) flag_singular(d, i);
+        if (m > 56) factor_small_products<true, FLOW>(d, i, k, Jk, Pk, from_p, lds);
+        else factor_small_products<false, FLOW>(d, i, k, Jk, Pk, from_p, lds);
+        if (d64_invert<true, FLOW>(Pk, m, ld, lds)) flag_singular(d, i);
         if (COUPLED && k + 1 < s) {
-            if (m > 56) factor_round_small<true, SHJ>(d, i, k, lds);
-            else factor_round_small<false, SHJ>(d, i, k, lds);
+            if (m > 56) factor_round_small<true, SHJ, FLOW>(d, i, k, lds);
+            else factor_round_small<false, SHJ, FLOW>(d, i, k, lds);
         }
         return;
     }
@@ -402,7 +413,68 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_tas
                                                                              const Item *__restrict__ items)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    factor_task_body<COUPLED, SHJ, CLS>(sysv, items, reinterpret_cast<double *>(smem_raw));
+    factor_task_body<COUPLED, SHJ, CLS>(sysv, items[blockIdx.x], reinterpret_cast<double *>(smem_raw));
+}
+
+// Consecutive wavefronts of the coupled factorization (m <= 64, one system)
+// in one launch, each task waiting only for the tasks it reads: (k, j) for
+// the lower neighbours j (their pivot inverses) and (k - 1, i) (the stage
+// round that left P_{k,i} and the cross blocks).  The scheme of the chained
+// sweeps (k_sweep_flow.hip): workgroups take the tasks items[off ..
+// off + n) (wavefront order) in the order they claim a ticket, so a task
+// only waits for tasks of workgroups already running, and the last claimant
+// sets the counter back to zero; a task's flag (element-major, [T][s])
+// holds the epoch of the factorization that published it.  Blocks written
+// by one task and read by another go through coherent (device-scope)
+// loads and stores; a task publishes after its stores have completed.  A
+// wait beyond its poll budget marks the system's state non-finite (never
+// a hang).
+template <bool SHJ>
+__global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__restrict__ sysv,
+                                                             const Item *__restrict__ items, int off, int n,
+                                                             unsigned long long *fflag, unsigned *ticket,
+                                                             unsigned long long epoch)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int s_t, s_late;
+    if (threadIdx.x == 0) {
+        const unsigned t = atomicAdd(ticket, 1u);
+        if (t == (unsigned)n - 1u) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_t = (int)t;
+        s_late = 0;
+    }
+    __syncthreads();
+    const int t = s_t;
+    if (t >= n) return;   // (the counter was not at zero: no task to read)
+    const Item it = items[off + t];
+    const SysDesc &d = sysv[it.sys];
+    const int s = d.s, i = it.first, k = it.aux;
+    const GAS int *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx), *diag_pos = gp(d.diag_pos);
+    const int p0 = row_ptr[i], nl = diag_pos[i] - p0;
+    for (int q = threadIdx.x; q < nl + (k > 0 ? 1 : 0); q += NTHREADS) {
+        const long long f = (q < nl) ? (long long)col_idx[p0 + q] * s + k : (long long)i * s + k - 1;
+        int spins = 0;
+        while (__hip_atomic_load(fflag + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > FACTOR_SPIN_MAX) { s_late = 1; break; }
+        }
+    }
+    __syncthreads();
+    if (s_late && threadIdx.x == 0) d.st->nonfinite = 1;
+    factor_task_body<true, SHJ, 0, true>(sysv, it, reinterpret_cast<double *>(smem_raw));
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's block stores have completed
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(fflag + (long long)i * s + k, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+void launch_factor_flow(const SysDesc *dsys, const Item *items, int off, int n, bool sharedJ, size_t shmem,
+                        unsigned long long *fflag, unsigned *ticket, unsigned long long epoch, hipStream_t st)
+{
+    if (n <= 0) return;
+    dim3 grid(n), block(NTHREADS);
+    if (sharedJ) hipLaunchKernelGGL(k_factor_flow<true>, grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch);
+    else hipLaunchKernelGGL(k_factor_flow<false>, grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch);
 }
 
 template <int CLS>
@@ -444,6 +516,8 @@ static void set_lds_limit_t(int b)
 void factor_set_lds_limit(size_t bytes)
 {
     set_lds_limit_t<0>((int)bytes);
+    (void)hipFuncSetAttribute((const void *)k_factor_flow<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipFuncSetAttribute((const void *)k_factor_flow<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     set_lds_limit_t<2>((int)bytes);
     set_lds_limit_t<3>((int)bytes);
 }
