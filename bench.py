@@ -91,7 +91,7 @@ TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_matvec.hip", "paper_1701_07181_a
 SWEEP_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_s3_64x64_m64_coupled_hbm_traffic.txt")
 SWEEP_TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_sweep.hip", "paper_1701_07181_amd/csrc/k_sweep_flow.hip",
                          "paper_1701_07181_amd/csrc/sweep_item.h", "paper_1701_07181_amd/csrc/irk_device.h"]
-FACTOR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_factor_task_s3_64x64_m64_coupled_counters.txt")
+FACTOR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_factor_s3_64x64_m64_coupled_counters.txt")
 FACTOR_TRAFFIC_SOURCES = ["paper_1701_07181_amd/csrc/k_factor.hip", "paper_1701_07181_amd/csrc/dense64.h",
                           "paper_1701_07181_amd/csrc/irk_device.h"]
 
@@ -129,7 +129,8 @@ def sweep_traffic():
 
 
 def factor_traffic():
-    """HBM bytes per factorization (all wavefronts of k_factor_task)."""
+    """HBM bytes per factorization (all wavefronts: k_factor_flow, the
+    asynchronous factorization of the timed steps)."""
     return _counter_traffic(FACTOR_TRAFFIC_FILE, FACTOR_TRAFFIC_SOURCES)
 
 
@@ -402,8 +403,9 @@ def family_report(prof, elapsed, sy, pc, iters, N):
         ms = prof["factor_ms"] / prof["factor_count"]
         fl = factor_flops(sy.s, sy.T, sy.m, sy.row_ptr, sy.col_idx, pc == "coupled")
         ach = fl / (ms * 1e-3) / 1e12
-        fam["factor"] = {"kernel": "k_factor_task (block ILU(0) factorization, all stage/level "
-                                   "wavefronts, FP64 matrix-core products and Gauss-Jordan inverses)",
+        fam["factor"] = {"kernel": "k_factor_flow / k_factor_task (block ILU(0) factorization, all "
+                                   "stage/level wavefronts, FP64 matrix-core products and Gauss-Jordan "
+                                   "inverses)",
                          "bound": "mfma",
                          "total_ms": round(prof["factor_ms"], 3), "share": round(prof["factor_ms"] / tot, 4),
                          "launches": prof["factor_count"], "avg_launch_us": round(ms * 1e3, 2),
