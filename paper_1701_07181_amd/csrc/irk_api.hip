@@ -1390,8 +1390,8 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     }
     // (non-blocking: no implicit ordering with a legacy default stream)
     if (hipStreamCreateWithFlags(&h->sstream, hipStreamNonBlocking) != hipSuccess) h->sstream = nullptr;
-    // the dependency-driven coupled factorization of irk_factor_ilu_async
-    // (variable IRK_FACTOR_FLOW=0 turns it off)
+    // the dependency-driven coupled factorization (variable
+    // IRK_FACTOR_FLOW=0 turns it off)
     {
         const char *e = std::getenv("IRK_FACTOR_FLOW");
         h->factor_flow = h->coupled && m <= 64 && o->pc != IRK_PC_NONE && !(e && std::atoi(e) == 0);
@@ -1453,8 +1453,16 @@ irk_status irk_factor_ilu(irk_handle *h)
     HIPCHK(hipMemcpyAsync(h->dst, h->hst, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
     hipEventRecord(h->ev_f0, h->stream);
     const int pf = prof_begin(h);
-    for (const Launch &F : h->fa)
-        launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->stream);
+    if (h->factor_flow && !h->fa.empty()) {
+        // every wavefront in one dependency-driven launch (k_factor_flow)
+        int n = 0;
+        for (const Launch &F : h->fa) n += F.n;
+        launch_factor_flow(h->dsys, h->ditems, h->fa[0].off, n, h->sharedJ, h->shm_fac, h->dfflag, h->dfticket,
+                           ++g_flow_epoch, h->stream);
+    } else {
+        for (const Launch &F : h->fa)
+            launch_factor(h->dsys, h->ditems + F.off, F.n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->stream);
+    }
     if (h->mixed) launch_quantize(h->dsys, h->hsys, h->ftype, h->stream);
     prof_end(h, pf, PK_FACTOR);
     hipEventRecord(h->ev_f1, h->stream);

@@ -1,8 +1,7 @@
-"""The dependency-driven coupled factorization (m <= 64; IRK_FACTOR_FLOW=0
-at set-up turns it off: an asynchronous factorization runs consecutive
-wavefronts in one launch, each task waiting only for the tasks it reads),
-on the GPU, against the synchronous factorization (one launch per
-wavefront).
+"""The dependency-driven coupled factorization (m <= 64: runs of
+consecutive wavefronts in one launch, each task waiting only for the tasks
+it reads), synchronous and asynchronous, on the GPU, against the
+factorization with one launch per wavefront (IRK_FACTOR_FLOW=0 at set-up).
 
 * Bitwise the same factors (pivot inverses and stored cross blocks) as the
   wavefront-per-launch factorization: s = 2, 3, 4, m from 6 to 64 (both
@@ -48,7 +47,7 @@ def test_flow_factors_equal_wavefront_factors(case, monkeypatch):
     print("factor flow", case, flush=True)
     sy = _system(s, dim, N, m, nJ)
     opts = irk.Options(pc="coupled")
-    monkeypatch.delenv("IRK_FACTOR_FLOW", raising=False)
+    monkeypatch.setenv("IRK_FACTOR_FLOW", "0")
     ref = irk.Solver(sy, opts)
     ref.factor()
     pr, cr = ref.export_factors(cross=True)
@@ -56,12 +55,14 @@ def test_flow_factors_equal_wavefront_factors(case, monkeypatch):
     monkeypatch.setenv("IRK_FACTOR_FLOW", "1")
     sol = irk.Solver(sy, opts)
     for rep in range(3):
-        sol.factor(wait=False)
+        sol.factor(wait=rep == 1)
         p, c = sol.export_factors(cross=True)
         assert torch.equal(p, pr) and torch.equal(c, cr), rep
     sol.factor(wait=False)
     x, i = sol.solve(sy.rhs)
     assert i["converged"] and i["iters"] == ir["iters"] and torch.equal(x, xr)
+    x, i = sol.solve(sy.rhs)          # (a solve with the same factors)
+    assert i["iters"] == ir["iters"] and torch.equal(x, xr)
     # a value update between two factorizations
     sy2 = _system(s, dim, N, m, nJ, seed=62, dt=0.3)
     for h in (ref, sol):
@@ -86,4 +87,7 @@ def test_flow_factor_reports_singular(monkeypatch):
     sol.factor(wait=False)
     x, info = sol.solve(sy.rhs, raise_on_error=False)
     assert info["status"] == irk.ERR_SINGULAR
+    with pytest.raises(irk.IrkError) as ei:
+        sol.factor()
+    assert ei.value.status == irk.ERR_SINGULAR
     sol.close()
