@@ -416,10 +416,10 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_tas
     factor_task_body<COUPLED, SHJ, CLS>(sysv, items[blockIdx.x], reinterpret_cast<double *>(smem_raw));
 }
 
-// Consecutive wavefronts of the coupled factorization (m <= 64, one system)
-// in one launch, each task waiting only for the tasks it reads: (k, j) for
-// the lower neighbours j (their pivot inverses) and (k - 1, i) (the stage
-// round that left P_{k,i} and the cross blocks).  The scheme of the chained
+// Consecutive wavefronts of the factorization (m <= 64, one system) in one
+// launch, each task waiting only for the tasks it reads: (k, j) for the
+// lower neighbours j (their pivot inverses) and, coupled, (k - 1, i) (the
+// stage round that left P_{k,i} and the cross blocks).  The scheme of the chained
 // sweeps (k_sweep_flow.hip): workgroups take the tasks items[off ..
 // off + n) (wavefront order) in the order they claim a ticket, so a task
 // only waits for tasks of workgroups already running, and the last claimant
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_tas
 // loads and stores; a task publishes after its stores have completed.  A
 // wait beyond its poll budget marks the system's state non-finite (never
 // a hang).
-template <bool SHJ>
+template <bool COUPLED, bool SHJ>
 __global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__restrict__ sysv,
                                                              const Item *__restrict__ items, int off, int n,
                                                              unsigned long long *fflag, unsigned *ticket,
@@ -447,11 +447,12 @@ __global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__re
     const int t = s_t;
     if (t >= n) return;   // (the counter was not at zero: no task to read)
     const Item it = items[off + t];
+    if (it.first < 0) return;   // padding task: no flag, nothing waits for it
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, i = it.first, k = it.aux;
     const GAS int *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx), *diag_pos = gp(d.diag_pos);
     const int p0 = row_ptr[i], nl = diag_pos[i] - p0;
-    for (int q = threadIdx.x; q < nl + (k > 0 ? 1 : 0); q += NTHREADS) {
+    for (int q = threadIdx.x; q < nl + ((COUPLED && k > 0) ? 1 : 0); q += NTHREADS) {
         const long long f = (q < nl) ? (long long)col_idx[p0 + q] * s + k : (long long)i * s + k - 1;
         int spins = 0;
         while (__hip_atomic_load(fflag + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -461,20 +462,23 @@ __global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__re
     }
     __syncthreads();
     if (s_late && threadIdx.x == 0) d.st->nonfinite = 1;
-    factor_task_body<true, SHJ, 0, true>(sysv, it, reinterpret_cast<double *>(smem_raw));
+    factor_task_body<COUPLED, SHJ, 0, true>(sysv, it, reinterpret_cast<double *>(smem_raw));
     __builtin_amdgcn_s_waitcnt(0);   // this thread's block stores have completed
     __syncthreads();
     if (threadIdx.x == 0)
         __hip_atomic_store(fflag + (long long)i * s + k, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-void launch_factor_flow(const SysDesc *dsys, const Item *items, int off, int n, bool sharedJ, size_t shmem,
-                        unsigned long long *fflag, unsigned *ticket, unsigned long long epoch, hipStream_t st)
+void launch_factor_flow(const SysDesc *dsys, const Item *items, int off, int n, bool coupled, bool sharedJ,
+                        size_t shmem, unsigned long long *fflag, unsigned *ticket, unsigned long long epoch,
+                        hipStream_t st)
 {
     if (n <= 0) return;
     dim3 grid(n), block(NTHREADS);
-    if (sharedJ) hipLaunchKernelGGL(k_factor_flow<true>, grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch);
-    else hipLaunchKernelGGL(k_factor_flow<false>, grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch);
+#define FF(C, SH) hipLaunchKernelGGL((k_factor_flow<C, SH>), grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch)
+    if (coupled) { if (sharedJ) FF(true, true); else FF(true, false); }
+    else { if (sharedJ) FF(false, true); else FF(false, false); }
+#undef FF
 }
 
 template <int CLS>
@@ -516,8 +520,9 @@ static void set_lds_limit_t(int b)
 void factor_set_lds_limit(size_t bytes)
 {
     set_lds_limit_t<0>((int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_flow<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    (void)hipFuncSetAttribute((const void *)k_factor_flow<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *ff[] = {(const void *)k_factor_flow<true, true>, (const void *)k_factor_flow<true, false>,
+                        (const void *)k_factor_flow<false, true>, (const void *)k_factor_flow<false, false>};
+    for (const void *f : ff) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     set_lds_limit_t<2>((int)bytes);
     set_lds_limit_t<3>((int)bytes);
 }

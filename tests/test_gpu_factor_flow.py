@@ -1,7 +1,8 @@
-"""The dependency-driven coupled factorization (m <= 64: runs of
-consecutive wavefronts in one launch, each task waiting only for the tasks
-it reads), synchronous and asynchronous, on the GPU, against the
-factorization with one launch per wavefront (IRK_FACTOR_FLOW=0 at set-up).
+"""The dependency-driven factorization (m <= 64: runs of consecutive
+wavefronts in one launch, each task waiting only for the tasks it reads),
+synchronous and asynchronous, all three preconditioner forms, on the GPU,
+against the factorization with one launch per wavefront (IRK_FACTOR_FLOW=0
+at set-up).
 
 * Bitwise the same factors (pivot inverses and stored cross blocks) as the
   wavefront-per-launch factorization: s = 2, 3, 4, m from 6 to 64 (both
@@ -11,7 +12,7 @@ factorization with one launch per wavefront (IRK_FACTOR_FLOW=0 at set-up).
   never reset) and a value update between them.
 * The solve after it: the same iterations and bitwise the same solution
   as after the synchronous factorization.
-* A singular pivot is still reported by the solve.
+* A singular pivot is still reported (asynchronous: by the solve).
 """
 import numpy as np
 import pytest
@@ -40,13 +41,14 @@ CASES = [(3, 2, 24, 64, 1), (2, 2, 16, 40, 1), (4, 2, 8, 16, 1), (3, 3, 5, 20, 1
          (3, 2, 32, 64, 1)]
 
 
+@pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted", "uncoupled"])
 @pytest.mark.parametrize("case", CASES, ids=_ids)
-def test_flow_factors_equal_wavefront_factors(case, monkeypatch):
+def test_flow_factors_equal_wavefront_factors(case, pc, monkeypatch):
     irk = _irk()
     s, dim, N, m, nJ = case
-    print("factor flow", case, flush=True)
+    print("factor flow", pc, case, flush=True)
     sy = _system(s, dim, N, m, nJ)
-    opts = irk.Options(pc="coupled")
+    opts = irk.Options(pc=pc)
     monkeypatch.setenv("IRK_FACTOR_FLOW", "0")
     ref = irk.Solver(sy, opts)
     ref.factor()
