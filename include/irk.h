@@ -169,8 +169,8 @@ irk_status irk_update_values(irk_handle *h, const double *J, const double *M, do
 
 /* Block ILU(0) factorization chosen by the options (Sec. 4.2.1 Alg. 2,
  * Sec. 4.3.1 Alg. 3 in its standard ILU(0) reading, Sec. 4.3.2).  Computed
- * in FP64 level by level (the stage-coupled form with m <= 64: every
- * wavefront in one launch, each task waiting only for the tasks whose
+ * in FP64 level by level (the uncoupled forms, and the stage-coupled form
+ * with m <= 64: every wavefront in one launch, each task waiting only for the tasks whose
  * blocks it reads, with the same arithmetic; variable IRK_FACTOR_FLOW=0 at
  * set-up keeps one launch per wavefront); then quantized when factor_prec
  * is not FP64.  Synchronizes; IRK_ERR_SINGULAR names the element in
@@ -179,8 +179,8 @@ irk_status irk_factor_ilu(irk_handle *h);
 
 /* The same factorization without waiting for it: returns once its launches
  * are enqueued, so the host prepares the next calls while it runs (the
- * stage-coupled form with m <= 64 in up to three dependency-driven
- * launches, cut at the points named below).  It
+ * uncoupled forms, and the stage-coupled form with m <= 64, in up to three
+ * dependency-driven launches, cut at the points named below).  It
  * starts at the current point of the handle's stream and runs on a second
  * stream of the handle (on the handle's stream itself while profiling is
  * on); the handle's stream goes on when the factorization reaches its first

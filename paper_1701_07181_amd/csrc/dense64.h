@@ -391,14 +391,21 @@ constexpr int DM_PIECES = DM_KP * DM_AP / 2;           // 16-byte pieces of eith
 constexpr int DM_Q = (DM_PIECES + DM_TEAM - 1) / DM_TEAM;
 constexpr int DM_LDS_DOUBLES = DM_KP * DM_AP + DM_AP * DM_BP;
 
+// coh_a: A read with coherent loads (see ld_coh)
 __device__ __forceinline__ void dm_load_panel(const GAS double *A, const GAS double *B, int m, int ld,
-                                              int k0, dbl2 (&ra)[DM_Q], dbl2 (&rb)[DM_Q])
+                                              int k0, dbl2 (&ra)[DM_Q], dbl2 (&rb)[DM_Q], bool coh_a = false)
 {
 #pragma unroll
     for (int q = 0; q < DM_Q; ++q) {
         const int e = min((int)threadIdx.x + q * DM_TEAM, DM_PIECES - 1);
         const int kk = e / 80, i = (e - kk * 80) * 2;     // A: column k0+kk, rows i, i+1
-        ra[q] = *reinterpret_cast<const GAS dbl2 *>(A + (size_t)min(k0 + kk, m - 1) * ld + min(i, ld - 2));
+        const GAS double *pa = A + (size_t)min(k0 + kk, m - 1) * ld + min(i, ld - 2);
+        if (coh_a) {
+            ra[q].x = ld_coh(pa);
+            ra[q].y = ld_coh(pa + 1);
+        } else {
+            ra[q] = *reinterpret_cast<const GAS dbl2 *>(pa);
+        }
         const int j = e >> 3, kb = (e & 7) * 2;           // B: column j, rows k0+kb, +1
         rb[q] = *reinterpret_cast<const GAS dbl2 *>(B + (size_t)min(j, m - 1) * ld + min(k0 + kb, ld - 2));
     }
@@ -421,7 +428,7 @@ __device__ __forceinline__ void dm_put_panel(double *Am, double *Bm, int m, int 
 }
 
 __device__ __forceinline__ void dm_gemm(int m, int ld, double alpha, const double *gA, const double *gB,
-                                        bool add, double *gC, double *lds)
+                                        bool add, double *gC, double *lds, bool coh_a = false)
 {
     const GAS double *A = gp(gA);
     const GAS double *B = gp(gB);
@@ -439,11 +446,11 @@ __device__ __forceinline__ void dm_gemm(int m, int ld, double alpha, const doubl
 #pragma unroll
         for (int y = 0; y < 3; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
     dbl2 ra[DM_Q], rb[DM_Q];
-    dm_load_panel(A, B, m, ld, 0, ra, rb);
+    dm_load_panel(A, B, m, ld, 0, ra, rb, coh_a);
     for (int k0 = 0; k0 < m; k0 += DM_KP) {
         __syncthreads();                                  // previous panel fully read
         dm_put_panel(Am, Bm, m, k0, ra, rb);
-        if (k0 + DM_KP < m) dm_load_panel(A, B, m, ld, k0 + DM_KP, ra, rb);
+        if (k0 + DM_KP < m) dm_load_panel(A, B, m, ld, k0 + DM_KP, ra, rb, coh_a);
         __syncthreads();
         const int nkc = (min(m - k0, DM_KP) + 3) >> 2;
 #pragma unroll
@@ -534,7 +541,7 @@ __device__ __forceinline__ void dm_publish(double v0, double v1, double v2, unsi
     }
 }
 
-template <int RG>
+template <int RG, bool COH = false>
 __device__ __forceinline__ int dm_invert_rg(double *gptr, int m, int ld, double *lds)
 {
     GAS double *G = gp(gptr);
@@ -634,7 +641,10 @@ __device__ __forceinline__ int dm_invert_rg(double *gptr, int m, int ld, double 
 #pragma unroll
         for (int j = 0; j < DMI_CW; ++j) {
             const int c = DMI_CW * w + j;
-            if (c < m) G[(size_t)row_of_step[c] * ld + st] = a[g][j] * sc;
+            if (c < m) {
+                if (COH) st_coh(G + (size_t)row_of_step[c] * ld + st, a[g][j] * sc);
+                else G[(size_t)row_of_step[c] * ld + st] = a[g][j] * sc;
+            }
         }
     }
     __syncthreads();

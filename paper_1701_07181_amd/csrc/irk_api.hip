@@ -391,8 +391,8 @@ struct irk_handle {
     // the forward sweep's first launch group)
     hipEvent_t ev_part = nullptr;
     int part_levels = 0;
-    // dependency-driven coupled factorization (k_factor_flow): its task
-    // flags and ticket counter
+    // dependency-driven factorization (k_factor_flow): its task flags and
+    // ticket counter
     bool factor_flow = false;
     unsigned long long *dfflag = nullptr;
     unsigned *dfticket = nullptr;
@@ -1390,11 +1390,11 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
     }
     // (non-blocking: no implicit ordering with a legacy default stream)
     if (hipStreamCreateWithFlags(&h->sstream, hipStreamNonBlocking) != hipSuccess) h->sstream = nullptr;
-    // the dependency-driven coupled factorization (variable
-    // IRK_FACTOR_FLOW=0 turns it off)
+    // the dependency-driven factorization: the uncoupled forms, and the
+    // coupled form with m <= 64 (variable IRK_FACTOR_FLOW=0 turns it off)
     {
         const char *e = std::getenv("IRK_FACTOR_FLOW");
-        h->factor_flow = m <= 64 && o->pc != IRK_PC_NONE && !(e && std::atoi(e) == 0);
+        h->factor_flow = (m <= 64 || !h->coupled) && o->pc != IRK_PC_NONE && !(e && std::atoi(e) == 0);
     }
     std::vector<Item> all(W.items);
     all.insert(all.end(), h->fitems.begin(), h->fitems.end());
@@ -1457,7 +1457,7 @@ irk_status irk_factor_ilu(irk_handle *h)
         // every wavefront in one dependency-driven launch (k_factor_flow)
         int n = 0;
         for (const Launch &F : h->fa) n += F.n;
-        launch_factor_flow(h->dsys, h->ditems, h->fa[0].off, n, h->coupled, h->sharedJ, h->shm_fac, h->dfflag, h->dfticket,
+        launch_factor_flow(h->dsys, h->ditems, h->fa[0].off, n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->dfflag, h->dfticket,
                            ++g_flow_epoch, h->stream);
     } else {
         for (const Launch &F : h->fa)
@@ -1533,7 +1533,7 @@ irk_status irk_factor_ilu_async(irk_handle *h)
             }
             int n = 0;
             for (int w = w0; w < w1; ++w) n += h->fa[w].n;
-            launch_factor_flow(h->dsys, h->ditems, h->fa[w0].off, n, h->coupled, h->sharedJ, h->shm_fac, h->dfflag,
+            launch_factor_flow(h->dsys, h->ditems, h->fa[w0].off, n, h->coupled, h->sharedJ, h->m, h->shm_fac, h->dfflag,
                                h->dfticket, ep, fs);
             if (w1 == wpart + 1 && w1 < nw) {
                 HIPCHK(hipEventRecord(h->ev_part, fs));

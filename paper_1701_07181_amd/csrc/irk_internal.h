@@ -262,11 +262,11 @@ void launch_export(const SysDesc *dsys, const SysDesc &hsys, double *pinv, doubl
                    hipStream_t st);
 void factor_set_lds_limit(size_t bytes);
 // Tasks items[off .. off + n) (consecutive wavefronts of one system's
-// factorization, m <= 64) in one launch, each waiting only for the tasks it
+// factorization: m <= 64, or any m uncoupled) in one launch, each waiting only for the tasks it
 // reads (flags fflag[T][s] = epoch; ticket counter at zero on entry and on
 // exit); k_factor.hip.
 void launch_factor_flow(const SysDesc *dsys, const Item *items, int off, int n, bool coupled, bool sharedJ,
-                        size_t shmem, unsigned long long *fflag, unsigned *ticket, unsigned long long epoch,
-                        hipStream_t st);
+                        int m, size_t shmem, unsigned long long *fflag, unsigned *ticket,
+                        unsigned long long epoch, hipStream_t st);
 
 }  // namespace irk

@@ -43,17 +43,17 @@ namespace irk {
 // product accumulates (acc) only with alpha = 1 or -1.
 template <int CLS>
 __device__ __forceinline__ void blk_gemm(int m, int ld, double alpha, const double *A, const double *B,
-                                         bool acc, double *C, double *lds)
+                                         bool acc, double *C, double *lds, bool coh_a = false)
 {
     if (CLS == 0) d64_gemm(m, ld, alpha, A, B, acc, C);
-    else dm_gemm(m, ld, alpha, A, B, acc, C, lds);
+    else dm_gemm(m, ld, alpha, A, B, acc, C, lds, coh_a);
 }
 
-template <int CLS>
+template <int CLS, bool COH = false>
 __device__ __forceinline__ int blk_inverse(double *g, int m, int ld, double *lds)
 {
     if (CLS == 0) return d64_invert(g, m, ld, lds);
-    return dm_invert_rg<(CLS == 0 ? 2 : CLS)>(g, m, ld, lds);
+    return dm_invert_rg<(CLS == 0 ? 2 : CLS), COH>(g, m, ld, lds);
 }
 
 template <int CLS> constexpr int team_of() { return CLS == 0 ? NTHREADS : DM_TEAM; }
@@ -353,7 +353,7 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
     const int ntot = nnb + nround;
     for (int t = 0; t <= ntot; ++t) {
         // every neighbour term is in: invert the pivot block in place
-        if (t == nnb && blk_inverse<CLS>(Pk, m, ld, lds)) flag_singular(d, i);
+        if (t == nnb && blk_inverse<CLS, FLOW>(Pk, m, ld, lds)) flag_singular(d, i);
         if (t == ntot) break;
         const double *A, *B;
         double *D;
@@ -385,7 +385,9 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
             else if (q == l) { A = L; B = cross_blk(d, i, k, l); D = P(l); al = -1.0; add = true; }
             else { A = L; B = cross_blk(d, i, k, q); D = cross_blk(d, i, l, q); al = -1.0; add = true; }
         }
-        blk_gemm<CLS>(m, ld, al, A, B, add, D, lds);
+        // (FLOW, uncoupled only: the lower neighbours' inverses come from
+        // other tasks of the launch)
+        blk_gemm<CLS>(m, ld, al, A, B, add, D, lds, FLOW && t < nnb && !(t & 1));
     }
     if (round && k == 0) {
         // later stages' pivots and the stored cross blocks from X = M P_0^{-1} M
@@ -416,8 +418,8 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_tas
     factor_task_body<COUPLED, SHJ, CLS>(sysv, items[blockIdx.x], reinterpret_cast<double *>(smem_raw));
 }
 
-// Consecutive wavefronts of the factorization (m <= 64, one system) in one
-// launch, each task waiting only for the tasks it reads: (k, j) for the
+// Consecutive wavefronts of the factorization (one system: the uncoupled
+// forms, and the coupled form with m <= 64) in one launch, each task waiting only for the tasks it reads: (k, j) for the
 // lower neighbours j (their pivot inverses) and, coupled, (k - 1, i) (the
 // stage round that left P_{k,i} and the cross blocks).  The scheme of the chained
 // sweeps (k_sweep_flow.hip): workgroups take the tasks items[off ..
@@ -429,8 +431,8 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_tas
 // loads and stores; a task publishes after its stores have completed.  A
 // wait beyond its poll budget marks the system's state non-finite (never
 // a hang).
-template <bool COUPLED, bool SHJ>
-__global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__restrict__ sysv,
+template <bool COUPLED, bool SHJ, int CLS>
+__global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_flow(const SysDesc *__restrict__ sysv,
                                                              const Item *__restrict__ items, int off, int n,
                                                              unsigned long long *fflag, unsigned *ticket,
                                                              unsigned long long epoch)
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__re
     const int s = d.s, i = it.first, k = it.aux;
     const GAS int *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx), *diag_pos = gp(d.diag_pos);
     const int p0 = row_ptr[i], nl = diag_pos[i] - p0;
-    for (int q = threadIdx.x; q < nl + ((COUPLED && k > 0) ? 1 : 0); q += NTHREADS) {
+    for (int q = threadIdx.x; q < nl + ((COUPLED && k > 0) ? 1 : 0); q += team_of<CLS>()) {
         const long long f = (q < nl) ? (long long)col_idx[p0 + q] * s + k : (long long)i * s + k - 1;
         int spins = 0;
         while (__hip_atomic_load(fflag + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -462,7 +464,7 @@ __global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__re
     }
     __syncthreads();
     if (s_late && threadIdx.x == 0) d.st->nonfinite = 1;
-    factor_task_body<COUPLED, SHJ, 0, true>(sysv, it, reinterpret_cast<double *>(smem_raw));
+    factor_task_body<COUPLED, SHJ, CLS, true>(sysv, it, reinterpret_cast<double *>(smem_raw));
     __builtin_amdgcn_s_waitcnt(0);   // this thread's block stores have completed
     __syncthreads();
     if (threadIdx.x == 0)
@@ -470,14 +472,22 @@ __global__ __launch_bounds__(NTHREADS, 4) void k_factor_flow(const SysDesc *__re
 }
 
 void launch_factor_flow(const SysDesc *dsys, const Item *items, int off, int n, bool coupled, bool sharedJ,
-                        size_t shmem, unsigned long long *fflag, unsigned *ticket, unsigned long long epoch,
-                        hipStream_t st)
+                        int m, size_t shmem, unsigned long long *fflag, unsigned *ticket,
+                        unsigned long long epoch, hipStream_t st)
 {
     if (n <= 0) return;
-    dim3 grid(n), block(NTHREADS);
-#define FF(C, SH) hipLaunchKernelGGL((k_factor_flow<C, SH>), grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch)
-    if (coupled) { if (sharedJ) FF(true, true); else FF(true, false); }
-    else { if (sharedJ) FF(false, true); else FF(false, false); }
+    const int cls = factor_class(m);
+    dim3 grid(n), block(cls == 0 ? NTHREADS : DM_TEAM);
+#define FF(C, SH, K) hipLaunchKernelGGL((k_factor_flow<C, SH, K>), grid, block, shmem, st, dsys, items, off, n, fflag, ticket, epoch)
+    // (m > 64: the uncoupled forms only)
+    if (cls == 0) {
+        if (coupled) { if (sharedJ) FF(true, true, 0); else FF(true, false, 0); }
+        else { if (sharedJ) FF(false, true, 0); else FF(false, false, 0); }
+    } else if (cls == 2) {
+        if (sharedJ) FF(false, true, 2); else FF(false, false, 2);
+    } else {
+        if (sharedJ) FF(false, true, 3); else FF(false, false, 3);
+    }
 #undef FF
 }
 
@@ -520,8 +530,10 @@ static void set_lds_limit_t(int b)
 void factor_set_lds_limit(size_t bytes)
 {
     set_lds_limit_t<0>((int)bytes);
-    const void *ff[] = {(const void *)k_factor_flow<true, true>, (const void *)k_factor_flow<true, false>,
-                        (const void *)k_factor_flow<false, true>, (const void *)k_factor_flow<false, false>};
+    const void *ff[] = {(const void *)k_factor_flow<true, true, 0>, (const void *)k_factor_flow<true, false, 0>,
+                        (const void *)k_factor_flow<false, true, 0>, (const void *)k_factor_flow<false, false, 0>,
+                        (const void *)k_factor_flow<false, true, 2>, (const void *)k_factor_flow<false, false, 2>,
+                        (const void *)k_factor_flow<false, true, 3>, (const void *)k_factor_flow<false, false, 3>};
     for (const void *f : ff) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     set_lds_limit_t<2>((int)bytes);
     set_lds_limit_t<3>((int)bytes);

@@ -1,12 +1,14 @@
-"""The dependency-driven factorization (m <= 64: runs of consecutive
-wavefronts in one launch, each task waiting only for the tasks it reads),
-synchronous and asynchronous, all three preconditioner forms, on the GPU,
-against the factorization with one launch per wavefront (IRK_FACTOR_FLOW=0
-at set-up).
+"""The dependency-driven factorization (the uncoupled forms, and the coupled
+form with m <= 64: runs of consecutive wavefronts in one launch, each task
+waiting only for the tasks it reads), synchronous and asynchronous, all
+three preconditioner forms, on the GPU, against the factorization with one
+launch per wavefront (IRK_FACTOR_FLOW=0 at set-up).
 
 * Bitwise the same factors (pivot inverses and stored cross blocks) as the
   wavefront-per-launch factorization: s = 2, 3, 4, m from 6 to 64 (both
-  forms of the block routines: all tiles for m > 56, masked tiles below),
+  forms of the four-wave block routines: all tiles for m > 56, masked
+  tiles below) and m = 100, 135 (the eight-wave routines, two and three
+  row groups; the coupled form keeps one launch per wavefront there),
   2D and 3D meshes, shared and per-stage Jacobians.
 * Repeated factorizations on one handle (the epochs grow, the flags are
   never reset) and a value update between them.
@@ -38,7 +40,7 @@ def _ids(c):
 
 
 CASES = [(3, 2, 24, 64, 1), (2, 2, 16, 40, 1), (4, 2, 8, 16, 1), (3, 3, 5, 20, 1), (3, 2, 12, 6, 3),
-         (3, 2, 32, 64, 1)]
+         (3, 2, 32, 64, 1), (3, 2, 8, 100, 1), (2, 2, 6, 135, 2)]
 
 
 @pytest.mark.parametrize("pc", ["coupled", "uncoupled_shifted", "uncoupled"])
