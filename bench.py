@@ -638,7 +638,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); "
               "multi-GPU sharding is a design note, not implemented", file=sys.stderr)
         sys.exit(2)
 
