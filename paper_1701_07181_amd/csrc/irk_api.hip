@@ -1369,19 +1369,19 @@ irk_status irk_setup(const irk_problem *p, const irk_options *o, void *workspace
         return IRK_ERR_DEVICE;
     }
     std::memset(h->hst, 0, sizeof(DevState));
-    hipEventCreate(&h->ev0);
-    hipEventCreate(&h->ev1);
-    hipEventCreateWithFlags(&h->ev_ready, hipEventDisableTiming);
-    hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming);
-    hipEventCreate(&h->ev_s0);
-    hipEventCreate(&h->ev_s1);
-    hipEventCreate(&h->ev_f0);
-    hipEventCreate(&h->ev_f1);
-    hipEventCreateWithFlags(&h->ev_pre, hipEventDisableTiming);
-    hipEventCreateWithFlags(&h->ev_factored, hipEventDisableTiming);
-    hipEventCreateWithFlags(&h->ev_tail, hipEventDisableTiming);
-    hipEventCreateWithFlags(&h->ev_read, hipEventDisableTiming);
-    hipEventCreateWithFlags(&h->ev_part, hipEventDisableTiming);
+    {
+        // (irk_destroy releases whatever was created before a failure)
+        hipEvent_t *timed[] = {&h->ev0, &h->ev1, &h->ev_s0, &h->ev_s1, &h->ev_f0, &h->ev_f1};
+        hipEvent_t *plain[] = {&h->ev_ready, &h->ev_done, &h->ev_pre, &h->ev_factored,
+                               &h->ev_tail, &h->ev_read, &h->ev_part};
+        bool ok = true;
+        for (hipEvent_t *e : timed) ok = ok && hipEventCreate(e) == hipSuccess;
+        for (hipEvent_t *e : plain) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            irk_destroy(h);
+            return IRK_ERR_DEVICE;
+        }
+    }
     {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
@@ -2629,9 +2629,10 @@ float time_us(irk_handle *h, F f, int reps)
     hipEventRecord(h->ev0, h->stream);
     for (int r = 0; r < reps; ++r) f();
     hipEventRecord(h->ev1, h->stream);
-    hipEventSynchronize(h->ev1);
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, h->ev0, h->ev1);
+    // (a failed candidate never wins)
+    if (hipEventSynchronize(h->ev1) != hipSuccess || hipEventElapsedTime(&ms, h->ev0, h->ev1) != hipSuccess)
+        return 1e30f;
     return ms * 1e3f / reps;
 }
 
