@@ -306,8 +306,13 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
 // task are one operation list (the neighbour products for m > 64, then the
 // stage round), so a kernel holds one inlined copy of the product and one of
 // the inverse.
+// (FLOW, m > 64: fflag / epoch of the launch; each lower neighbour's flag is
+// awaited right before its first product, so the task's own set-up and its
+// earlier neighbours' products overlap the later neighbours' tasks)
 template <bool COUPLED, bool SHJ, int CLS, bool FLOW = false>
-__device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sysv, const Item it, double *lds)
+__device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sysv, const Item it, double *lds,
+                                                 unsigned long long *fflag = nullptr,
+                                                 unsigned long long epoch = 0)
 {
     constexpr int TEAM = team_of<CLS>();
     if (it.first < 0) return;                     // padding task (whole workgroup)
@@ -364,6 +369,18 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
             const int p = p0 + (t >> 1);
             const bool second = t & 1;
             const long long j = col_idx[p];
+            if (FLOW && !second) {
+                // task (k, j) has published its pivot inverse (a wait beyond
+                // the poll budget marks the state non-finite)
+                if (threadIdx.x == 0) {
+                    int spins = 0;
+                    while (__hip_atomic_load(fflag + j * s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > FACTOR_SPIN_MAX) { d.st->nonfinite = 1; break; }
+                    }
+                }
+                __syncthreads();
+            }
             A = second ? Jk + (long long)p * bs : d.P64 + (j * s + k) * bs;
             B = second ? X : Jk + (long long)tpos[p] * bs;
             D = second ? Pk : X;
@@ -454,7 +471,8 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_flo
     const int s = d.s, i = it.first, k = it.aux;
     const GAS int *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx), *diag_pos = gp(d.diag_pos);
     const int p0 = row_ptr[i], nl = diag_pos[i] - p0;
-    for (int q = threadIdx.x; q < nl + ((COUPLED && k > 0) ? 1 : 0); q += team_of<CLS>()) {
+    // (m > 64: the waits are in the task body, one per lower neighbour)
+    for (int q = threadIdx.x; CLS == 0 && q < nl + ((COUPLED && k > 0) ? 1 : 0); q += team_of<CLS>()) {
         const long long f = (q < nl) ? (long long)col_idx[p0 + q] * s + k : (long long)i * s + k - 1;
         int spins = 0;
         while (__hip_atomic_load(fflag + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -464,7 +482,7 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_flo
     }
     __syncthreads();
     if (s_late && threadIdx.x == 0) d.st->nonfinite = 1;
-    factor_task_body<COUPLED, SHJ, CLS, true>(sysv, it, reinterpret_cast<double *>(smem_raw));
+    factor_task_body<COUPLED, SHJ, CLS, true>(sysv, it, reinterpret_cast<double *>(smem_raw), fflag, epoch);
     __builtin_amdgcn_s_waitcnt(0);   // this thread's block stores have completed
     __syncthreads();
     if (threadIdx.x == 0)
