@@ -64,6 +64,22 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
     if (threadIdx.x == 0) atomicCAS(&d.st->singular, 0, elem + 1);
 }
 
+// Dependency-driven factorization: the workgroup waits until flag f holds
+// the launch's epoch (the task it names has published its blocks); a wait
+// beyond the poll budget marks the system's state non-finite (never a hang).
+__device__ __forceinline__ void flow_wait(const SysDesc &d, unsigned long long *fflag, long long f,
+                                          unsigned long long epoch)
+{
+    if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(fflag + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > FACTOR_SPIN_MAX) { d.st->nonfinite = 1; break; }
+        }
+    }
+    __syncthreads();
+}
+
 // Neighbour terms for m <= 64 with the products fused: the accumulators of
 // P_{k,i} stay in registers from their starting value (d_k M_i - dt J_ii, or
 // the stored P_{k,i} when from_p) through every lower neighbour j, and
@@ -72,7 +88,8 @@ __device__ __forceinline__ void flag_singular(const SysDesc &d, int elem) {
 // (lds + D64_STAGE, leading dimension D64_LDX).
 template <bool FULL, bool FLOW = false>
 __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, int k, const double *Jk,
-                                                      double *Pk, bool from_p, double *Xs)
+                                                      double *Pk, bool from_p, double *Xs,
+                                                      unsigned long long *fflag, unsigned long long epoch)
 {
     const int s = d.s, lane = threadIdx.x & 63, w = wave_id();
     int m = d.m, ld = d.ld;
@@ -100,6 +117,7 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
     for (int p = p0; p < pd; ++p) {
         asm volatile("" : "+s"(m), "+s"(ld));   // per-lane offsets recomputed inside the loop
         const long long j = col_idx[p];
+        if (FLOW) flow_wait(d, fflag, j * s + k, epoch);   // P_{k,j}^{-1} is published
         dbl4 ax[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -306,9 +324,9 @@ __device__ __forceinline__ void factor_round_small(const SysDesc &d, int i, int 
 // task are one operation list (the neighbour products for m > 64, then the
 // stage round), so a kernel holds one inlined copy of the product and one of
 // the inverse.
-// (FLOW, m > 64: fflag / epoch of the launch; each lower neighbour's flag is
-// awaited right before its first product, so the task's own set-up and its
-// earlier neighbours' products overlap the later neighbours' tasks)
+// (FLOW: fflag / epoch of the launch; each lower neighbour's flag is awaited
+// right before its first product, so the task's own set-up and its earlier
+// neighbours' products overlap the later neighbours' tasks)
 template <bool COUPLED, bool SHJ, int CLS, bool FLOW = false>
 __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sysv, const Item it, double *lds,
                                                  unsigned long long *fflag = nullptr,
@@ -333,8 +351,8 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
     const int p0 = row_ptr[i], pd = diag_pos[i];
     const int nnb = (CLS == 0) ? 0 : 2 * (pd - p0);   // neighbour products (m > 64)
     if (CLS == 0) {
-        if (m > 56) factor_small_products<true, FLOW>(d, i, k, Jk, Pk, from_p, lds);
-        else factor_small_products<false, FLOW>(d, i, k, Jk, Pk, from_p, lds);
+        if (m > 56) factor_small_products<true, FLOW>(d, i, k, Jk, Pk, from_p, lds, fflag, epoch);
+        else factor_small_products<false, FLOW>(d, i, k, Jk, Pk, from_p, lds, fflag, epoch);
         if (d64_invert<true, FLOW>(Pk, m, ld, lds)) flag_singular(d, i);
         if (COUPLED && k + 1 < s) {
             if (m > 56) factor_round_small<true, SHJ, FLOW>(d, i, k, lds);
@@ -369,18 +387,7 @@ __device__ __forceinline__ void factor_task_body(const SysDesc *__restrict__ sys
             const int p = p0 + (t >> 1);
             const bool second = t & 1;
             const long long j = col_idx[p];
-            if (FLOW && !second) {
-                // task (k, j) has published its pivot inverse (a wait beyond
-                // the poll budget marks the state non-finite)
-                if (threadIdx.x == 0) {
-                    int spins = 0;
-                    while (__hip_atomic_load(fflag + j * s + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                        __builtin_amdgcn_s_sleep(2);
-                        if (++spins > FACTOR_SPIN_MAX) { d.st->nonfinite = 1; break; }
-                    }
-                }
-                __syncthreads();
-            }
+            if (FLOW && !second) flow_wait(d, fflag, j * s + k, epoch);   // P_{k,j}^{-1} is published
             A = second ? Jk + (long long)p * bs : d.P64 + (j * s + k) * bs;
             B = second ? X : Jk + (long long)tpos[p] * bs;
             D = second ? Pk : X;
@@ -455,12 +462,11 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_flo
                                                              unsigned long long epoch)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ int s_t, s_late;
+    __shared__ int s_t;
     if (threadIdx.x == 0) {
         const unsigned t = atomicAdd(ticket, 1u);
         if (t == (unsigned)n - 1u) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_t = (int)t;
-        s_late = 0;
     }
     __syncthreads();
     const int t = s_t;
@@ -469,19 +475,9 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_flo
     if (it.first < 0) return;   // padding task: no flag, nothing waits for it
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, i = it.first, k = it.aux;
-    const GAS int *row_ptr = gp(d.row_ptr), *col_idx = gp(d.col_idx), *diag_pos = gp(d.diag_pos);
-    const int p0 = row_ptr[i], nl = diag_pos[i] - p0;
-    // (m > 64: the waits are in the task body, one per lower neighbour)
-    for (int q = threadIdx.x; CLS == 0 && q < nl + ((COUPLED && k > 0) ? 1 : 0); q += team_of<CLS>()) {
-        const long long f = (q < nl) ? (long long)col_idx[p0 + q] * s + k : (long long)i * s + k - 1;
-        int spins = 0;
-        while (__hip_atomic_load(fflag + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > FACTOR_SPIN_MAX) { s_late = 1; break; }
-        }
-    }
-    __syncthreads();
-    if (s_late && threadIdx.x == 0) d.st->nonfinite = 1;
+    // the earlier stage round that left P_{k,i} (the lower neighbours are
+    // awaited in the task body, each right before its first product)
+    if (COUPLED && k > 0) flow_wait(d, fflag, (long long)i * s + k - 1, epoch);
     factor_task_body<COUPLED, SHJ, CLS, true>(sysv, it, reinterpret_cast<double *>(smem_raw), fflag, epoch);
     __builtin_amdgcn_s_waitcnt(0);   // this thread's block stores have completed
     __syncthreads();
