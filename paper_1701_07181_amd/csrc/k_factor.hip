@@ -81,8 +81,9 @@ __device__ __forceinline__ void flow_wait(const SysDesc &d, unsigned long long *
 }
 
 // Neighbour terms for m <= 64 with the products fused: the accumulators of
-// P_{k,i} stay in registers from their starting value (d_k M_i - dt J_ii, or
-// the stored P_{k,i} when from_p) through every lower neighbour j, and
+// P_{k,i} stay in registers from their starting value (d_k M_i - dt J_ii;
+// zero when from_p, the stored P_{k,i} being added after the last
+// neighbour) through every lower neighbour j, and
 // X = -dt^2 P_j^{-1} J_ji passes through LDS (64 x 66 doubles) into
 // P_{k,i} += J_ij X; P_{k,i} is left in LDS where the inverse reads it
 // (lds + D64_STAGE, leading dimension D64_LDX).
@@ -111,7 +112,7 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
             for (int q = 0; q < 4; ++q) {
                 const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
                 const size_t e = (size_t)min(c, m - 1) * ld + min(r, m - 1);
-                acc[x][y][q] = from_p ? (FLOW ? ld_coh(Ps + e) : Ps[e]) : dk * Mi[e] - dt * Jd[e];
+                acc[x][y][q] = from_p ? 0.0 : dk * Mi[e] - dt * Jd[e];
             }
     const int p0 = row_ptr[i], pd = diag_pos[i];
     for (int p = p0; p < pd; ++p) {
@@ -140,6 +141,21 @@ __device__ __forceinline__ void factor_small_products(const SysDesc &d, int i, i
         }
         __syncthreads();
         if (act) d64_accum<FULL, true, 2>(acc, m, ld, gp(Jk + (long long)p * bs), nullptr, Xs, nx, ny);
+    }
+    if (from_p) {
+        // the stored P_{k,i} last, so the neighbour terms need not wait for
+        // the earlier stage round that leaves it
+        if (FLOW) flow_wait(d, fflag, (long long)i * s + k - 1, epoch);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = d64_tile_row(lane, w, x, q), c = d64_tile_col(lane, w, y);
+                    const size_t e = (size_t)min(c, m - 1) * ld + min(r, m - 1);
+                    acc[x][y][q] += FLOW ? ld_coh(Ps + e) : Ps[e];
+                }
     }
     __syncthreads();                              // every wave is done with X in LDS
     if (act) {
@@ -475,9 +491,9 @@ __global__ __launch_bounds__(team_of<CLS>(), CLS == 0 ? 4 : 1) void k_factor_flo
     if (it.first < 0) return;   // padding task: no flag, nothing waits for it
     const SysDesc &d = sysv[it.sys];
     const int s = d.s, i = it.first, k = it.aux;
-    // the earlier stage round that left P_{k,i} (the lower neighbours are
-    // awaited in the task body, each right before its first product)
-    if (COUPLED && k > 0) flow_wait(d, fflag, (long long)i * s + k - 1, epoch);
+    // (every wait is in the task body: each lower neighbour right before its
+    // first product, coupled k > 0 the earlier stage round right before
+    // P_{k,i} is read)
     factor_task_body<COUPLED, SHJ, CLS, true>(sysv, it, reinterpret_cast<double *>(smem_raw), fflag, epoch);
     __builtin_amdgcn_s_waitcnt(0);   // this thread's block stores have completed
     __syncthreads();
